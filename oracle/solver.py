@@ -1,0 +1,405 @@
+"""DBFFT linear systems, preconditioned CG and Newton (oracle; test
+infrastructure only).
+
+Unknown: {a | e}, a the normalized Fourier coefficients of the displacement
+fluctuation on the half spectrum (3 components), e the macroscopic strain
+(small strains) or displacement-gradient (finite strains) components on the
+stress-controlled set S, in an orthonormal basis.
+
+Operator (sign-flipped so that it is positive semi-definite; the printed
+operator d:F(C:F^-1(s.u)) is its negative, Sec. 2.2 eq. lineqf):
+    eps(x)   = E + sum_a e_a B_a + sum_k (s(k).a(k)) exp(i xi.x)
+    sigma(x) = C(x) : eps(x)
+    s(k)     = F[sigma](k) / N
+    (K{a|e})_a(k) = -i xi_j s_ij(k)  (k outside the null set, else 0)
+    (K{a|e})_e    = B_a : s(0) = B_a : <sigma>,   a in S
+This is the Hessian of the average energy 1/2 <eps:C:eps> - sbar_S . e, so it
+is symmetric for the real inner product on the half spectrum plus the
+Euclidean product on e (Sec. 2.2 and Sec. 2.3: full rank and Hermitian once
+the zero frequency and the duplicated real-transform terms are removed).
+
+Right-hand side (Sec. 2.2 eq. lineqf, Sec. 2.3 final system):
+    b_a = i xi_j F[C:E_U]_ij / N,   b_e = sbar_S - B_a : <C:E_U>.
+
+Preconditioner (Sec. 2.5 eqs. pred2/pred3): M(xi) = [xi.Cbar.xi]^-1 with
+(xi.Cbar.xi)_ik = xi_j Cbar_ijkl xi_l, Cbar the voxel average of the
+stiffness (or tangent); at xi = 0 the macro block uses [B_a:Cbar:B_b]^-1.
+
+Residuals (Sec. 3, eqs. chedckeq and chedckimp): the equilibrium residual
+||div sigma||_L2 / ||<sigma>|| with the L2 norm taken as the RMS over the
+unit cell equals the full-spectrum norm of the a-part of the CG residual
+divided by ||<sigma>||_F; the loading residual is ||r_e|| / ||<sigma>||_F.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import spectral as sp
+from .materials import isotropic_tensor, mandel_to_tensor4, sym_to_mandel, mandel_to_sym
+
+SMALL = "small"
+FINITE = "finite"
+
+
+class IsoTangent:
+    """Per-voxel isotropic stiffness, sigma = lam tr(eps) I + 2 mu eps."""
+
+    def __init__(self, lam, mu):
+        self.lam = np.asarray(lam, dtype=np.float64)
+        self.mu = np.asarray(mu, dtype=np.float64)
+
+    def stress(self, eps):
+        tr = eps[0, 0] + eps[1, 1] + eps[2, 2]
+        out = 2.0 * self.mu * eps
+        for i in range(3):
+            out[i, i] = out[i, i] + self.lam * tr
+        return out
+
+    def mean(self):
+        return isotropic_tensor(float(np.mean(self.lam)), float(np.mean(self.mu)))
+
+
+class GeneralTangent:
+    """Per-voxel fourth-order tensor C[x, y, z, i, j, k, l]; sigma_ij = C_ijkl eps_kl.
+    Also serves the finite-strain tangent K_iJkL acting on H_kL."""
+
+    def __init__(self, C):
+        self.C = np.asarray(C, dtype=np.float64)
+
+    def stress(self, eps):
+        return np.einsum("xyzijkl,klxyz->ijxyz", self.C, eps)
+
+    def mean(self):
+        return self.C.mean(axis=(0, 1, 2))
+
+
+class Space:
+    """Discrete setting of one RVE: grid, frequencies, null set, weights and
+    the macroscopic basis restricted to the stress-controlled set S."""
+
+    def __init__(self, shape, kin=SMALL, stress_mask=None):
+        self.shape = tuple(int(v) for v in shape)
+        self.N = float(np.prod(self.shape))
+        self.kin = kin
+        self.xi = sp.xi_half(self.shape)
+        self.Z = sp.null_set(self.shape)
+        self.w = sp.half_weights(self.shape)
+        if stress_mask is None:
+            stress_mask = np.zeros((3, 3), dtype=bool)
+        self.mask = np.asarray(stress_mask, dtype=bool)
+        if kin == SMALL:
+            if not np.array_equal(self.mask, self.mask.T):
+                raise ValueError("small strains need a symmetric stress mask")
+            basis, pairs = sp.mandel_basis(), sp.MANDEL_PAIRS
+        else:
+            basis, pairs = sp.full_basis(), tuple((a // 3, a % 3) for a in range(9))
+        self.basis = basis
+        self.S = [a for a, (i, j) in enumerate(pairs) if self.mask[i, j]]
+        self.BS = basis[self.S] if self.S else np.zeros((0, 3, 3))
+        self.grad = sp.sym_grad if kin == SMALL else sp.full_grad
+
+    # vectors are pairs (a, e)
+    def zeros(self):
+        return (np.zeros((3,) + sp.half_shape(self.shape), dtype=complex), np.zeros(len(self.S)))
+
+    def dot(self, u, v):
+        return sp.inner(u[0], v[0], self.w) + float(np.dot(u[1], v[1]))
+
+    def macro_tensor(self, e):
+        return np.einsum("a,aij->ij", e, self.BS)
+
+    def macro_row(self, t):
+        return np.einsum("aij,ij->a", self.BS, t)
+
+    def field_of(self, a, e, E):
+        """Real strain (or displacement-gradient) field E + e + grad(u)."""
+        g = sp.real_field(self.grad(a, self.xi), self.shape)
+        return g + (E + self.macro_tensor(e))[:, :, None, None, None]
+
+    def divergence_residual(self, sig):
+        """(i xi_j F[sigma]_ij / N, <sigma>) with the null set cleared."""
+        s = sp.fourier(sig, self.shape)
+        r = sp.div(s, self.xi)
+        r[:, self.Z] = 0.0
+        return r, s[:, :, 0, 0, 0].real.copy()
+
+    def apply(self, x, tangent, E=None):
+        """K{a|e} for a linear tangent; also returns <sigma> of the field."""
+        if E is None:
+            E = np.zeros((3, 3))
+        eps = self.field_of(x[0], x[1], E)
+        r, dc = self.divergence_residual(tangent.stress(eps))
+        return (-r, self.macro_row(dc)), dc
+
+    def preconditioner(self, Cbar):
+        """Returns z = M r for M of eqs. pred2/pred3."""
+        A = np.einsum("j...,ijkl,l...->...ik", self.xi, Cbar, self.xi)
+        nz = ~self.Z
+        Minv = np.zeros(A.shape)
+        Minv[nz] = np.linalg.inv(A[nz])
+        if self.S:
+            Ce = np.einsum("aij,ijkl,bkl->ab", self.BS, Cbar, self.BS)
+            Me = np.linalg.inv(Ce)
+        else:
+            Me = np.zeros((0, 0))
+
+        def apply_m(r):
+            za = np.einsum("...ik,k...->i...", Minv, r[0])
+            return (za, Me @ r[1])
+        return apply_m
+
+
+@dataclass
+class PCGInfo:
+    iterations: int = 0
+    converged: bool = False
+    breakdown: bool = False
+    eq_res: float = np.inf
+    load_res: float = np.inf
+    history: list = field(default_factory=list)
+
+
+def residual_norms(space, r, sig):
+    nrm = float(np.linalg.norm(sig))
+    ra = np.sqrt(max(sp.inner(r[0], r[0], space.w), 0.0))
+    re = float(np.linalg.norm(r[1]))
+    if nrm == 0.0:
+        return (0.0 if ra == 0.0 else np.inf), (0.0 if re == 0.0 else np.inf)
+    return ra / nrm, re / nrm
+
+
+def pcg(space, tangent, precond, b, sig0, tol=1e-8, tol_load=1e-10, max_iter=10000,
+        x0=None, keep_history=False):
+    """Preconditioned conjugate gradient on K{a|e} = b (Sec. 3 intro: CG for
+    complex numbers with the preconditioner of eqs. pred2/pred3).
+
+    sig0 is <sigma> of the field that produced b; the average stress of the
+    current iterate is tracked as sig0 + <sigma>(K x).  Stops when the
+    equilibrium residual is below tol and the loading residual below
+    tol_load (checked before the first iteration too)."""
+    info = PCGInfo()
+    if x0 is None:
+        x = space.zeros()
+        r = (b[0].copy(), b[1].copy())
+        sig = np.array(sig0, dtype=np.float64)
+    else:
+        x = (x0[0].copy(), x0[1].copy())
+        Kx, dcx = space.apply(x, tangent)
+        r = (b[0] - Kx[0], b[1] - Kx[1])
+        sig = np.array(sig0, dtype=np.float64) + dcx
+    z = precond(r)
+    p = (z[0].copy(), z[1].copy())
+    rz = space.dot(r, z)
+    while True:
+        eq, ld = residual_norms(space, r, sig)
+        info.eq_res, info.load_res = eq, ld
+        if keep_history:
+            info.history.append(eq)
+        if eq < tol and ld < tol_load:
+            info.converged = True
+            break
+        if info.iterations >= max_iter:
+            break
+        q, dcp = space.apply(p, tangent)
+        pq = space.dot(p, q)
+        if not pq > 0.0:
+            info.breakdown = True
+            break
+        alpha = rz / pq
+        x = (x[0] + alpha * p[0], x[1] + alpha * p[1])
+        r = (r[0] - alpha * q[0], r[1] - alpha * q[1])
+        sig = sig + alpha * dcp
+        z = precond(r)
+        rz_new = space.dot(r, z)
+        beta = rz_new / rz
+        rz = rz_new
+        p = (z[0] + beta * p[0], z[1] + beta * p[1])
+        info.iterations += 1
+    return x, sig, info
+
+
+def split_load(space, load):
+    """Prescribed strain part (zero on S) and the prescribed stress row."""
+    load = np.asarray(load, dtype=np.float64)
+    m = space.mask.astype(np.float64)
+    return load * (1.0 - m), space.macro_row(load * m)
+
+
+@dataclass
+class LinearResult:
+    a: np.ndarray
+    e: np.ndarray
+    sigma_bar: np.ndarray
+    eps_bar: np.ndarray
+    info: PCGInfo
+    space: Space
+    E_U: np.ndarray
+
+    def strain_field(self):
+        return self.space.field_of(self.a, self.e, self.E_U)
+
+
+def solve_linear(shape, tangent, load, stress_mask=None, tol=1e-8, tol_load=1e-10,
+                 max_iter=10000, x0=None, keep_history=False):
+    """Small-strain linear elastic DBFFT solve (Sec. 2.2 strain control,
+    Sec. 2.3 stress/mixed control).  `load` holds the prescribed strain on
+    strain-controlled components and the prescribed stress on the components
+    where stress_mask is true."""
+    space = Space(shape, SMALL, stress_mask)
+    E_U, sbar = split_load(space, load)
+    (ka, _), dc0 = space.apply(space.zeros(), tangent, E_U)
+    b = (-ka, sbar - space.macro_row(dc0))
+    M = space.preconditioner(tangent.mean())
+    x, sig, info = pcg(space, tangent, M, b, dc0, tol, tol_load, max_iter, x0, keep_history)
+    eps_bar = E_U + space.macro_tensor(x[1])
+    return LinearResult(x[0], x[1], sig, eps_bar, info, space, E_U)
+
+
+def true_residual(space, tangent, res: LinearResult, load):
+    """Equilibrium and loading residuals recomputed from the solution field."""
+    eps = res.strain_field()
+    r, dc = space.divergence_residual(tangent.stress(eps))
+    _, sbar = split_load(space, load)
+    return residual_norms(space, (r, sbar - space.macro_row(dc)), dc)
+
+
+# ---------------------------------------------------------------------------
+# Newton scheme (Sec. 2.4, eqs. lineariz, eqfinite, nonlineqf and
+# nonlineqfstress).  Each Newton iteration linearizes the stress around the
+# current field, solves the linear DBFFT system for {da | de} with the
+# consistent tangent by PCG, and updates.  Stopping: the largest change of
+# any component of the strain (small) or deformation gradient (finite) at
+# any voxel during the last update is below newton_tol (Sec. 2.4).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class NewtonInfo:
+    increments: int = 0
+    newton_iters: list = field(default_factory=list)
+    pcg_iters: list = field(default_factory=list)
+    eq_res: list = field(default_factory=list)
+    converged: bool = True
+    sigma_bar: list = field(default_factory=list)
+    eps_bar: list = field(default_factory=list)
+
+
+def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
+           newton_tol=1e-6, max_newton=25, max_iter=10000, refresh="increment",
+           state=None):
+    """Incremental Newton-DBFFT driver.
+
+    law.update(field, state) -> (stress, tangent_obj, new_state) where field
+    is the real strain (small) or displacement gradient H = F - I (finite)
+    with layout (3, 3, n1, n2, n3).  loads: list of 3x3 prescribed values per
+    increment (strain / F - I on strain-controlled components, stress on S).
+    refresh: 'increment' recomputes the preconditioner's mean tangent at the
+    first Newton iteration of every increment (Sec. 2.5), 'initial' only once.
+    Returns (a, e, state, info)."""
+    space = Space(shape, kin, stress_mask)
+    a, e = space.zeros()
+    info = NewtonInfo()
+    Cbar = None
+    for k, L in enumerate(loads):
+        E_U, sbar = split_load(space, L)
+        fld = space.field_of(a, e, E_U)
+        its, pits = 0, 0
+        conv = False
+        for i in range(max_newton + 1):
+            sig, tan, new_state = law.update(fld, state)
+            if Cbar is None or (i == 0 and refresh == "increment"):
+                Cbar = tan.mean()
+            r_a, dc = space.divergence_residual(sig)
+            r = (r_a, sbar - space.macro_row(dc))
+            if i > 0 and dmax < newton_tol:
+                conv = True
+                break
+            if i == max_newton:
+                break
+            M = space.preconditioner(Cbar)
+            d, _, pinfo = pcg(space, tan, M, r, dc, tol, tol_load, max_iter)
+            pits += pinfo.iterations
+            a = a + d[0]
+            e = e + d[1]
+            new_fld = space.field_of(a, e, E_U)
+            dmax = float(np.max(np.abs(new_fld - fld)))
+            fld = new_fld
+            its += 1
+        eq, _ = residual_norms(space, r, dc)
+        state = new_state
+        info.increments += 1
+        info.newton_iters.append(its)
+        info.pcg_iters.append(pits)
+        info.eq_res.append(eq)
+        info.converged = info.converged and conv
+        info.sigma_bar.append(dc.copy())
+        avg = E_U + space.macro_tensor(e)
+        info.eps_bar.append(avg)
+    return a, e, state, info
+
+
+class J2Law:
+    """Small-strain law object for newton(): rate-dependent J2 with per-voxel
+    Mandel elastic stiffness C (n1, n2, n3, 6, 6)."""
+
+    def __init__(self, C_mandel, s0, m, edot0, dt):
+        self.C = np.asarray(C_mandel, dtype=np.float64)
+        self.s0, self.m, self.edot0, self.dt = s0, m, edot0, dt
+        self.shape = self.C.shape[:3]
+
+    def initial_state(self):
+        return np.zeros(self.shape + (6,))
+
+    def update(self, eps, state):
+        from .materials import j2vp_return_map
+        if state is None:
+            state = self.initial_state()
+        nv = int(np.prod(self.shape))
+        ev = np.moveaxis(sym_to_mandel(eps), 0, -1).reshape(nv, 6)
+        sig, dp, ep, tan = j2vp_return_map(ev, state.reshape(nv, 6), self.C.reshape(nv, 6, 6),
+                                           self.s0, self.m, self.edot0, self.dt)
+        sig_t = mandel_to_sym(np.moveaxis(sig.reshape(self.shape + (6,)), -1, 0))
+        Ct = mandel_to_tensor4(tan.reshape(self.shape + (6, 6)))
+        return sig_t, GeneralTangent(Ct), ep.reshape(self.shape + (6,))
+
+
+class NeoHookeLaw:
+    """Finite-strain law object for newton(): field is H = F - I."""
+
+    def __init__(self, mu, lam):
+        self.mu = np.asarray(mu, dtype=np.float64)
+        self.lam = np.asarray(lam, dtype=np.float64)
+
+    def update(self, H, state):
+        from .materials import neohooke_stress, neohooke_tangent
+        F = np.moveaxis(H, (0, 1), (-2, -1)) + np.eye(3)
+        P = neohooke_stress(F, self.mu, self.lam)
+        K = neohooke_tangent(F, self.mu, self.lam)
+        return np.moveaxis(P, (-2, -1), (0, 1)), GeneralTangent(K), state
+
+
+# ---------------------------------------------------------------------------
+# Adjoint gradient of a homogenized response with respect to per-voxel
+# moduli (not in the paper).  For J = G:<sigma> + H:<eps> at the solution of
+# the linear problem, the Lagrangian gives dJ/dtheta(x) = (1/N) eta:dC/dtheta:eps
+# where eta solves the same DBFFT system with prescribed strain G on the
+# strain-controlled set and prescribed stress -H on S.
+# ---------------------------------------------------------------------------
+
+def adjoint_gradient(shape, tangent, dtangent, load, stress_mask, G, H, tol=1e-12,
+                     max_iter=10000):
+    """Returns (J, dJ/dtheta field (n1, n2, n3), forward result, adjoint result).
+    dtangent: IsoTangent of dC/dtheta per voxel (e.g. C(E=1, nu))."""
+    fwd = solve_linear(shape, tangent, load, stress_mask, tol, tol, max_iter)
+    mask = np.asarray(stress_mask if stress_mask is not None else np.zeros((3, 3)), bool)
+    G = np.asarray(G, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    adj_load = np.where(mask, -H, G)
+    adj = solve_linear(shape, tangent, adj_load, stress_mask, tol, tol, max_iter)
+    eps = fwd.strain_field()
+    eta = adj.strain_field()
+    N = float(np.prod(shape))
+    g = np.einsum("ij...,ij...->...", eta, dtangent.stress(eps)) / N
+    J = float(np.sum(G * fwd.sigma_bar) + np.sum(H * fwd.eps_bar))
+    return J, g, fwd, adj

@@ -1,0 +1,211 @@
+"""Pins of the oracle's linear DBFFT solve (Sec. 2.2, 2.3, 2.5) against
+closed forms, bounds, invariants and an FFT-free direct solve."""
+import numpy as np
+import pytest
+
+from oracle import dense, spectral as sp, solver as so, materials as mt
+from paper_1905_12725_amd import microstructure as ms
+
+
+def iso_phase_tangent(phase, E, nu):
+    Ev = np.asarray(E)[phase]
+    lam, mu = mt.lame(Ev, nu)
+    return so.IsoTangent(lam, mu)
+
+
+def uniaxial(v=1e-3):
+    L = np.zeros((3, 3))
+    L[0, 0] = v
+    return L
+
+
+def test_homogeneous_strain_control_zero_iterations():
+    n = (8, 8, 8)
+    tan = iso_phase_tangent(np.zeros(n, dtype=np.uint8), [2.0], 0.25)
+    L = np.array([[1e-3, 2e-4, 0], [2e-4, -5e-4, 1e-4], [0, 1e-4, 3e-4]])
+    r = so.solve_linear(n, tan, L)
+    assert r.info.iterations == 0
+    lam, mu = mt.lame(2.0, 0.25)
+    expect = lam * np.trace(L) * np.eye(3) + 2 * mu * L
+    assert np.allclose(r.sigma_bar, expect, rtol=1e-14, atol=1e-18)
+
+
+def test_homogeneous_uniaxial_stress_one_iteration():
+    """Mixed control on a homogeneous cell: the macro preconditioner is the
+    exact inverse, so CG converges in one iteration to the 0-D answer
+    sigma11 = E eps11, eps22 = eps33 = -nu eps11."""
+    n = (6, 6, 6)
+    E, nu = 3.0, 0.3
+    tan = iso_phase_tangent(np.zeros(n, dtype=np.uint8), [E], nu)
+    mask = np.ones((3, 3), bool)
+    mask[0, 0] = False
+    r = so.solve_linear(n, tan, uniaxial(), mask)
+    assert r.info.iterations == 1
+    assert np.isclose(r.sigma_bar[0, 0], E * 1e-3, rtol=1e-13)
+    assert np.allclose(np.diag(r.eps_bar), [1e-3, -nu * 1e-3, -nu * 1e-3], rtol=1e-13)
+    off = r.sigma_bar - np.diag(np.diag(r.sigma_bar))
+    assert np.max(np.abs(off)) < 1e-18
+    assert abs(r.sigma_bar[1, 1]) < 1e-16 and abs(r.sigma_bar[2, 2]) < 1e-16
+
+
+def laminate_closed_form(C_phases, fractions, normal, ebar):
+    """Piecewise-constant strain with traction continuity across layers."""
+    nvec = np.zeros(3)
+    nvec[normal] = 1.0
+    K = [np.einsum("j,ijkl,l->ik", nvec, C, nvec) for C in C_phases]
+    q = [np.einsum("ijkl,kl,j->i", C, ebar, nvec) for C in C_phases]
+    Kinv_avg = sum(f * np.linalg.inv(Kp) for f, Kp in zip(fractions, K))
+    Kinvq_avg = sum(f * np.linalg.solve(Kp, qp) for f, Kp, qp in zip(fractions, K, q))
+    t = np.linalg.solve(Kinv_avg, Kinvq_avg)
+    sig = np.zeros((3, 3))
+    for f, C, Kp, qp in zip(fractions, C_phases, K, q):
+        a = np.linalg.solve(Kp, t - qp)
+        eps = ebar + 0.5 * (np.outer(a, nvec) + np.outer(nvec, a))
+        sig += f * np.einsum("ijkl,kl->ij", C, eps)
+    return sig
+
+
+@pytest.mark.parametrize("shape,axis,layers", [
+    ((8, 4, 4), 0, [4, 2, 2]),       # even thicknesses on an even grid
+    ((4, 8, 6), 1, [2, 6]),
+    ((5, 5, 7), 2, [3, 4]),          # odd grid: any thickness
+])
+def test_laminate_exact(shape, axis, layers):
+    phase = ms.laminate(shape, axis, layers)
+    E = [1.0, 25.0]
+    nu = 0.3
+    tan = iso_phase_tangent(phase, E, nu)
+    L = np.array([[1e-3, 3e-4, -2e-4], [3e-4, 5e-4, 1e-4], [-2e-4, 1e-4, -7e-4]])
+    r = so.solve_linear(shape, tan, L, tol=1e-13, tol_load=1e-13)
+    f1 = float(phase.mean())
+    C = [mt.isotropic_tensor(*mt.lame(e, nu)) for e in E]
+    expect = laminate_closed_form(C, [1 - f1, f1], axis, L)
+    assert np.allclose(r.sigma_bar, expect, rtol=0, atol=1e-11 * np.abs(expect).max())
+
+
+def test_laminate_planted_transpose_fails():
+    """Swapping the normal (a transposed contraction) breaks the pin."""
+    shape, axis, layers = (8, 4, 4), 0, [4, 2, 2]
+    phase = ms.laminate(shape, axis, layers)
+    E, nu = [1.0, 25.0], 0.3
+    tan = iso_phase_tangent(phase, E, nu)
+    L = uniaxial()
+    L[0, 1] = L[1, 0] = 5e-4
+    r = so.solve_linear(shape, tan, L, tol=1e-12)
+    C = [mt.isotropic_tensor(*mt.lame(e, nu)) for e in E]
+    wrong = laminate_closed_form(C, [0.5, 0.5], 1, L)
+    assert not np.allclose(r.sigma_bar, wrong, atol=1e-9)
+
+
+def test_voigt_reuss_bounds_and_hill_mandel():
+    n = (16, 16, 16)
+    phase = ms.centred_sphere(n, 0.2)
+    E, nu = [1.0, 10.0], 0.3
+    tan = iso_phase_tangent(phase, E, nu)
+    rng = np.random.default_rng(7)
+    for _ in range(2):
+        L = rng.standard_normal((3, 3)) * 1e-3
+        L = 0.5 * (L + L.T)
+        r = so.solve_linear(n, tan, L, tol=1e-10)
+        W = float(np.sum(r.sigma_bar * L))
+        Cs = [mt.tensor4_to_mandel(mt.isotropic_tensor(*mt.lame(e, nu))) for e in E]
+        f1 = float(phase.mean())
+        Cv = (1 - f1) * Cs[0] + f1 * Cs[1]
+        Sr = (1 - f1) * np.linalg.inv(Cs[0]) + f1 * np.linalg.inv(Cs[1])
+        lv = mt.sym_to_mandel(L)
+        upper = lv @ Cv @ lv
+        lower = lv @ np.linalg.solve(Sr, lv)
+        assert lower <= W <= upper
+        eps = r.strain_field()
+        sig = tan.stress(eps)
+        hm = float(np.mean(np.sum(sig * eps, axis=(0, 1))))
+        assert abs(hm - W) <= 1e-8 * abs(W)
+
+
+def test_dense_direct_solve_matches_pcg():
+    """R1 (dense definition, no FFT, no iteration) equals R2 (FFT + PCG)."""
+    for shape, mask_comps in [((4, 4, 4), []), ((6, 4, 4), [(1, 1), (2, 2), (1, 2)]), ((5, 3, 4), [(0, 1)])]:
+        rng = np.random.default_rng(8)
+        phase = (rng.random(shape) < 0.4).astype(np.uint8)
+        E, nu = [1.0, 8.0], 0.3
+        tan = iso_phase_tangent(phase, E, nu)
+        mask = np.zeros((3, 3), bool)
+        for (i, j) in mask_comps:
+            mask[i, j] = mask[j, i] = True
+        L = np.array([[1e-3, 2e-4, 0], [2e-4, 4e-4, -1e-4], [0, -1e-4, -3e-4]])
+        r = so.solve_linear(shape, tan, L, mask, tol=1e-13, tol_load=1e-13)
+        Cm = np.stack([mt.tensor4_to_mandel(mt.isotropic_tensor(*mt.lame(E[p], nu)))
+                       for p in phase.reshape(-1)])
+        u_d, e_d, sig_d = dense.solve(shape, Cm, L, mask)
+        assert np.allclose(r.sigma_bar, sig_d, rtol=0, atol=1e-11 * np.abs(sig_d).max())
+        u_f = sp.real_field(r.a, shape)
+        u_d = u_d - u_d.mean(axis=(1, 2, 3), keepdims=True)
+        assert np.allclose(u_f, u_d, atol=1e-10 * np.abs(u_d).max())
+        assert np.allclose(r.e, e_d, atol=1e-11 * max(np.abs(e_d).max(initial=0), 1e-3))
+
+
+def test_preconditioner_exact_for_homogeneous():
+    shape = (6, 8, 4)
+    rng = np.random.default_rng(9)
+    mask = np.zeros((3, 3), bool)
+    mask[2, 2] = True
+    space = so.Space(shape, so.SMALL, mask)
+    C = rng.standard_normal((6, 6))
+    C = C @ C.T + 6 * np.eye(6)
+    C4 = mt.mandel_to_tensor4(C)
+    tan = so.GeneralTangent(np.broadcast_to(C4, shape + (3, 3, 3, 3)))
+    M = space.preconditioner(C4)
+    u = rng.standard_normal((3,) + shape)
+    a = sp.fourier(u, shape)
+    a[:, space.Z] = 0
+    x = (a, np.array([0.7]))
+    Kx, _ = space.apply(x, tan)
+    y = M(Kx)
+    assert np.allclose(y[0], x[0], atol=1e-12 * np.abs(a).max())
+    assert np.allclose(y[1], x[1], atol=1e-13)
+
+
+def test_translation_and_scaling_invariance():
+    n = (12, 12, 12)
+    phase = ms.centred_sphere(n, 0.2)
+    E, nu = [1.0, 10.0], 0.3
+    L = uniaxial()
+    r0 = so.solve_linear(n, iso_phase_tangent(phase, E, nu), L, tol=1e-11)
+    r1 = so.solve_linear(n, iso_phase_tangent(np.roll(phase, (3, -2, 5), axis=(0, 1, 2)), E, nu), L, tol=1e-11)
+    assert np.allclose(r0.sigma_bar, r1.sigma_bar, rtol=1e-9, atol=1e-15)
+    r2 = so.solve_linear(n, iso_phase_tangent(phase, [3.0, 30.0], nu), L, tol=1e-11)
+    assert r2.info.iterations == r0.info.iterations
+    assert np.allclose(r2.sigma_bar, 3.0 * r0.sigma_bar, rtol=1e-12, atol=1e-18)
+
+
+def test_sphere_axis_permutation_symmetry():
+    n = (12, 12, 12)
+    phase = ms.centred_sphere(n, 0.2)
+    tan = iso_phase_tangent(phase, [1.0, 10.0], 0.3)
+    L1 = np.zeros((3, 3)); L1[0, 0] = 1e-3
+    L2 = np.zeros((3, 3)); L2[1, 1] = 1e-3
+    s1 = so.solve_linear(n, tan, L1, tol=1e-11).sigma_bar
+    s2 = so.solve_linear(n, tan, L2, tol=1e-11).sigma_bar
+    P = np.array([[0, 1, 0], [1, 0, 0], [0, 0, 1]])
+    assert np.allclose(P @ s1 @ P.T, s2, rtol=1e-9, atol=1e-15)
+
+
+def test_cg_iteration_bound():
+    """PCG error bound with kappa <= E_max/E_min for same-nu phases."""
+    n = (16, 16, 16)
+    phase = ms.centred_sphere(n, 0.2)
+    tan = iso_phase_tangent(phase, [1.0, 10.0], 0.3)
+    r = so.solve_linear(n, tan, uniaxial())
+    assert r.info.converged
+    assert r.info.iterations <= 40
+    assert r.info.iterations == 32  # survey-time value of this configuration
+
+
+def test_breakdown_on_indefinite_tangent():
+    n = (4, 4, 4)
+    phase = np.zeros(n, dtype=np.uint8)
+    phase[0, 0, 0] = 1
+    lam, mu = mt.lame(np.where(phase == 1, -50.0, 1.0), 0.3)
+    tan = so.IsoTangent(lam, mu)
+    r = so.solve_linear(n, tan, uniaxial(), max_iter=200)
+    assert r.info.breakdown or not r.info.converged
