@@ -1,0 +1,188 @@
+/*
+ * dbfft.h — C ABI of the MI355X (gfx950) DBFFT hot path.
+ *
+ * DBFFT (Lucarini & Segurado, "DBFFT: A displacement based FFT approach for
+ * non-linear homogenization of the mechanical behavior", arXiv:1905.12725)
+ * solves periodic cell problems of solid mechanics with the displacement
+ * fluctuation, expressed by its Fourier coefficients, as the unknown.
+ *
+ * Problem statement (Sec. 2): a periodic unit cell discretized in
+ * n1 x n2 x n3 voxels (Sec. 2.1), a constitutive law per voxel, and a
+ * macroscopic load given by six (small strains) or nine (finite strains)
+ * values, each one a prescribed strain / deformation gradient component or a
+ * prescribed stress component (Sec. 2.2, 2.3, 2.4), applied in increments.
+ *
+ * Conventions of this library:
+ *   - unit cell (all L_a = 1); fields sampled at voxel centres; even grids
+ *     give the Nyquist frequency a zero wavenumber;
+ *   - n3 must be even (real-to-complex transforms along the last axis);
+ *     every grid size must factor into 2, 3 and 5;
+ *   - real fields are device arrays of doubles, component-major
+ *     [c][x][y][z] with z fastest; symmetric tensors have 6 components in
+ *     the order 11 22 33 23 13 12 (plain tensor components, no factors),
+ *     full 3x3 tensors 9 components row-major;
+ *   - Fourier unknowns are normalized coefficients a(k) = F[u](k)/N on the
+ *     real-transform half spectrum k3 = 0..n3/2, as device arrays of
+ *     interleaved complex doubles [3][n1][n2][n3/2+1];
+ *   - 3x3 host arrays (load, mask, averages) are row-major.
+ *
+ * Ownership: every device pointer passed in is owned by the caller and must
+ * stay valid until the call returns (all entry points synchronize the
+ * context's stream before returning).  The context owns its workspaces.
+ * Errors: every entry point returns a dbfft_status; dbfft_last_error()
+ * gives a message for the calling thread.  No C++ exception crosses the ABI.
+ */
+#ifndef DBFFT_H
+#define DBFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dbfft_ctx dbfft_ctx;
+
+typedef enum {
+  DBFFT_OK = 0,
+  DBFFT_EINVAL = 1,       /* bad argument (null pointer, size, mask, material) */
+  DBFFT_ENOMEM = 2,       /* device allocation failed */
+  DBFFT_EHIP = 3,         /* HIP runtime error; message has the hipError_t string */
+  DBFFT_ENOTCONV = 4,     /* iteration cap reached; info is filled */
+  DBFFT_EBREAKDOWN = 5,   /* <p, K p> <= 0 or NaN: tangent not positive definite */
+  DBFFT_EUNSUPPORTED = 6, /* valid request this build does not handle */
+  DBFFT_EMATERIAL = 7     /* constitutive update failed (J <= 0, local Newton) */
+} dbfft_status;
+
+enum { DBFFT_SMALL = 0, DBFFT_FINITE = 1 };          /* kinematics */
+enum { DBFFT_FP64 = 0, DBFFT_FP32_MIXED = 1 };       /* precision */
+
+/* Material kinds.  `field` is a device array of N = n1 n2 n3 entries;
+ * `params` a host array of `nparams` doubles.
+ *  ISO_PHASE   field uint8 phase id; params (E, nu) per phase (<= 8 phases).
+ *              Linear isotropic elasticity (Sec. 2.2, Sec. 3.1 material).
+ *  ISO_FIELD   field double E(x); params (nu).  Linear isotropic with a
+ *              per-voxel Young's modulus; the only kind dbfft_adjoint handles.
+ *  ANISO_GRAIN field int32 grain id; params 36 doubles per grain: the 6x6
+ *              stiffness in the orthonormal Mandel basis (11 22 33 √2·23
+ *              √2·13 √2·12), row-major.  Linear anisotropic elasticity.
+ *  J2VP_CUBIC  field int32 grain id; params (C11, C12, C44, sigma0, m,
+ *              edot0) then 9 doubles per grain: the rotation R (row-major)
+ *              mapping crystal to sample axes.  Cubic elasticity with rate-
+ *              dependent J2 flow d eps_p/dt = edot0 (s_eq/sigma0)^m (3/2) s/s_eq,
+ *              backward Euler; small strains; Newton outer loop (Sec. 2.4).
+ *  NEOHOOKE    field uint8 phase id; params (mu, kappa) per phase.
+ *              W = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2 with
+ *              lambda = kappa - 2 mu / 3; finite strains (Sec. 2.4). */
+enum {
+  DBFFT_MAT_ISO_PHASE = 0,
+  DBFFT_MAT_ISO_FIELD = 1,
+  DBFFT_MAT_ANISO_GRAIN = 2,
+  DBFFT_MAT_J2VP_CUBIC = 3,
+  DBFFT_MAT_NEOHOOKE = 4
+};
+
+typedef struct {
+  double tol;          /* equilibrium residual ||div sigma||_L2/||<sigma>|| (Sec. 3, eq. chedckeq); 1e-8 */
+  double tol_load;     /* loading residual ||<sigma>_S - sbar_S||/||<sigma>|| (eq. chedckimp); 1e-10 */
+  int32_t max_iter;    /* PCG iteration cap per linear solve (Sec. 3.1); 10000 */
+  double newton_tol;   /* max change of any strain / F component in a Newton update (Sec. 2.4); 1e-6 */
+  int32_t max_newton;  /* Newton iterations per increment; 25 */
+  int32_t refresh;     /* preconditioner mean tangent: 0 every increment, 1 first increment only (Sec. 2.5) */
+  double inner_tol;    /* FP32_MIXED: relative reduction asked of each inner FP32 solve; 1e-4 */
+  int32_t max_refine;  /* FP32_MIXED: outer FP64 residual corrections; 30 */
+  int32_t check_every; /* PCG iterations enqueued between host convergence polls; 8 */
+} dbfft_opts;
+
+typedef struct {
+  int32_t pcg_iters;    /* PCG iterations (operator applications) of the last dbfft_solve, all steps */
+  int32_t newton_iters; /* Newton iterations, all increments */
+  int32_t increments;   /* increments completed */
+  int32_t refine_steps; /* FP32_MIXED outer corrections */
+  int32_t status;       /* dbfft_status of the solve */
+  int32_t pad;
+  double eq_res;        /* equilibrium residual of the final state */
+  double load_res;      /* loading residual of the final state */
+  double sigma_bar[9];  /* <sigma> (or <P>), row-major */
+  double eps_bar[9];    /* <eps> (or <F>), row-major */
+} dbfft_info;
+
+/* Fills the defaults listed above. */
+void dbfft_default_opts(dbfft_opts* opts);
+
+/* Creates a context for one cell (Sec. 2.1 discretization + material).
+ * n: grid size (host, 3 values); kinematics DBFFT_SMALL / DBFFT_FINITE
+ * (NEOHOOKE needs FINITE, every other kind SMALL); precision DBFFT_FP64 or
+ * DBFFT_FP32_MIXED (FP32 transforms and pointwise work, FP64 dot products,
+ * residuals and outer corrections); hip_stream: hipStream_t the context
+ * enqueues on (NULL = default stream).  The material field is copied.
+ * EINVAL on null pointers, non-positive or odd n3, sizes with prime factors
+ * other than 2, 3, 5, unknown or mismatched material kind. */
+dbfft_status dbfft_setup(dbfft_ctx** out, const int64_t n[3], int32_t kinematics, int32_t precision,
+                         int32_t material, const void* field_dev, const double* params, int32_t nparams,
+                         void* hip_stream);
+
+/* Real-space operator application of Sec. 2.2 eq. lineqf (sign flipped so
+ * that it is positive semi-definite): f = -div(C : sym grad u) for small
+ * strains, f = -div(K : grad u) for finite strains, with the tangent of the
+ * current state (the elastic stiffness before any solve).  Steps: forward
+ * transform of the 3 displacement components, Fourier gradient, inverse
+ * transform, pointwise tangent, forward transform, Fourier divergence,
+ * inverse transform.  u_dev, f_dev: device doubles [3][n1][n2][n3]. */
+dbfft_status dbfft_apply(dbfft_ctx* ctx, const double* u_dev, double* f_dev);
+
+/* The same operator on Fourier unknowns, as iterated by the solver:
+ * (K a)(k) = -i xi_j s_ij(k) with s = F[C : (e + sum_k s(k).a(k) e^{i xi.x})]/N,
+ * and its macroscopic row <sigma> (9 doubles, row-major, written to
+ * sigma_bar_out if not NULL).  e_macro: host 3x3 macro strain added to the
+ * field (NULL = 0).  a_dev, f_dev: device complex doubles [3][n1][n2][n3/2+1]. */
+dbfft_status dbfft_apply_fourier(dbfft_ctx* ctx, const void* a_dev, const double* e_macro, void* f_dev,
+                                 double* sigma_bar_out);
+
+/* Solves the cell problem (Sec. 2.2-2.5): PCG with the preconditioner
+ * [xi.Cbar.xi]^-1 (eqs. pred2/pred3); Newton over increments for J2VP_CUBIC
+ * and NEOHOOKE.  load: 9 host doubles, row-major; on components whose
+ * stress_mask entry is 0 the prescribed strain (small) or deformation
+ * gradient F (finite), elsewhere the prescribed stress (Sec. 2.3).  Small
+ * strains need a symmetric mask and symmetric load.  The load is reached by
+ * n_increments equal steps of the strain (or F - I) and stress; dt is the
+ * time per increment (rate-dependent laws).  Linear materials use one step.
+ * opts may be NULL (defaults).  info may be NULL.  The solution stays in
+ * the context for dbfft_homogenize / dbfft_adjoint.  Returns ENOTCONV or
+ * EBREAKDOWN with info filled when the iteration fails. */
+dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t stress_mask[9], int32_t n_increments,
+                         double dt, const dbfft_opts* opts, dbfft_info* info);
+
+/* Homogenized response of the last solve (Sec. 3 post-processing):
+ * <sigma> and <eps> (row-major, host, either may be NULL) and, when the
+ * pointers are not NULL, the real fields of strain (6 or 9 comps), stress
+ * (6 or 9 comps) and displacement fluctuation u~ (3 comps) as device doubles
+ * [c][n1][n2][n3]. */
+dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_bar[9], double* strain_dev,
+                              double* stress_dev, double* disp_dev);
+
+/* Fourier unknowns of the last solve: a (device complex doubles
+ * [3][n1][n2][n3/2+1]) and the macro strain on the stress-controlled
+ * components (host 3x3 row-major); either may be NULL. */
+dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]);
+
+/* Adjoint gradient of J = G:<sigma> + H:<eps> at the last linear solve with
+ * respect to the per-voxel Young's modulus (DBFFT_MAT_ISO_FIELD, small
+ * strains).  A second PCG solve with the same operator and stress mask and
+ * load (G on the strain-controlled, -H on the stress-controlled components)
+ * gives eta; grad(x) = eta(x) : C1 : eps(x) / N with C1 the unit-modulus
+ * stiffness.  G, H: host row-major 3x3.  grad_dev: device doubles [N].
+ * J_out (host, may be NULL) receives J. */
+dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out);
+
+/* Releases the context and its device memory. */
+void dbfft_destroy(dbfft_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dbfft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBFFT_H */

@@ -1,0 +1,180 @@
+"""Python front end of the DBFFT HIP library.
+
+PyTorch provides device memory and the stream; all arithmetic runs in
+libdbfft.so.  Shapes follow include/dbfft.h: real fields (c, n1, n2, n3)
+float64, Fourier unknowns (3, n1, n2, n3//2+1) complex128, 3x3 host arrays.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+import torch
+
+from . import _native as nat
+
+_KIN = {"small": nat.SMALL, "finite": nat.FINITE}
+_PREC = {"fp64": nat.FP64, "fp32_mixed": nat.FP32_MIXED}
+_MAT = {
+    "iso_phase": (nat.MAT_ISO_PHASE, torch.uint8),
+    "iso_field": (nat.MAT_ISO_FIELD, torch.float64),
+    "aniso_grain": (nat.MAT_ANISO_GRAIN, torch.int32),
+    "j2vp_cubic": (nat.MAT_J2VP_CUBIC, torch.int32),
+    "neohooke": (nat.MAT_NEOHOOKE, torch.uint8),
+}
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr())
+
+
+def _info_dict(info):
+    return {
+        "pcg_iters": info.pcg_iters,
+        "newton_iters": info.newton_iters,
+        "increments": info.increments,
+        "refine_steps": info.refine_steps,
+        "status": info.status,
+        "eq_res": info.eq_res,
+        "load_res": info.load_res,
+        "sigma_bar": np.array(info.sigma_bar[:]).reshape(3, 3),
+        "eps_bar": np.array(info.eps_bar[:]).reshape(3, 3),
+    }
+
+
+class Cell:
+    """One periodic cell (grid + material) bound to a HIP stream."""
+
+    def __init__(self, n, material, field, params, kinematics="small", precision="fp64", stream=None,
+                 device="cuda"):
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        self.kin = kinematics
+        self.prec = precision
+        self.material = material
+        kind, dtype = _MAT[material]
+        f = torch.as_tensor(field).to(device=device, dtype=dtype).contiguous()
+        if f.numel() != self.N:
+            raise ValueError("material field must have n1*n2*n3 entries")
+        self.field = f
+        self.device = f.device
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+        dims = (ct.c_int64 * 3)(*self.n)
+        h = ct.c_void_p()
+        nat.check(nat.lib().dbfft_setup(ct.byref(h), dims, _KIN[kinematics], _PREC[precision], kind,
+                                        _ptr(f), p.ctypes.data_as(ct.POINTER(ct.c_double)), int(p.size),
+                                        ct.c_void_p(stream.cuda_stream)))
+        self._h = h
+        self.ncomp = 6 if kinematics == "small" else 9
+        self.half = (self.n[0], self.n[1], self.n[2] // 2 + 1)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            nat.lib().dbfft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def solve(self, load, stress_mask=None, n_increments=1, dt=1.0, raise_on_fail=True, **opts):
+        load = np.asarray(load, dtype=np.float64).reshape(9)
+        mask = np.zeros(9, dtype=np.uint8) if stress_mask is None else \
+            np.asarray(stress_mask, dtype=bool).reshape(9).astype(np.uint8)
+        o = nat.default_opts(**opts)
+        info = nat.Info()
+        st = nat.lib().dbfft_solve(self._h, nat.dvec(load), (ct.c_uint8 * 9)(*mask.tolist()), int(n_increments),
+                                   float(dt), ct.byref(o), ct.byref(info))
+        if st != nat.DBFFT_OK and raise_on_fail:
+            nat.check(st)
+        d = _info_dict(info)
+        d["status"] = st
+        return d
+
+    def apply(self, u):
+        u = u.to(device=self.device, dtype=torch.float64).contiguous()
+        f = torch.empty_like(u)
+        nat.check(nat.lib().dbfft_apply(self._h, _ptr(u), _ptr(f)))
+        return f
+
+    def apply_fourier(self, a, e_macro=None):
+        a = a.to(device=self.device, dtype=torch.complex128).contiguous()
+        f = torch.empty_like(a)
+        sig = (ct.c_double * 9)()
+        em = None if e_macro is None else nat.dvec(np.asarray(e_macro, dtype=np.float64).reshape(9))
+        nat.check(nat.lib().dbfft_apply_fourier(self._h, _ptr(a), em, _ptr(f), sig))
+        return f, np.array(sig[:]).reshape(3, 3)
+
+    def homogenize(self, strain=False, stress=False, displacement=False):
+        sig = (ct.c_double * 9)()
+        eps = (ct.c_double * 9)()
+        out = {}
+        fs = torch.empty((self.ncomp,) + self.n, dtype=torch.float64, device=self.device) if strain else None
+        fp = torch.empty((self.ncomp,) + self.n, dtype=torch.float64, device=self.device) if stress else None
+        fu = torch.empty((3,) + self.n, dtype=torch.float64, device=self.device) if displacement else None
+        nat.check(nat.lib().dbfft_homogenize(self._h, sig, eps, _ptr(fs) if fs is not None else None,
+                                             _ptr(fp) if fp is not None else None,
+                                             _ptr(fu) if fu is not None else None))
+        out["sigma_bar"] = np.array(sig[:]).reshape(3, 3)
+        out["eps_bar"] = np.array(eps[:]).reshape(3, 3)
+        if strain:
+            out["strain"] = fs
+        if stress:
+            out["stress"] = fp
+        if displacement:
+            out["displacement"] = fu
+        return out
+
+    def solution(self):
+        a = torch.empty((3,) + self.half, dtype=torch.complex128, device=self.device)
+        e = (ct.c_double * 9)()
+        nat.check(nat.lib().dbfft_get_solution(self._h, _ptr(a), e))
+        return a, np.array(e[:]).reshape(3, 3)
+
+    def adjoint(self, G, H=None):
+        G = np.asarray(G, dtype=np.float64).reshape(9)
+        H = np.zeros(9) if H is None else np.asarray(H, dtype=np.float64).reshape(9)
+        grad = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        J = ct.c_double()
+        nat.check(nat.lib().dbfft_adjoint(self._h, nat.dvec(G), nat.dvec(H), _ptr(grad), ct.byref(J)))
+        return grad, J.value
+
+
+class HomogenizedResponse(torch.autograd.Function):
+    """J(E) = G:<sigma> + H:<eps> of a linear cell with per-voxel Young's
+    modulus E (Poisson ratio nu), load / stress_mask as in Cell.solve.
+    backward runs the adjoint solve of the same operator."""
+
+    @staticmethod
+    def forward(ctx, E, load, stress_mask, G, H, nu, precision, tol):
+        cell = Cell(E.shape, "iso_field", E.detach(), [nu], precision=precision, device=E.device)
+        cell.solve(load, stress_mask, tol=tol, tol_load=tol)
+        grad, J = cell.adjoint(G, H)
+        cell.close()
+        ctx.save_for_backward(grad)
+        return torch.tensor(J, dtype=torch.float64, device=E.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout * grad, None, None, None, None, None, None, None
+
+
+def homogenized_response(E, load, stress_mask=None, G=None, H=None, nu=0.3, precision="fp64", tol=1e-10):
+    if G is None:
+        G = np.zeros((3, 3))
+    if H is None:
+        H = np.zeros((3, 3))
+    return HomogenizedResponse.apply(E, load, stress_mask, G, H, nu, precision, tol)

@@ -1,0 +1,181 @@
+// Internal declarations shared by the HIP kernels and the host engine.
+//
+// Layouts (all device arrays, C order):
+//   half spectrum  [c][k1][k2][k3]   k3 = 0 .. n3/2   (complex, T2 = float2/double2)
+//   real field     [c][x][y][z]      z fastest        (T)
+// A vector of the Krylov space is 3 half-spectrum components plus a small
+// FP64 macro block kept separately.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace dbfft {
+
+constexpr int kMaxStages = 12;
+constexpr int kMaxPhases = 8;
+constexpr int kMaxMacro = 9;
+constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2*pi
+
+// Stockham plan of one complex transform of length n = prod(radix).
+struct FftPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  int ns[kMaxStages];  // length of the sub-transforms combined before the stage
+};
+
+struct Geom {
+  int n1, n2, n3, nh3;  // nh3 = n3/2 + 1
+  long long nh;         // n1*n2*nh3
+  long long nvox;       // n1*n2*n3
+  double inv_nvox;
+};
+
+enum Kin : int { KIN_SMALL = 0, KIN_FINITE = 1 };
+
+// Pointwise tangent used inside the fused z pass.
+enum TanKind : int {
+  TAN_ISO_PHASE = 0,   // uint8 phase id -> (lambda, mu)
+  TAN_ISO_FIELD = 1,   // per-voxel modulus scaling unit-modulus (lambda1, mu1)
+  TAN_ANISO_GRAIN = 2, // int32 grain id -> 21 Mandel coefficients (table)
+  TAN_ANISO_FIELD = 3, // 21 Mandel coefficients per voxel, [21][nvox]
+  TAN_NEO_FIELD = 4,   // finite strain: per-voxel F^-1 (9) and ln J, [10][nvox]; phase -> (mu, lambda)
+};
+
+template <typename T>
+struct TangentArgs {
+  int kind;
+  int nphase;
+  double lam[kMaxPhases];
+  double mu[kMaxPhases];
+  double lam1, mu1;             // TAN_ISO_FIELD
+  const uint8_t* phase;         // TAN_ISO_PHASE, TAN_NEO_FIELD
+  const T* field;               // TAN_ISO_FIELD: [nvox]; ANISO_FIELD: [21][nvox]; NEO: [10][nvox]
+  const int32_t* grain;         // TAN_ANISO_GRAIN
+  const double* grain_table;    // TAN_ANISO_GRAIN: [ngrain][21]
+};
+
+// Preconditioner M(xi) = [xi.Cbar.xi]^-1: A_ik = sum_{j<=l} xi_j xi_l G[jl][ik]
+// (symmetric 3x3 stored as 6: 00 11 22 12 02 01).
+struct PrecondArgs {
+  double G[6][6];
+};
+
+// Device-resident scalars of one PCG solve.
+struct PcgScalars {
+  double rz;          // <r, z>
+  double pq;          // <p, K p>
+  double alpha, beta;
+  double rr;          // <r_a, r_a> (full-spectrum norm^2 of the displacement part)
+  double re2;         // |r_e|^2
+  double sig[9];      // average stress (or nominal stress) of the current iterate
+  double xe[kMaxMacro], re[kMaxMacro], pe[kMaxMacro], qe[kMaxMacro];
+  double pmac[9];     // macro strain tensor of p (stored component order), read by the z pass
+  double eq_res, load_res;
+  int iter;
+  int converged;      // 1 converged, 2 breakdown, 3 iteration cap
+  int pad[2];
+};
+
+struct PcgConst {
+  double tol, tol_load;
+  int max_iter;
+  int nmacro;                         // |S|
+  int ncomp;                          // 6 or 9
+  double Me[kMaxMacro][kMaxMacro];    // macro preconditioner
+  double basis[kMaxMacro][9];         // B_a as row-major 3x3 (stress-controlled set only)
+};
+
+// ---------------------------------------------------------------- launchers
+// All launches are asynchronous on `st`.  T is float or double.
+
+// x/y passes over lines with element stride `lstride`, `nother` lines per
+// column tile (other index stride `ostride`), contiguous k3 columns.
+struct StridedGeom {
+  int nline;          // transform length
+  long long lstride;  // element stride along the line
+  long long ostride;  // stride of the other (non-transformed, non-k3) index
+  int nother;         // count of the other index
+  int ncols;          // nh3
+  long long cstride_in, cstride_out;  // component strides
+};
+
+enum StridedMode : int {
+  SP_PLAIN = 0,       // C independent components (grid z = component)
+  SP_GRAD_SMALL = 1,  // in: 3 comps a -> out: 6 comps i/2 (xi_j a_i + xi_i a_j), then inverse FFT along x
+  SP_GRAD_FINITE = 2, // in: 3 comps a -> out: 9 comps i xi_j a_i, inverse FFT along x
+  SP_DIV_SMALL = 3,   // in: 6 comps, forward FFT along x, out: 3 comps -i xi_j s_ij
+  SP_DIV_FINITE = 4,  // in: 9 comps, forward FFT along x, out: 3 comps
+};
+
+template <typename T>
+void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,
+                    const Geom& g, const FftPlan& plan, const void* tw, int dir, double* dc_out,
+                    hipStream_t st, const int* stop);
+
+enum LineMode : int {
+  LP_FUSED = 0,       // C2R -> (+ macro) -> tangent -> R2C (scaled 1/N); energy partials
+  LP_C2R = 1,         // C2R (+ macro) -> real out
+  LP_R2C = 2,         // real in -> R2C scaled 1/N
+  LP_CONST = 3,       // constant field (macro only) -> tangent -> R2C scaled 1/N
+  LP_STRESS = 4,      // C2R (+ macro) -> tangent -> real out
+};
+
+template <typename T>
+void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, const FftPlan& plan,
+                 const void* tw, const void* rtw, const TangentArgs<T>& tan, const double* macro_dev,
+                 const double* macro_add, double* partials, int ncomp, hipStream_t st, int* nblocks_out,
+                 const int* stop);
+
+int line_block_count(const Geom& g);
+int line_lines_per_block(const Geom& g, int ncomp, int elem_bytes);
+
+// PCG vector kernels (3 half-spectrum components).
+template <typename T>
+void launch_pcg_update(void* x, void* r, const void* p, const void* q, const PcgScalars* sc,
+                       const PrecondArgs& pa, const Geom& g, double* partials, int nblocks, hipStream_t st);
+template <typename T>
+void launch_pcg_pupdate(void* p, const void* r, const PcgScalars* sc, const PrecondArgs& pa,
+                        const Geom& g, int nblocks, hipStream_t st);
+template <typename T>
+void launch_precond_init(void* p, const void* r, const PrecondArgs& pa, const Geom& g, double* partials,
+                         int nblocks, hipStream_t st);
+void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
+                      hipStream_t st);
+void launch_pcg_beta(PcgScalars* sc, const double* partials, int nparts, const PcgConst& pc, int first,
+                     hipStream_t st);
+int pcg_block_count(const Geom& g);
+
+// vector utilities
+template <typename T>
+void launch_axpby(void* y, const void* x, double a, double b, long long n2, hipStream_t st);  // y = a x + b y (n2 reals)
+template <typename Tin, typename Tout>
+void launch_convert(void* out, const void* in, long long n, hipStream_t st);
+void launch_dot_w(const void* u, const void* v, int isf32, const Geom& g, double* partials, int nblocks,
+                  hipStream_t st);
+void launch_reduce(const double* partials, int nparts, int nvals, double* out, hipStream_t st);
+
+// materials / fields
+template <typename T>
+void launch_tangent_mean(const TangentArgs<T>& tan, int kin, const Geom& g, double* partials, int nblocks,
+                         hipStream_t st);
+int tangent_mean_block_count(const Geom& g);
+int tangent_mean_nvals(int kin);
+
+struct NeoParams {
+  double mu[kMaxPhases];
+  double lam[kMaxPhases];
+};
+
+void launch_j2_update(const double* eps, const double* epsp_n, const int32_t* grain, const double* grain_C,
+                      const double* grain_S, double s0, double m, double edot0, double dt, long long nvox,
+                      double* sig, double* tangent21, double* epsp_new, int* fail, hipStream_t st);
+void launch_neo_update(const double* H, const uint8_t* phase, const NeoParams& np, long long nvox, double* P,
+                       double* data, int* fail, hipStream_t st);
+void launch_max_abs_diff(const double* a, const double* b, long long n, double* partials, int nblocks,
+                         hipStream_t st);
+void launch_adjoint_density(const double* eps, const double* eta, double lam1, double mu1, long long nvox,
+                            double* grad, double scale, hipStream_t st);
+
+}  // namespace dbfft

@@ -1,0 +1,1405 @@
+// Host engine and C ABI of the DBFFT hot path.
+//
+// One context = one periodic cell: grid, material, FFT plans and twiddles,
+// device workspaces, and the current solution.  Every entry point enqueues
+// on the context's stream and synchronizes before returning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dbfft.h"
+#include "dbfft_internal.h"
+
+namespace dbfft {
+
+static thread_local std::string g_err;
+
+struct Err {
+  int code;
+};
+
+#define DB_THROW(code, msg)    \
+  do {                         \
+    g_err = (msg);             \
+    throw Err{(int)(code)};    \
+  } while (0)
+
+#define HIPCK(call)                                                                           \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      g_err = std::string("HIP error ") + hipGetErrorString(e_) + " at " #call;              \
+      throw Err{(int)DBFFT_EHIP};                                                             \
+    }                                                                                         \
+  } while (0)
+
+static const int kPair[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+
+// ------------------------------------------------------------------ helpers
+static bool make_plan(int n, FftPlan& p) {
+  std::memset(&p, 0, sizeof(p));
+  p.n = n;
+  int m = n, ns = 1;
+  const int radices[5] = {8, 4, 2, 3, 5};
+  for (int r : radices) {
+    while (m % r == 0) {
+      if (p.nstages >= kMaxStages) return false;
+      p.radix[p.nstages] = r;
+      p.ns[p.nstages] = ns;
+      ns *= r;
+      m /= r;
+      p.nstages++;
+    }
+  }
+  return m == 1;
+}
+
+// inverse of a small dense matrix (row-major, n <= 9), Gauss-Jordan with pivoting
+static bool small_inverse(const std::vector<double>& A, int n, std::vector<double>& X) {
+  std::vector<double> M(A);
+  X.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) X[i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(M[i * n + k]) > std::fabs(M[piv * n + k])) piv = i;
+    if (!(std::fabs(M[piv * n + k]) > 0.0)) return false;
+    if (piv != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(M[k * n + j], M[piv * n + j]);
+        std::swap(X[k * n + j], X[piv * n + j]);
+      }
+    const double inv = 1.0 / M[k * n + k];
+    for (int j = 0; j < n; ++j) {
+      M[k * n + j] *= inv;
+      X[k * n + j] *= inv;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = M[i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        M[i * n + j] -= f * M[k * n + j];
+        X[i * n + j] -= f * X[k * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+// Mandel basis tensor B_a (row-major 3x3)
+static void mandel_tensor(int a, double B[9]) {
+  std::memset(B, 0, 9 * sizeof(double));
+  const int i = kPair[a][0], j = kPair[a][1];
+  if (i == j) B[i * 3 + i] = 1.0;
+  else {
+    B[i * 3 + j] = B[j * 3 + i] = 1.0 / std::sqrt(2.0);
+  }
+}
+
+// row-major 3x3 <-> stored component order
+static void rm_to_stored(int kin, const double rm[9], double st[9]) {
+  if (kin == KIN_FINITE) {
+    for (int c = 0; c < 9; ++c) st[c] = rm[c];
+  } else {
+    for (int c = 0; c < 6; ++c) st[c] = rm[kPair[c][0] * 3 + kPair[c][1]];
+    for (int c = 6; c < 9; ++c) st[c] = 0.0;
+  }
+}
+static void stored_to_rm(int kin, const double st[9], double rm[9]) {
+  if (kin == KIN_FINITE) {
+    for (int c = 0; c < 9; ++c) rm[c] = st[c];
+  } else {
+    for (int c = 0; c < 6; ++c) {
+      rm[kPair[c][0] * 3 + kPair[c][1]] = st[c];
+      rm[kPair[c][1] * 3 + kPair[c][0]] = st[c];
+    }
+  }
+}
+
+template <typename T>
+struct Tables {
+  void *tw1, *tw2, *tw3, *rtw;
+};
+
+struct Ctx {
+  int n[3];
+  Geom g;
+  int kin, prec, mat, ncomp;
+  hipStream_t st;
+  FftPlan p1, p2, p3;
+  Tables<double> td;
+  Tables<float> tf;
+
+  // material
+  int nphase = 0;
+  uint8_t* phase = nullptr;
+  double* E64 = nullptr;
+  float* E32 = nullptr;
+  int32_t* grain = nullptr;
+  int ngrain = 0;
+  double* grain21 = nullptr;  // [ngrain][21] Mandel upper triangle
+  double* grainC = nullptr;   // [ngrain][36]
+  double* grainS = nullptr;   // [ngrain][36] inverse
+  double lam[kMaxPhases] = {0}, mu[kMaxPhases] = {0};
+  double nu = 0.3, lam1 = 0, mu1 = 0;
+  double j2_s0 = 0, j2_m = 0, j2_edot0 = 0;
+
+  // workspaces
+  void* W = nullptr;  // ncomp x nh complex double
+  void *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *b = nullptr, *t64 = nullptr;
+  double* sol = nullptr;   // FP64 coefficients of the solution
+  double* sol2 = nullptr;  // adjoint solution
+  double *fa = nullptr, *fb = nullptr, *fc = nullptr;  // real FP64 fields ncomp x N
+  double *state = nullptr, *state_new = nullptr;        // J2 plastic strain (Mandel) 6 x N
+  double* tanf = nullptr;                               // J2: 21 x N; neo: 10 x N  (FP64)
+  float* tanf32 = nullptr;
+  double* partA = nullptr;  // energy partials / general
+  double* partB = nullptr;  // update partials
+  size_t npart = 0;
+  PcgScalars* sc_dev = nullptr;
+  PcgScalars* sc_host = nullptr;
+  double* dc_dev = nullptr;
+  double* mac_dev = nullptr;  // 9 doubles: macro added in the z pass
+  double* red_dev = nullptr;  // 128 doubles reduction output
+  double* red_host = nullptr;
+  int* fail_dev = nullptr;
+
+  // current tangent for apply: 0 elastic, 1 field (after a nonlinear solve)
+  int tangent_from_field = 0;
+
+  // solution state
+  bool solved = false;
+  int last_mask[9] = {0};
+  double EU_st[9] = {0};   // prescribed strain part (stored order)
+  double e_st[9] = {0};    // macro unknown as a tensor (stored order)
+  double sig_rm[9] = {0}, eps_rm[9] = {0};
+  bool linear_material() const { return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE; }
+};
+
+static void* dalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    DB_THROW(DBFFT_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+template <typename T>
+static void* upload_table(const std::vector<double>& re, const std::vector<double>& im) {
+  std::vector<T> h(2 * re.size());
+  for (size_t i = 0; i < re.size(); ++i) {
+    h[2 * i] = (T)re[i];
+    h[2 * i + 1] = (T)im[i];
+  }
+  void* d = dalloc(h.size() * sizeof(T));
+  HIPCK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+static void twiddles(int n, int denom, int count, std::vector<double>& re, std::vector<double>& im) {
+  re.resize(count);
+  im.resize(count);
+  for (int k = 0; k < count; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)denom;
+    re[k] = std::cos(ang);
+    im[k] = -std::sin(ang);
+  }
+  (void)n;
+}
+
+// ------------------------------------------------------------------ tangent args
+template <typename T>
+static TangentArgs<T> elastic_tangent(Ctx& c);
+
+template <>
+TangentArgs<double> elastic_tangent<double>(Ctx& c) {
+  TangentArgs<double> t;
+  std::memset(&t, 0, sizeof(t));
+  t.nphase = c.nphase;
+  for (int i = 0; i < kMaxPhases; ++i) {
+    t.lam[i] = c.lam[i];
+    t.mu[i] = c.mu[i];
+  }
+  t.lam1 = c.lam1;
+  t.mu1 = c.mu1;
+  t.phase = c.phase;
+  t.grain = c.grain;
+  t.grain_table = c.grain21;
+  switch (c.mat) {
+    case DBFFT_MAT_ISO_PHASE: t.kind = TAN_ISO_PHASE; break;
+    case DBFFT_MAT_ISO_FIELD: t.kind = TAN_ISO_FIELD; t.field = c.E64; break;
+    case DBFFT_MAT_NEOHOOKE: t.kind = TAN_NEO_FIELD; t.field = c.tanf; break;
+    case DBFFT_MAT_J2VP_CUBIC:
+      if (c.tangent_from_field) {
+        t.kind = TAN_ANISO_FIELD;
+        t.field = c.tanf;
+      } else {
+        t.kind = TAN_ANISO_GRAIN;
+      }
+      break;
+    default: t.kind = TAN_ANISO_GRAIN; break;
+  }
+  return t;
+}
+
+template <>
+TangentArgs<float> elastic_tangent<float>(Ctx& c) {
+  TangentArgs<double> d = elastic_tangent<double>(c);
+  TangentArgs<float> t;
+  std::memset(&t, 0, sizeof(t));
+  t.kind = d.kind;
+  t.nphase = d.nphase;
+  for (int i = 0; i < kMaxPhases; ++i) {
+    t.lam[i] = d.lam[i];
+    t.mu[i] = d.mu[i];
+  }
+  t.lam1 = d.lam1;
+  t.mu1 = d.mu1;
+  t.phase = d.phase;
+  t.grain = d.grain;
+  t.grain_table = d.grain_table;
+  if (d.kind == TAN_ISO_FIELD) t.field = c.E32;
+  else if (d.kind == TAN_ANISO_FIELD || d.kind == TAN_NEO_FIELD) t.field = c.tanf32;
+  return t;
+}
+
+template <typename T>
+static Tables<T>& tables(Ctx& c);
+template <>
+Tables<double>& tables<double>(Ctx& c) { return c.td; }
+template <>
+Tables<float>& tables<float>(Ctx& c) { return c.tf; }
+
+static StridedGeom xgeom(const Ctx& c) {
+  StridedGeom s;
+  s.nline = c.n[0];
+  s.lstride = (long long)c.n[1] * c.g.nh3;
+  s.ostride = c.g.nh3;
+  s.nother = c.n[1];
+  s.ncols = c.g.nh3;
+  s.cstride_in = c.g.nh;
+  s.cstride_out = c.g.nh;
+  return s;
+}
+static StridedGeom ygeom(const Ctx& c) {
+  StridedGeom s;
+  s.nline = c.n[1];
+  s.lstride = c.g.nh3;
+  s.ostride = (long long)c.n[1] * c.g.nh3;
+  s.nother = c.n[0];
+  s.ncols = c.g.nh3;
+  s.cstride_in = c.g.nh;
+  s.cstride_out = c.g.nh;
+  return s;
+}
+
+// ------------------------------------------------------------------ operator pieces
+// K a: x inverse + gradient -> y inverse -> z fused tangent -> y forward -> x forward + divergence
+template <typename T>
+static void apply_K(Ctx& c, const void* a, void* out, const double* macro_dev, const double* macro_add,
+                    const TangentArgs<T>& tan, double* energy_partials, double* dc_out, const int* stop) {
+  Tables<T>& tb = tables<T>(c);
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  const int gm = (c.kin == KIN_SMALL) ? SP_GRAD_SMALL : SP_GRAD_FINITE;
+  const int dm = (c.kin == KIN_SMALL) ? SP_DIV_SMALL : SP_DIV_FINITE;
+  launch_strided<T>(gm, a, c.W, 0, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, stop);
+  launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, stop);
+  int nb = 0;
+  launch_line<T>(LP_FUSED, c.kin, c.W, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, macro_dev, macro_add, energy_partials,
+                 c.ncomp, c.st, &nb, stop);
+  launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
+  launch_strided<T>(dm, c.W, out, 0, sx, c.g, c.p1, tb.tw1, -1, dc_out, c.st, stop);
+}
+
+template <typename T>
+static int energy_blocks(Ctx& c) {
+  const int L = line_lines_per_block(c.g, c.ncomp, (int)(2 * sizeof(T)));
+  return (int)(((long long)c.g.n1 * c.g.n2 + L - 1) / L);
+}
+
+// K [0; E] (stress of a uniform strain E): -> out (3 comps), dc
+template <typename T>
+static void apply_const(Ctx& c, void* out, const double* macro_add, const TangentArgs<T>& tan, double* dc_out) {
+  Tables<T>& tb = tables<T>(c);
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  const int dm = (c.kin == KIN_SMALL) ? SP_DIV_SMALL : SP_DIV_FINITE;
+  launch_line<T>(LP_CONST, c.kin, nullptr, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, macro_add, nullptr,
+                 c.ncomp, c.st, nullptr, nullptr);
+  launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, nullptr);
+  launch_strided<T>(dm, c.W, out, 0, sx, c.g, c.p1, tb.tw1, -1, dc_out, c.st, nullptr);
+}
+
+// real strain (or H) field of coefficients a (FP64) plus uniform macro part
+static void strain_field(Ctx& c, const void* a, const double* macro_add, double* out, int with_tangent = 0) {
+  Tables<double>& tb = c.td;
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  const int gm = (c.kin == KIN_SMALL) ? SP_GRAD_SMALL : SP_GRAD_FINITE;
+  launch_strided<double>(gm, a, c.W, 0, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, nullptr);
+  TangentArgs<double> tan = elastic_tangent<double>(c);
+  launch_line<double>(with_tangent ? LP_STRESS : LP_C2R, c.kin, c.W, out, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr,
+                      macro_add, nullptr, c.ncomp, c.st, nullptr, nullptr);
+}
+
+// residual i xi_j F[sigma]_ij / N of a real FP64 stress field -> out (FP64, = -K-form), dc
+static void stress_residual(Ctx& c, const double* sig, void* out, double* dc_out) {
+  Tables<double>& tb = c.td;
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  const int dm = (c.kin == KIN_SMALL) ? SP_DIV_SMALL : SP_DIV_FINITE;
+  TangentArgs<double> tan = elastic_tangent<double>(c);
+  launch_line<double>(LP_R2C, c.kin, sig, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, c.ncomp,
+                      c.st, nullptr, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, nullptr);
+  launch_strided<double>(dm, c.W, out, 0, sx, c.g, c.p1, tb.tw1, -1, dc_out, c.st, nullptr);
+  // out holds -i xi_j s_ij; the residual is its negative
+  launch_axpby<double>(out, out, 0.0, -1.0, 6 * c.g.nh, c.st);
+}
+
+static double dot64(Ctx& c, const void* u, const void* v) {
+  const int nb = pcg_block_count(c.g);
+  launch_dot_w(u, v, 0, c.g, c.partB, nb, c.st);
+  launch_reduce(c.partB, nb, 1, c.red_dev, c.st);
+  HIPCK(hipMemcpyAsync(c.red_host, c.red_dev, sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  return c.red_host[0];
+}
+
+static void read_dc(Ctx& c, double dc_st[9]) {
+  HIPCK(hipMemcpyAsync(c.red_host, c.dc_dev, 9 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  for (int i = 0; i < 9; ++i) dc_st[i] = (i < c.ncomp) ? c.red_host[i] : 0.0;
+}
+
+static void set_macro(Ctx& c, const double st9[9]) {
+  double h[9];
+  for (int i = 0; i < 9; ++i) h[i] = st9[i];
+  HIPCK(hipMemcpyAsync(c.mac_dev, h, 9 * sizeof(double), hipMemcpyHostToDevice, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+}
+
+static double frob_stored(int kin, const double t[9]) {
+  double s = 0.0;
+  if (kin == KIN_SMALL) {
+    for (int i = 0; i < 3; ++i) s += t[i] * t[i];
+    for (int i = 3; i < 6; ++i) s += 2.0 * t[i] * t[i];
+  } else {
+    for (int i = 0; i < 9; ++i) s += t[i] * t[i];
+  }
+  return std::sqrt(s);
+}
+
+// ------------------------------------------------------------------ macro basis and preconditioner
+struct MacroSet {
+  int nS = 0;
+  int idx[kMaxMacro];
+  double bst[kMaxMacro][9];  // basis tensors in stored order
+};
+
+static MacroSet macro_set(const Ctx& c, const int mask[9]) {
+  MacroSet m;
+  if (c.kin == KIN_SMALL) {
+    for (int a = 0; a < 6; ++a) {
+      if (mask[kPair[a][0] * 3 + kPair[a][1]]) {
+        double B[9], s[9];
+        mandel_tensor(a, B);
+        rm_to_stored(KIN_SMALL, B, s);
+        m.idx[m.nS] = a;
+        for (int k = 0; k < 9; ++k) m.bst[m.nS][k] = s[k];
+        m.nS++;
+      }
+    }
+  } else {
+    for (int a = 0; a < 9; ++a) {
+      if (mask[a]) {
+        m.idx[m.nS] = a;
+        for (int k = 0; k < 9; ++k) m.bst[m.nS][k] = (k == a) ? 1.0 : 0.0;
+        m.nS++;
+      }
+    }
+  }
+  return m;
+}
+
+// contraction B : t with t in stored order
+static double bdot(int kin, const double B[9], const double t[9]) {
+  double s = 0.0;
+  for (int k = 0; k < 9; ++k) s += B[k] * t[k] * ((kin == KIN_SMALL && k >= 3 && k < 6) ? 2.0 : 1.0);
+  return s;
+}
+
+// mean tangent -> 4th order C[i][j][k][l] (FP64)
+static void mean_tangent(Ctx& c, double C4[81]) {
+  TangentArgs<double> tan = elastic_tangent<double>(c);
+  const int nb = tangent_mean_block_count(c.g);
+  const int nv = tangent_mean_nvals(c.kin);
+  launch_tangent_mean<double>(tan, c.kin, c.g, c.partA, nb, c.st);
+  launch_reduce(c.partA, nb, nv, c.red_dev, c.st);
+  HIPCK(hipMemcpyAsync(c.red_host, c.red_dev, nv * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  const double inv = c.g.inv_nvox;
+  if (c.kin == KIN_SMALL) {
+    double M[6][6];
+    int idx = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a; b < 6; ++b) {
+        M[a][b] = M[b][a] = c.red_host[idx++] * inv;
+      }
+    double B[6][9];
+    for (int a = 0; a < 6; ++a) mandel_tensor(a, B[a]);
+    for (int i = 0; i < 81; ++i) C4[i] = 0.0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) {
+        if (M[a][b] == 0.0) continue;
+        for (int ij = 0; ij < 9; ++ij)
+          for (int kl = 0; kl < 9; ++kl) C4[ij * 9 + kl] += B[a][ij] * M[a][b] * B[b][kl];
+      }
+  } else {
+    for (int i = 0; i < 81; ++i) C4[i] = c.red_host[i] * inv;
+  }
+}
+
+static void build_precond(const Ctx& c, const double C4[81], const MacroSet& ms, PrecondArgs& pa, PcgConst& pc) {
+  // q = (j, l) pairs and m = (i, k) pairs in storage 00 11 22 12 02 01
+  auto C = [&](int i, int j, int k, int l) { return C4[((i * 3 + j) * 3 + k) * 3 + l]; };
+  for (int q = 0; q < 6; ++q) {
+    const int j = kPair[q][0], l = kPair[q][1];
+    for (int m = 0; m < 6; ++m) {
+      const int i = kPair[m][0], k = kPair[m][1];
+      double v = (j == l) ? C(i, j, k, j) : C(i, j, k, l) + C(i, l, k, j);
+      if (i != k) {
+        // symmetric part of A_ik
+        const double v2 = (j == l) ? C(k, j, i, j) : C(k, j, i, l) + C(k, l, i, j);
+        v = 0.5 * (v + v2);
+      }
+      pa.G[q][m] = v;
+    }
+  }
+  pc.nmacro = ms.nS;
+  pc.ncomp = c.ncomp;
+  for (int a = 0; a < kMaxMacro; ++a)
+    for (int k = 0; k < 9; ++k) pc.basis[a][k] = (a < ms.nS) ? ms.bst[a][k] : 0.0;
+  for (int a = 0; a < kMaxMacro; ++a)
+    for (int b = 0; b < kMaxMacro; ++b) pc.Me[a][b] = 0.0;
+  if (ms.nS > 0) {
+    // Cee_ab = B_a : C : B_b (B in row-major)
+    std::vector<double> Cee(ms.nS * ms.nS), inv;
+    for (int a = 0; a < ms.nS; ++a)
+      for (int b = 0; b < ms.nS; ++b) {
+        double Ba[9], Bb[9];
+        stored_to_rm(c.kin, ms.bst[a], Ba);
+        stored_to_rm(c.kin, ms.bst[b], Bb);
+        double s = 0.0;
+        for (int ij = 0; ij < 9; ++ij)
+          for (int kl = 0; kl < 9; ++kl) s += Ba[ij] * C4[ij * 9 + kl] * Bb[kl];
+        Cee[a * ms.nS + b] = s;
+      }
+    if (!small_inverse(Cee, ms.nS, inv)) DB_THROW(DBFFT_EBREAKDOWN, "singular mean stiffness on the stress-controlled set");
+    for (int a = 0; a < ms.nS; ++a)
+      for (int b = 0; b < ms.nS; ++b) pc.Me[a][b] = inv[a * ms.nS + b];
+  }
+}
+
+// ------------------------------------------------------------------ PCG driver
+struct PcgOut {
+  int iters;
+  int status;  // 1 conv, 2 breakdown, 3 cap
+  double eq, ld;
+  double sig[9];
+  double xe[kMaxMacro];
+};
+
+// Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
+template <typename T>
+static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r,
+                      void* p, void* q, const double sig0[9], const double re0[kMaxMacro], int check_every) {
+  const size_t vbytes = 3 * (size_t)c.g.nh * 2 * sizeof(T);
+  HIPCK(hipMemsetAsync(x, 0, vbytes, c.st));
+  PcgScalars& h = *c.sc_host;
+  std::memset(&h, 0, sizeof(h));
+  for (int i = 0; i < 9; ++i) h.sig[i] = sig0[i];
+  for (int a = 0; a < kMaxMacro; ++a) h.re[a] = re0[a];
+  HIPCK(hipMemcpyAsync(c.sc_dev, c.sc_host, sizeof(PcgScalars), hipMemcpyHostToDevice, c.st));
+  const int nb = pcg_block_count(c.g);
+  const int neb = energy_blocks<T>(c);
+  launch_precond_init<T>(p, r, pa, c.g, c.partB, nb, c.st);
+  launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 1, c.st);
+  HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  const double* pmac = reinterpret_cast<const double*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, pmac));
+  const int* stop = reinterpret_cast<const int*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, converged));
+  if (check_every < 1) check_every = 1;
+  while (!c.sc_host->converged) {
+    for (int k = 0; k < check_every; ++k) {
+      apply_K<T>(c, p, q, pmac, nullptr, tan, c.partA, c.dc_dev, stop);
+      launch_pcg_alpha(c.sc_dev, c.partA, neb, c.dc_dev, pc, c.st);
+      launch_pcg_update<T>(x, r, p, q, c.sc_dev, pa, c.g, c.partB, nb, c.st);
+      launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 0, c.st);
+      launch_pcg_pupdate<T>(p, r, c.sc_dev, pa, c.g, nb, c.st);
+    }
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
+    HIPCK(hipStreamSynchronize(c.st));
+  }
+  PcgOut o;
+  o.iters = h.iter;
+  o.status = h.converged;
+  o.eq = h.eq_res;
+  o.ld = h.load_res;
+  for (int i = 0; i < 9; ++i) o.sig[i] = h.sig[i];
+  for (int a = 0; a < kMaxMacro; ++a) o.xe[a] = h.xe[a];
+  return o;
+}
+
+// ------------------------------------------------------------------ linear solve
+struct LinOut {
+  int iters = 0, refine = 0, status = DBFFT_OK;
+  double eq = 0, ld = 0;
+  double sig_st[9] = {0};
+  double e_coef[kMaxMacro] = {0};
+};
+
+static int pcg_status(int s) {
+  if (s == 1) return DBFFT_OK;
+  if (s == 2) return DBFFT_EBREAKDOWN;
+  return DBFFT_ENOTCONV;
+}
+
+// Solves the linear problem with prescribed strain EU (stored) and stress
+// row sbar (over the macro set) into sol_out (FP64 coefficients).
+static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const double sbar[kMaxMacro],
+                           const dbfft_opts& o, double* sol_out) {
+  LinOut out;
+  double C4[81];
+  mean_tangent(c, C4);
+  PrecondArgs pa;
+  PcgConst pc;
+  std::memset(&pc, 0, sizeof(pc));
+  build_precond(c, C4, ms, pa, pc);
+  pc.tol = o.tol;
+  pc.tol_load = o.tol_load;
+  pc.max_iter = o.max_iter;
+  const size_t v64 = 3 * (size_t)c.g.nh * 2 * sizeof(double);
+
+  // right-hand side in FP64: b = -K[0; EU], b_e = sbar - B:<C:EU>
+  TangentArgs<double> tan64 = elastic_tangent<double>(c);
+  set_macro(c, EU);
+  apply_const<double>(c, c.b, c.mac_dev, tan64, c.dc_dev);
+  launch_axpby<double>(c.b, c.b, 0.0, -1.0, 6 * c.g.nh, c.st);
+  double dc0[9];
+  read_dc(c, dc0);
+  double re0[kMaxMacro] = {0};
+  for (int a = 0; a < ms.nS; ++a) re0[a] = sbar[a] - bdot(c.kin, ms.bst[a], dc0);
+
+  if (c.prec == DBFFT_FP64) {
+    HIPCK(hipMemcpyAsync(c.r, c.b, v64, hipMemcpyDeviceToDevice, c.st));
+    PcgOut po = run_pcg<double>(c, tan64, pa, pc, sol_out, c.r, c.p, c.q, dc0, re0, o.check_every);
+    out.iters = po.iters;
+    out.status = pcg_status(po.status);
+    out.eq = po.eq;
+    out.ld = po.ld;
+    for (int i = 0; i < 9; ++i) out.sig_st[i] = po.sig[i];
+    for (int a = 0; a < kMaxMacro; ++a) out.e_coef[a] = po.xe[a];
+    return out;
+  }
+
+  // FP32 inner PCG with FP64 outer corrections (iterative refinement)
+  TangentArgs<float> tan32 = elastic_tangent<float>(c);
+  HIPCK(hipMemsetAsync(sol_out, 0, v64, c.st));
+  double e[kMaxMacro] = {0};
+  double sig[9], re[kMaxMacro];
+  for (int i = 0; i < 9; ++i) sig[i] = dc0[i];
+  for (int a = 0; a < kMaxMacro; ++a) re[a] = re0[a];
+  void* r64 = c.t64;
+  HIPCK(hipMemcpyAsync(r64, c.b, v64, hipMemcpyDeviceToDevice, c.st));
+  for (int it = 0;; ++it) {
+    if (it > 0) {
+      // r64 = b - K64 [x; e]
+      double mt[9] = {0};
+      for (int a = 0; a < ms.nS; ++a)
+        for (int k = 0; k < 9; ++k) mt[k] += e[a] * ms.bst[a][k];
+      set_macro(c, mt);
+      apply_K<double>(c, sol_out, r64, c.mac_dev, nullptr, tan64, c.partA, c.dc_dev, nullptr);
+      launch_axpby<double>(r64, c.b, 1.0, -1.0, 6 * c.g.nh, c.st);
+      double dcx[9];
+      read_dc(c, dcx);
+      for (int i = 0; i < 9; ++i) sig[i] = dc0[i] + dcx[i];
+      for (int a = 0; a < ms.nS; ++a) re[a] = re0[a] - bdot(c.kin, ms.bst[a], dcx);
+    }
+    const double nrm = frob_stored(c.kin, sig);
+    const double ra = std::sqrt(std::max(dot64(c, r64, r64), 0.0));
+    double rl = 0.0;
+    for (int a = 0; a < ms.nS; ++a) rl += re[a] * re[a];
+    rl = std::sqrt(rl);
+    const double eq = nrm > 0 ? ra / nrm : (ra == 0 ? 0.0 : INFINITY);
+    const double ld = nrm > 0 ? rl / nrm : (rl == 0 ? 0.0 : INFINITY);
+    out.eq = eq;
+    out.ld = ld;
+    for (int i = 0; i < 9; ++i) out.sig_st[i] = sig[i];
+    for (int a = 0; a < kMaxMacro; ++a) out.e_coef[a] = e[a];
+    if (eq < o.tol && ld < o.tol_load) {
+      out.status = DBFFT_OK;
+      break;
+    }
+    if (it >= o.max_refine) {
+      out.status = DBFFT_ENOTCONV;
+      break;
+    }
+    PcgConst pci = pc;
+    pci.tol = std::max(eq * o.inner_tol, 0.5 * o.tol);
+    pci.tol_load = std::max(ld * o.inner_tol, 0.5 * o.tol_load);
+    pci.max_iter = std::max(1, o.max_iter - out.iters);
+    launch_convert<double, float>(c.r, r64, 6 * c.g.nh, c.st);
+    PcgOut po = run_pcg<float>(c, tan32, pa, pci, c.x, c.r, c.p, c.q, sig, re, o.check_every);
+    out.iters += po.iters;
+    out.refine += 1;
+    if (po.status == 2) {
+      out.status = DBFFT_EBREAKDOWN;
+      break;
+    }
+    // sol += delta
+    launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
+    launch_axpby<double>(sol_out, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
+    for (int a = 0; a < ms.nS; ++a) e[a] += po.xe[a];
+    if (out.iters >= o.max_iter) {
+      out.status = DBFFT_ENOTCONV;
+      // one more residual evaluation happens at the loop top
+    }
+  }
+  return out;
+}
+
+// true residuals and <sigma> of coefficients sol (FP64) with macro total mt (stored)
+static void evaluate_linear(Ctx& c, const double* sol, const double mt[9], const MacroSet& ms,
+                            const double sbar[kMaxMacro], double sig_st[9], double& eq, double& ld) {
+  TangentArgs<double> tan64 = elastic_tangent<double>(c);
+  set_macro(c, mt);
+  apply_K<double>(c, sol, c.t64, c.mac_dev, nullptr, tan64, c.partA, c.dc_dev, nullptr);
+  read_dc(c, sig_st);
+  const double ra = std::sqrt(std::max(dot64(c, c.t64, c.t64), 0.0));
+  double rl = 0.0;
+  for (int a = 0; a < ms.nS; ++a) {
+    const double d = sbar[a] - bdot(c.kin, ms.bst[a], sig_st);
+    rl += d * d;
+  }
+  rl = std::sqrt(rl);
+  const double nrm = frob_stored(c.kin, sig_st);
+  eq = nrm > 0 ? ra / nrm : 0.0;
+  ld = nrm > 0 ? rl / nrm : 0.0;
+}
+
+// ------------------------------------------------------------------ Newton
+static void material_update(Ctx& c, const double* fld, double* sig_out, double dt) {
+  HIPCK(hipMemsetAsync(c.fail_dev, 0, sizeof(int), c.st));
+  if (c.mat == DBFFT_MAT_J2VP_CUBIC) {
+    launch_j2_update(fld, c.state, c.grain, c.grainC, c.grainS, c.j2_s0, c.j2_m, c.j2_edot0, dt, c.g.nvox, sig_out,
+                     c.tanf, c.state_new, c.fail_dev, c.st);
+  } else {
+    NeoParams np;
+    for (int i = 0; i < kMaxPhases; ++i) {
+      np.mu[i] = c.mu[i];
+      np.lam[i] = c.lam[i];
+    }
+    launch_neo_update(fld, c.phase, np, c.g.nvox, sig_out, c.tanf, c.fail_dev, c.st);
+  }
+  int fail = 0;
+  HIPCK(hipMemcpyAsync(&fail, c.fail_dev, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  if (fail) DB_THROW(DBFFT_EMATERIAL, "constitutive update failed (local Newton or J <= 0)");
+  c.tangent_from_field = 1;
+  if (c.prec == DBFFT_FP32_MIXED) {
+    const int nt = (c.mat == DBFFT_MAT_J2VP_CUBIC) ? 21 : 10;
+    launch_convert<double, float>(c.tanf32, c.tanf, (long long)nt * c.g.nvox, c.st);
+  }
+}
+
+static double max_abs_diff(Ctx& c, const double* a, const double* b, long long n) {
+  const int nb = 512;
+  launch_max_abs_diff(a, b, n, c.partA, nb, c.st);
+  std::vector<double> h(nb);
+  HIPCK(hipMemcpyAsync(h.data(), c.partA, nb * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  return m;
+}
+
+static int newton_solve(Ctx& c, const double load_rm[9], const int mask[9], int ninc, double dt,
+                        const dbfft_opts& o, dbfft_info& info) {
+  const MacroSet ms = macro_set(c, mask);
+  const size_t v64 = 3 * (size_t)c.g.nh * 2 * sizeof(double);
+  const long long nf = (long long)c.ncomp * c.g.nvox;
+  double e[kMaxMacro] = {0};
+  HIPCK(hipMemsetAsync(c.sol, 0, v64, c.st));
+  if (c.mat == DBFFT_MAT_J2VP_CUBIC) HIPCK(hipMemsetAsync(c.state, 0, 6 * c.g.nvox * sizeof(double), c.st));
+  PrecondArgs pa;
+  PcgConst pc;
+  std::memset(&pc, 0, sizeof(pc));
+  bool have_pre = false;
+  int status = DBFFT_OK;
+  info.pcg_iters = info.newton_iters = info.increments = info.refine_steps = 0;
+  double sig_st[9] = {0}, EU[9] = {0};
+  for (int k = 1; k <= ninc && status == DBFFT_OK; ++k) {
+    const double frac = (double)k / (double)ninc;
+    double lrm[9], U_rm[9];
+    for (int i = 0; i < 9; ++i) {
+      double v = load_rm[i];
+      if (c.kin == KIN_FINITE && !mask[i] && (i % 4 == 0)) v -= 1.0;  // F - I
+      lrm[i] = frac * v;
+      U_rm[i] = mask[i] ? 0.0 : lrm[i];
+    }
+    rm_to_stored(c.kin, U_rm, EU);
+    double sbar[kMaxMacro] = {0};
+    double lst[9];
+    rm_to_stored(c.kin, lrm, lst);
+    for (int a = 0; a < ms.nS; ++a) sbar[a] = bdot(c.kin, ms.bst[a], lst);
+    auto macro_total = [&](double mt[9]) {
+      for (int i = 0; i < 9; ++i) mt[i] = EU[i];
+      for (int a = 0; a < ms.nS; ++a)
+        for (int i = 0; i < 9; ++i) mt[i] += e[a] * ms.bst[a][i];
+    };
+    double mt[9];
+    macro_total(mt);
+    set_macro(c, mt);
+    strain_field(c, c.sol, c.mac_dev, c.fa);
+    double dmax = INFINITY;
+    bool conv = false;
+    for (int i = 0;; ++i) {
+      material_update(c, c.fa, c.fc, dt);
+      if (!have_pre || (i == 0 && o.refresh == 0)) {
+        double C4[81];
+        mean_tangent(c, C4);
+        build_precond(c, C4, ms, pa, pc);
+        have_pre = true;
+      }
+      stress_residual(c, c.fc, c.t64, c.dc_dev);
+      read_dc(c, sig_st);
+      double re[kMaxMacro] = {0};
+      for (int a = 0; a < ms.nS; ++a) re[a] = sbar[a] - bdot(c.kin, ms.bst[a], sig_st);
+      if (i > 0 && dmax < o.newton_tol) {
+        conv = true;
+        break;
+      }
+      if (i >= o.max_newton) break;
+      pc.tol = o.tol;
+      pc.tol_load = o.tol_load;
+      pc.max_iter = o.max_iter;
+      PcgOut po;
+      if (c.prec == DBFFT_FP64) {
+        HIPCK(hipMemcpyAsync(c.r, c.t64, v64, hipMemcpyDeviceToDevice, c.st));
+        TangentArgs<double> tan = elastic_tangent<double>(c);
+        po = run_pcg<double>(c, tan, pa, pc, c.x, c.r, c.p, c.q, sig_st, re, o.check_every);
+        launch_axpby<double>(c.sol, c.x, 1.0, 1.0, 6 * c.g.nh, c.st);
+      } else {
+        launch_convert<double, float>(c.r, c.t64, 6 * c.g.nh, c.st);
+        TangentArgs<float> tan = elastic_tangent<float>(c);
+        po = run_pcg<float>(c, tan, pa, pc, c.x, c.r, c.p, c.q, sig_st, re, o.check_every);
+        launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
+        launch_axpby<double>(c.sol, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
+      }
+      info.pcg_iters += po.iters;
+      info.newton_iters += 1;
+      if (po.status == 2) {
+        status = DBFFT_EBREAKDOWN;
+        break;
+      }
+      if (po.status == 3) {
+        status = DBFFT_ENOTCONV;
+        break;
+      }
+      for (int a = 0; a < ms.nS; ++a) e[a] += po.xe[a];
+      macro_total(mt);
+      set_macro(c, mt);
+      std::swap(c.fa, c.fb);
+      strain_field(c, c.sol, c.mac_dev, c.fa);
+      dmax = max_abs_diff(c, c.fa, c.fb, nf);
+    }
+    if (status != DBFFT_OK) break;
+    if (!conv) {
+      status = DBFFT_ENOTCONV;
+      break;
+    }
+    if (c.mat == DBFFT_MAT_J2VP_CUBIC) std::swap(c.state, c.state_new);
+    info.increments += 1;
+  }
+  // final state: residuals and averages
+  const double ra = std::sqrt(std::max(dot64(c, c.t64, c.t64), 0.0));
+  const double nrm = frob_stored(c.kin, sig_st);
+  info.eq_res = nrm > 0 ? ra / nrm : 0.0;
+  double rl = 0.0;
+  {
+    double lrm[9], lst[9];
+    const double frac = (double)std::max(info.increments, 1) / (double)ninc;
+    for (int i = 0; i < 9; ++i) lrm[i] = frac * load_rm[i];
+    rm_to_stored(c.kin, lrm, lst);
+    for (int a = 0; a < ms.nS; ++a) {
+      const double d = bdot(c.kin, ms.bst[a], lst) - bdot(c.kin, ms.bst[a], sig_st);
+      rl += d * d;
+    }
+  }
+  info.load_res = nrm > 0 ? std::sqrt(rl) / nrm : 0.0;
+  double et[9];
+  for (int i = 0; i < 9; ++i) et[i] = 0.0;
+  for (int a = 0; a < ms.nS; ++a)
+    for (int i = 0; i < 9; ++i) et[i] += e[a] * ms.bst[a][i];
+  for (int i = 0; i < 9; ++i) c.e_st[i] = et[i];
+  for (int i = 0; i < 9; ++i) c.EU_st[i] = EU[i];
+  double avg_st[9];
+  for (int i = 0; i < 9; ++i) avg_st[i] = EU[i] + et[i];
+  stored_to_rm(c.kin, sig_st, c.sig_rm);
+  stored_to_rm(c.kin, avg_st, c.eps_rm);
+  if (c.kin == KIN_FINITE)
+    for (int i = 0; i < 9; i += 4) c.eps_rm[i] += 1.0;  // <F> = I + <H>
+  for (int i = 0; i < 9; ++i) {
+    info.sigma_bar[i] = c.sig_rm[i];
+    info.eps_bar[i] = c.eps_rm[i];
+  }
+  return status;
+}
+
+// ------------------------------------------------------------------ setup
+static bool smooth(long long n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+static void release(Ctx* c) {
+  (void)hipStreamSynchronize(c->st);
+  void* dev[] = {c->td.tw1, c->td.tw2, c->td.tw3, c->td.rtw, c->tf.tw1, c->tf.tw2, c->tf.tw3, c->tf.rtw,
+                 c->phase, c->E64, c->E32, c->grain, c->grain21, c->grainC, c->grainS, c->W, c->x, c->r, c->p,
+                 c->q, c->b, c->t64, c->sol, c->sol2, c->fa, c->fb, c->fc, c->state, c->state_new, c->tanf,
+                 c->tanf32, c->partA, c->partB, c->sc_dev, c->dc_dev, c->mac_dev, c->red_dev, c->fail_dev};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (c->sc_host) (void)hipHostFree(c->sc_host);
+  if (c->red_host) (void)hipHostFree(c->red_host);
+}
+
+static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const void* field, const double* params,
+                  int nparams, void* stream) {
+  if (!n) DB_THROW(DBFFT_EINVAL, "null grid size");
+  for (int a = 0; a < 3; ++a)
+    if (n[a] < 1 || n[a] > 4096 || !smooth(n[a])) DB_THROW(DBFFT_EINVAL, "grid sizes must be 2^a 3^b 5^c");
+  if (n[2] % 2 != 0) DB_THROW(DBFFT_EINVAL, "n3 must be even");
+  {
+    // the x/y passes keep one line (plus twiddles) of every tile column in
+    // LDS, the z pass one z line of every component: both within 64 KiB
+    const int nc = (kin == DBFFT_FINITE) ? 9 : 6;
+    for (int a = 0; a < 2; ++a)
+      if ((size_t)3 * n[a] * 16 > 64 * 1024) DB_THROW(DBFFT_EUNSUPPORTED, "n1 and n2 must be <= 1365");
+    const size_t M = (size_t)n[2] / 2;
+    if ((2 * M + 1) * 16 + 2 * M * 16 + (M + 1) * 16 + (size_t)nc * n[2] * 8 > 64 * 1024)
+      DB_THROW(DBFFT_EUNSUPPORTED, "n3 too large for the z pass");
+  }
+  if (kin != DBFFT_SMALL && kin != DBFFT_FINITE) DB_THROW(DBFFT_EINVAL, "unknown kinematics");
+  if (prec != DBFFT_FP64 && prec != DBFFT_FP32_MIXED) DB_THROW(DBFFT_EINVAL, "unknown precision");
+  if (mat < 0 || mat > DBFFT_MAT_NEOHOOKE) DB_THROW(DBFFT_EINVAL, "unknown material kind");
+  if ((mat == DBFFT_MAT_NEOHOOKE) != (kin == DBFFT_FINITE))
+    DB_THROW(DBFFT_EINVAL, "NEOHOOKE needs FINITE kinematics and every other material SMALL");
+  if (!field) DB_THROW(DBFFT_EINVAL, "null material field");
+  if (!params || nparams < 1) DB_THROW(DBFFT_EINVAL, "null material parameters");
+
+  {
+    for (int a = 0; a < 3; ++a) c->n[a] = (int)n[a];
+    c->kin = kin;
+    c->prec = prec;
+    c->mat = mat;
+    c->ncomp = (kin == DBFFT_SMALL) ? 6 : 9;
+    c->st = static_cast<hipStream_t>(stream);
+    Geom& g = c->g;
+    g.n1 = c->n[0];
+    g.n2 = c->n[1];
+    g.n3 = c->n[2];
+    g.nh3 = g.n3 / 2 + 1;
+    g.nh = (long long)g.n1 * g.n2 * g.nh3;
+    g.nvox = (long long)g.n1 * g.n2 * g.n3;
+    g.inv_nvox = 1.0 / (double)g.nvox;
+    if (!make_plan(g.n1, c->p1) || !make_plan(g.n2, c->p2) || !make_plan(g.n3 / 2, c->p3))
+      DB_THROW(DBFFT_EINVAL, "cannot plan the transform lengths");
+    std::vector<double> re, im;
+    twiddles(g.n1, g.n1, g.n1, re, im);
+    c->td.tw1 = upload_table<double>(re, im);
+    c->tf.tw1 = upload_table<float>(re, im);
+    twiddles(g.n2, g.n2, g.n2, re, im);
+    c->td.tw2 = upload_table<double>(re, im);
+    c->tf.tw2 = upload_table<float>(re, im);
+    const int M = g.n3 / 2;
+    twiddles(M, M, std::max(M, 1), re, im);
+    c->td.tw3 = upload_table<double>(re, im);
+    c->tf.tw3 = upload_table<float>(re, im);
+    twiddles(g.n3, g.n3, M + 1, re, im);
+    c->td.rtw = upload_table<double>(re, im);
+    c->tf.rtw = upload_table<float>(re, im);
+
+    const long long N = g.nvox;
+    // material
+    if (mat == DBFFT_MAT_ISO_PHASE || mat == DBFFT_MAT_NEOHOOKE) {
+      if (nparams % 2 != 0 || nparams / 2 > kMaxPhases) DB_THROW(DBFFT_EINVAL, "phase parameters: pairs, at most 8 phases");
+      c->nphase = nparams / 2;
+      for (int p = 0; p < c->nphase; ++p) {
+        const double a = params[2 * p], b = params[2 * p + 1];
+        if (mat == DBFFT_MAT_ISO_PHASE) {
+          c->lam[p] = a * b / ((1.0 + b) * (1.0 - 2.0 * b));
+          c->mu[p] = a / (2.0 * (1.0 + b));
+        } else {
+          c->mu[p] = a;
+          c->lam[p] = b - 2.0 * a / 3.0;
+        }
+      }
+      std::vector<uint8_t> hp(N);
+      HIPCK(hipMemcpy(hp.data(), field, N, hipMemcpyDeviceToHost));
+      for (long long v = 0; v < N; ++v)
+        if (hp[v] >= c->nphase) DB_THROW(DBFFT_EINVAL, "phase id out of range");
+      c->phase = static_cast<uint8_t*>(dalloc(N));
+      HIPCK(hipMemcpy(c->phase, field, N, hipMemcpyDeviceToDevice));
+    } else if (mat == DBFFT_MAT_ISO_FIELD) {
+      c->nu = params[0];
+      c->lam1 = c->nu / ((1.0 + c->nu) * (1.0 - 2.0 * c->nu));
+      c->mu1 = 1.0 / (2.0 * (1.0 + c->nu));
+      c->E64 = static_cast<double*>(dalloc(N * sizeof(double)));
+      HIPCK(hipMemcpy(c->E64, field, N * sizeof(double), hipMemcpyDeviceToDevice));
+      c->E32 = static_cast<float*>(dalloc(N * sizeof(float)));
+      launch_convert<double, float>(c->E32, c->E64, N, c->st);
+    } else {
+      // grain based
+      std::vector<int32_t> hg(N);
+      HIPCK(hipMemcpy(hg.data(), field, N * sizeof(int32_t), hipMemcpyDeviceToHost));
+      int gmax = -1;
+      for (long long v = 0; v < N; ++v) {
+        if (hg[v] < 0) DB_THROW(DBFFT_EINVAL, "negative grain id");
+        gmax = std::max(gmax, (int)hg[v]);
+      }
+      std::vector<double> C36;
+      if (mat == DBFFT_MAT_ANISO_GRAIN) {
+        c->ngrain = nparams / 36;
+        if (c->ngrain * 36 != nparams || c->ngrain <= gmax) DB_THROW(DBFFT_EINVAL, "ANISO_GRAIN needs 36 values per grain id");
+        C36.assign(params, params + nparams);
+      } else {
+        if (nparams < 6 || (nparams - 6) % 9 != 0) DB_THROW(DBFFT_EINVAL, "J2VP_CUBIC parameters: 6 + 9 per grain");
+        c->ngrain = (nparams - 6) / 9;
+        if (c->ngrain <= gmax) DB_THROW(DBFFT_EINVAL, "grain id without rotation");
+        const double c11 = params[0], c12 = params[1], c44 = params[2];
+        c->j2_s0 = params[3];
+        c->j2_m = params[4];
+        c->j2_edot0 = params[5];
+        double Cc[81] = {0};
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            if (i == j) Cc[((i * 3 + i) * 3 + i) * 3 + i] = c11;
+            else {
+              Cc[((i * 3 + i) * 3 + j) * 3 + j] = c12;
+              Cc[((i * 3 + j) * 3 + i) * 3 + j] = c44;
+              Cc[((i * 3 + j) * 3 + j) * 3 + i] = c44;
+            }
+          }
+        C36.assign((size_t)c->ngrain * 36, 0.0);
+        double B[6][9];
+        for (int a = 0; a < 6; ++a) mandel_tensor(a, B[a]);
+        for (int gi = 0; gi < c->ngrain; ++gi) {
+          const double* R = params + 6 + 9 * gi;
+          // C'_ijkl = R_ia R_jb R_kc R_ld C_abcd, then Mandel B_a : C' : B_b
+          std::vector<double> Cr(81, 0.0);
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) {
+                  double s = 0.0;
+                  for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                      for (int cc = 0; cc < 3; ++cc)
+                        for (int d = 0; d < 3; ++d) {
+                          const double cv = Cc[((a * 3 + b) * 3 + cc) * 3 + d];
+                          if (cv != 0.0) s += R[i * 3 + a] * R[j * 3 + b] * R[k * 3 + cc] * R[l * 3 + d] * cv;
+                        }
+                  Cr[((i * 3 + j) * 3 + k) * 3 + l] = s;
+                }
+          for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+              double s = 0.0;
+              for (int ij = 0; ij < 9; ++ij)
+                for (int kl = 0; kl < 9; ++kl) s += B[a][ij] * Cr[ij * 9 + kl] * B[b][kl];
+              C36[(size_t)gi * 36 + a * 6 + b] = s;
+            }
+        }
+      }
+      std::vector<double> t21((size_t)c->ngrain * 21), S36((size_t)c->ngrain * 36);
+      for (int gi = 0; gi < c->ngrain; ++gi) {
+        int idx = 0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = a; b < 6; ++b)
+            t21[(size_t)gi * 21 + idx++] = 0.5 * (C36[(size_t)gi * 36 + a * 6 + b] + C36[(size_t)gi * 36 + b * 6 + a]);
+        std::vector<double> A(C36.begin() + (size_t)gi * 36, C36.begin() + (size_t)gi * 36 + 36), X;
+        if (!small_inverse(A, 6, X)) DB_THROW(DBFFT_EINVAL, "singular grain stiffness");
+        for (int i = 0; i < 36; ++i) S36[(size_t)gi * 36 + i] = X[i];
+      }
+      c->grain = static_cast<int32_t*>(dalloc(N * sizeof(int32_t)));
+      HIPCK(hipMemcpy(c->grain, field, N * sizeof(int32_t), hipMemcpyDeviceToDevice));
+      c->grain21 = static_cast<double*>(dalloc(t21.size() * sizeof(double)));
+      HIPCK(hipMemcpy(c->grain21, t21.data(), t21.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->grainC = static_cast<double*>(dalloc(C36.size() * sizeof(double)));
+      HIPCK(hipMemcpy(c->grainC, C36.data(), C36.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->grainS = static_cast<double*>(dalloc(S36.size() * sizeof(double)));
+      HIPCK(hipMemcpy(c->grainS, S36.data(), S36.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+
+    // workspaces
+    const size_t vb = 3 * (size_t)g.nh * 2 * sizeof(double);
+    c->W = dalloc((size_t)c->ncomp * g.nh * 2 * sizeof(double));
+    c->x = dalloc(vb);
+    c->r = dalloc(vb);
+    c->p = dalloc(vb);
+    c->q = dalloc(vb);
+    c->b = dalloc(vb);
+    c->t64 = dalloc(vb);
+    c->sol = static_cast<double*>(dalloc(vb));
+    HIPCK(hipMemset(c->sol, 0, vb));
+    const size_t fbytes = (size_t)c->ncomp * N * sizeof(double);
+    c->fa = static_cast<double*>(dalloc(fbytes));
+    c->fb = static_cast<double*>(dalloc(fbytes));
+    c->fc = static_cast<double*>(dalloc(fbytes));
+    if (mat == DBFFT_MAT_J2VP_CUBIC) {
+      c->state = static_cast<double*>(dalloc(6 * N * sizeof(double)));
+      c->state_new = static_cast<double*>(dalloc(6 * N * sizeof(double)));
+      HIPCK(hipMemset(c->state, 0, 6 * N * sizeof(double)));
+      c->tanf = static_cast<double*>(dalloc(21 * N * sizeof(double)));
+      c->tanf32 = static_cast<float*>(dalloc(21 * N * sizeof(float)));
+    } else if (mat == DBFFT_MAT_NEOHOOKE) {
+      c->tanf = static_cast<double*>(dalloc(10 * N * sizeof(double)));
+      c->tanf32 = static_cast<float*>(dalloc(10 * N * sizeof(float)));
+      // reference configuration: F^-1 = I, ln J = 0
+      std::vector<double> h(10 * N, 0.0);
+      for (long long v = 0; v < N; ++v) h[0 * N + v] = h[4 * N + v] = h[8 * N + v] = 1.0;
+      HIPCK(hipMemcpy(c->tanf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      launch_convert<double, float>(c->tanf32, c->tanf, 10 * N, c->st);
+    }
+    const int nparts = std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
+                                tangent_mean_block_count(g) * 81) + 64;
+    c->npart = nparts;
+    c->partA = static_cast<double*>(dalloc(nparts * sizeof(double)));
+    c->partB = static_cast<double*>(dalloc(nparts * sizeof(double)));
+    c->sc_dev = static_cast<PcgScalars*>(dalloc(sizeof(PcgScalars)));
+    HIPCK(hipHostMalloc((void**)&c->sc_host, sizeof(PcgScalars), hipHostMallocDefault));
+    c->dc_dev = static_cast<double*>(dalloc(16 * sizeof(double)));
+    HIPCK(hipMemset(c->dc_dev, 0, 16 * sizeof(double)));
+    c->mac_dev = static_cast<double*>(dalloc(16 * sizeof(double)));
+    HIPCK(hipMemset(c->mac_dev, 0, 16 * sizeof(double)));
+    c->red_dev = static_cast<double*>(dalloc(128 * sizeof(double)));
+    HIPCK(hipHostMalloc((void**)&c->red_host, 128 * sizeof(double), hipHostMallocDefault));
+    c->fail_dev = static_cast<int*>(dalloc(sizeof(int)));
+    HIPCK(hipStreamSynchronize(c->st));
+  }
+}
+
+}  // namespace dbfft
+
+using namespace dbfft;
+
+struct dbfft_ctx {
+  Ctx impl;
+};
+
+static Ctx* C(dbfft_ctx* c) { return &c->impl; }
+
+#define API_BEGIN try {
+#define API_END                                       \
+  }                                                   \
+  catch (const Err& e) {                              \
+    return (dbfft_status)e.code;                      \
+  }                                                   \
+  catch (...) {                                       \
+    g_err = "unexpected C++ exception";               \
+    return DBFFT_EHIP;                                \
+  }
+
+extern "C" {
+
+void dbfft_default_opts(dbfft_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->tol_load = 1e-10;
+  o->max_iter = 10000;
+  o->newton_tol = 1e-6;
+  o->max_newton = 25;
+  o->refresh = 0;
+  o->inner_tol = 1e-4;
+  o->max_refine = 30;
+  o->check_every = 8;
+}
+
+const char* dbfft_last_error(void) { return g_err.c_str(); }
+
+dbfft_status dbfft_setup(dbfft_ctx** out, const int64_t n[3], int32_t kinematics, int32_t precision, int32_t material,
+                         const void* field_dev, const double* params, int32_t nparams, void* hip_stream) {
+  g_err.clear();
+  API_BEGIN
+  if (!out) DB_THROW(DBFFT_EINVAL, "null output pointer");
+  *out = nullptr;
+  dbfft_ctx* h = new dbfft_ctx();
+  try {
+    setup(&h->impl, n, kinematics, precision, material, field_dev, params, nparams, hip_stream);
+  } catch (...) {
+    release(&h->impl);
+    delete h;
+    throw;
+  }
+  *out = h;
+  return DBFFT_OK;
+  API_END
+}
+
+void dbfft_destroy(dbfft_ctx* ctx) {
+  if (!ctx) return;
+  release(&ctx->impl);
+  delete ctx;
+}
+
+dbfft_status dbfft_apply(dbfft_ctx* ctx, const double* u_dev, double* f_dev) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !u_dev || !f_dev) DB_THROW(DBFFT_EINVAL, "null argument");
+  Ctx& c = *C(ctx);
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  const long long N = c.g.nvox;
+  double zero[9] = {0};
+  set_macro(c, zero);
+  if (c.prec == DBFFT_FP64) {
+    Tables<double>& tb = c.td;
+    TangentArgs<double> tan = elastic_tangent<double>(c);
+    launch_line<double>(LP_R2C, c.kin, u_dev, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3,
+                        c.st, nullptr, nullptr);
+    launch_strided<double>(SP_PLAIN, c.W, c.W, 3, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, nullptr);
+    launch_strided<double>(SP_PLAIN, c.W, c.p, 3, sx, c.g, c.p1, tb.tw1, -1, nullptr, c.st, nullptr);
+    apply_K<double>(c, c.p, c.q, c.mac_dev, nullptr, tan, c.partA, c.dc_dev, nullptr);
+    launch_strided<double>(SP_PLAIN, c.q, c.W, 3, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, nullptr);
+    launch_strided<double>(SP_PLAIN, c.W, c.W, 3, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, nullptr);
+    launch_line<double>(LP_C2R, c.kin, c.W, f_dev, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3,
+                        c.st, nullptr, nullptr);
+  } else {
+    Tables<float>& tb = c.tf;
+    TangentArgs<float> tan = elastic_tangent<float>(c);
+    float* u32 = reinterpret_cast<float*>(c.fa);
+    launch_convert<double, float>(u32, u_dev, 3 * N, c.st);
+    launch_line<float>(LP_R2C, c.kin, u32, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3, c.st,
+                       nullptr, nullptr);
+    launch_strided<float>(SP_PLAIN, c.W, c.W, 3, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, nullptr);
+    launch_strided<float>(SP_PLAIN, c.W, c.p, 3, sx, c.g, c.p1, tb.tw1, -1, nullptr, c.st, nullptr);
+    apply_K<float>(c, c.p, c.q, c.mac_dev, nullptr, tan, c.partA, c.dc_dev, nullptr);
+    launch_strided<float>(SP_PLAIN, c.q, c.W, 3, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, nullptr);
+    launch_strided<float>(SP_PLAIN, c.W, c.W, 3, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, nullptr);
+    launch_line<float>(LP_C2R, c.kin, c.W, u32, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3, c.st,
+                       nullptr, nullptr);
+    launch_convert<float, double>(f_dev, u32, 3 * N, c.st);
+  }
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(c.st));
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_apply_fourier(dbfft_ctx* ctx, const void* a_dev, const double* e_macro, void* f_dev,
+                                 double* sigma_bar_out) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !a_dev || !f_dev) DB_THROW(DBFFT_EINVAL, "null argument");
+  Ctx& c = *C(ctx);
+  double st[9] = {0};
+  if (e_macro) rm_to_stored(c.kin, e_macro, st);
+  set_macro(c, st);
+  const long long n2 = 6 * c.g.nh;
+  if (c.prec == DBFFT_FP64) {
+    TangentArgs<double> tan = elastic_tangent<double>(c);
+    apply_K<double>(c, a_dev, f_dev, c.mac_dev, nullptr, tan, c.partA, c.dc_dev, nullptr);
+  } else {
+    TangentArgs<float> tan = elastic_tangent<float>(c);
+    launch_convert<double, float>(c.p, a_dev, n2, c.st);
+    apply_K<float>(c, c.p, c.q, c.mac_dev, nullptr, tan, c.partA, c.dc_dev, nullptr);
+    launch_convert<float, double>(f_dev, c.q, n2, c.st);
+  }
+  HIPCK(hipGetLastError());
+  double dc[9];
+  read_dc(c, dc);
+  if (sigma_bar_out) stored_to_rm(c.kin, dc, sigma_bar_out);
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t stress_mask[9], int32_t n_increments,
+                         double dt, const dbfft_opts* opts, dbfft_info* info) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !load || !stress_mask) DB_THROW(DBFFT_EINVAL, "null argument");
+  Ctx& c = *C(ctx);
+  dbfft_opts o;
+  if (opts) o = *opts;
+  else dbfft_default_opts(&o);
+  int mask[9];
+  for (int i = 0; i < 9; ++i) mask[i] = stress_mask[i] ? 1 : 0;
+  if (c.kin == KIN_SMALL) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        if (mask[i * 3 + j] != mask[j * 3 + i]) DB_THROW(DBFFT_EINVAL, "small strains need a symmetric stress mask");
+        if (load[i * 3 + j] != load[j * 3 + i]) DB_THROW(DBFFT_EINVAL, "small strains need a symmetric load");
+      }
+  }
+  dbfft_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  for (int i = 0; i < 9; ++i) c.last_mask[i] = mask[i];
+  int status;
+  if (c.linear_material()) {
+    const MacroSet ms = macro_set(c, mask);
+    double U_rm[9], lst[9];
+    for (int i = 0; i < 9; ++i) U_rm[i] = mask[i] ? 0.0 : load[i];
+    rm_to_stored(c.kin, U_rm, c.EU_st);
+    rm_to_stored(c.kin, load, lst);
+    double sbar[kMaxMacro] = {0};
+    for (int a = 0; a < ms.nS; ++a) sbar[a] = bdot(c.kin, ms.bst[a], lst);
+    LinOut lo = linear_solve(c, c.EU_st, ms, sbar, o, c.sol);
+    status = lo.status;
+    for (int i = 0; i < 9; ++i) c.e_st[i] = 0.0;
+    for (int a = 0; a < ms.nS; ++a)
+      for (int i = 0; i < 9; ++i) c.e_st[i] += lo.e_coef[a] * ms.bst[a][i];
+    double mt[9], sig_st[9], eq, ld;
+    for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+    evaluate_linear(c, c.sol, mt, ms, sbar, sig_st, eq, ld);
+    stored_to_rm(c.kin, sig_st, c.sig_rm);
+    stored_to_rm(c.kin, mt, c.eps_rm);
+    inf.pcg_iters = lo.iters;
+    inf.refine_steps = lo.refine;
+    inf.increments = 1;
+    inf.eq_res = eq;
+    inf.load_res = ld;
+    for (int i = 0; i < 9; ++i) {
+      inf.sigma_bar[i] = c.sig_rm[i];
+      inf.eps_bar[i] = c.eps_rm[i];
+    }
+  } else {
+    if (n_increments < 1) DB_THROW(DBFFT_EINVAL, "n_increments must be >= 1");
+    if (c.mat == DBFFT_MAT_J2VP_CUBIC && !(dt > 0.0)) DB_THROW(DBFFT_EINVAL, "dt must be > 0 for J2VP_CUBIC");
+    status = newton_solve(c, load, mask, n_increments, dt, o, inf);
+  }
+  inf.status = status;
+  c.solved = true;
+  if (info) *info = inf;
+  if (status != DBFFT_OK && g_err.empty())
+    g_err = status == DBFFT_ENOTCONV ? "iteration cap reached" : "breakdown: <p, K p> <= 0 or NaN";
+  return (dbfft_status)status;
+  API_END
+}
+
+dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_bar[9], double* strain_dev,
+                              double* stress_dev, double* disp_dev) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx) DB_THROW(DBFFT_EINVAL, "null context");
+  Ctx& c = *C(ctx);
+  if (!c.solved) DB_THROW(DBFFT_EINVAL, "no solution yet");
+  if (sigma_bar)
+    for (int i = 0; i < 9; ++i) sigma_bar[i] = c.sig_rm[i];
+  if (eps_bar)
+    for (int i = 0; i < 9; ++i) eps_bar[i] = c.eps_rm[i];
+  double mt[9];
+  for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+  if (strain_dev) {
+    set_macro(c, mt);
+    strain_field(c, c.sol, c.mac_dev, strain_dev);
+  }
+  if (stress_dev) {
+    if (c.linear_material()) {
+      set_macro(c, mt);
+      strain_field(c, c.sol, c.mac_dev, stress_dev, 1);
+    } else {
+      HIPCK(hipMemcpyAsync(stress_dev, c.fc, (size_t)c.ncomp * c.g.nvox * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+    }
+  }
+  if (disp_dev) {
+    const StridedGeom sx = xgeom(c), sy = ygeom(c);
+    Tables<double>& tb = c.td;
+    TangentArgs<double> tan = elastic_tangent<double>(c);
+    launch_strided<double>(SP_PLAIN, c.sol, c.W, 3, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, nullptr);
+    launch_strided<double>(SP_PLAIN, c.W, c.W, 3, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, nullptr);
+    launch_line<double>(LP_C2R, c.kin, c.W, disp_dev, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3,
+                        c.st, nullptr, nullptr);
+  }
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(c.st));
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx) DB_THROW(DBFFT_EINVAL, "null context");
+  Ctx& c = *C(ctx);
+  if (!c.solved) DB_THROW(DBFFT_EINVAL, "no solution yet");
+  if (a_dev)
+    HIPCK(hipMemcpyAsync(a_dev, c.sol, 3 * (size_t)c.g.nh * 2 * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+  if (e_macro) stored_to_rm(c.kin, c.e_st, e_macro);
+  HIPCK(hipStreamSynchronize(c.st));
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !G || !H || !grad_dev) DB_THROW(DBFFT_EINVAL, "null argument");
+  Ctx& c = *C(ctx);
+  if (c.mat != DBFFT_MAT_ISO_FIELD || c.kin != KIN_SMALL)
+    DB_THROW(DBFFT_EUNSUPPORTED, "the adjoint handles ISO_FIELD materials under small strains");
+  if (!c.solved) DB_THROW(DBFFT_EINVAL, "no forward solution");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (G[i * 3 + j] != G[j * 3 + i] || H[i * 3 + j] != H[j * 3 + i]) DB_THROW(DBFFT_EINVAL, "G and H must be symmetric");
+  if (!c.sol2) c.sol2 = static_cast<double*>(dalloc(3 * (size_t)c.g.nh * 2 * sizeof(double)));
+  dbfft_opts o;
+  dbfft_default_opts(&o);
+  o.tol = 1e-12;
+  o.tol_load = 1e-12;
+  const MacroSet ms = macro_set(c, c.last_mask);
+  double Urm[9], Lrm[9];
+  for (int i = 0; i < 9; ++i) {
+    Urm[i] = c.last_mask[i] ? 0.0 : G[i];
+    Lrm[i] = c.last_mask[i] ? -H[i] : G[i];
+  }
+  double EU2[9], lst[9];
+  rm_to_stored(c.kin, Urm, EU2);
+  rm_to_stored(c.kin, Lrm, lst);
+  double sbar[kMaxMacro] = {0};
+  for (int a = 0; a < ms.nS; ++a) sbar[a] = bdot(c.kin, ms.bst[a], lst);
+  LinOut lo = linear_solve(c, EU2, ms, sbar, o, c.sol2);
+  if (lo.status != DBFFT_OK) DB_THROW(lo.status, "adjoint solve did not converge");
+  double mt2[9];
+  for (int i = 0; i < 9; ++i) mt2[i] = EU2[i];
+  for (int a = 0; a < ms.nS; ++a)
+    for (int i = 0; i < 9; ++i) mt2[i] += lo.e_coef[a] * ms.bst[a][i];
+  double mt[9];
+  for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+  set_macro(c, mt);
+  strain_field(c, c.sol, c.mac_dev, c.fa);
+  set_macro(c, mt2);
+  strain_field(c, c.sol2, c.mac_dev, c.fb);
+  launch_adjoint_density(c.fa, c.fb, c.lam1, c.mu1, c.g.nvox, grad_dev, c.g.inv_nvox, c.st);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(c.st));
+  if (J_out) {
+    double J = 0.0;
+    for (int i = 0; i < 9; ++i) J += G[i] * c.sig_rm[i] + H[i] * c.eps_rm[i];
+    *J_out = J;
+  }
+  return DBFFT_OK;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64 bar: operator applications within 1e-12 relative (max-norm over the
+field); solutions solved to tol 1e-12 on both sides within 1e-10 relative;
+PCG iteration counts at tol 1e-8 within +-2.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_12725_amd import microstructure as ms
+from oracle import spectral as sp, solver as so, materials as mt
+
+pytestmark = pytest.mark.gpu
+
+
+def iso_params(E, nu):
+    out = []
+    for e in E:
+        out += [e, nu]
+    return out
+
+
+def oracle_iso(phase, E, nu):
+    lam, mu = mt.lame(np.asarray(E)[phase], nu)
+    return so.IsoTangent(lam, mu)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (16, 12, 10), (6, 10, 4), (32, 32, 32), (20, 18, 30)])
+def test_real_apply_iso_phase(gpu, n):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case real_apply iso_phase n={n}", flush=True)
+    rng = np.random.default_rng(100)
+    phase = (rng.random(n) < 0.35).astype(np.uint8)
+    E = [1.0, 7.0]
+    u = rng.standard_normal((3,) + n)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3)) as cell:
+        f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    space = so.Space(n)
+    a = sp.fourier(u, n)
+    a[:, space.Z] = 0
+    (ka, _), _ = space.apply((a, np.zeros(0)), oracle_iso(phase, E, 0.3))
+    ref = sp.real_field(ka, n)
+    assert rel(f, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (12, 10, 16)])
+def test_real_apply_aniso_grain(gpu, n):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case real_apply aniso n={n}", flush=True)
+    rng = np.random.default_rng(101)
+    ng = 5
+    grain = rng.integers(0, ng, size=n).astype(np.int32)
+    A = rng.standard_normal((ng, 6, 6))
+    Cm = np.einsum("gab,gcb->gac", A, A) + 6 * np.eye(6)
+    u = rng.standard_normal((3,) + n)
+    with Cell(n, "aniso_grain", torch.from_numpy(grain), Cm.reshape(-1)) as cell:
+        f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    space = so.Space(n)
+    a = sp.fourier(u, n)
+    a[:, space.Z] = 0
+    C4 = mt.mandel_to_tensor4(Cm[grain])
+    (ka, _), _ = space.apply((a, np.zeros(0)), so.GeneralTangent(C4))
+    ref = sp.real_field(ka, n)
+    assert rel(f, ref) < 1e-12
+
+
+def test_fourier_apply_with_macro(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (12, 10, 8)
+    print(f"case fourier_apply n={n}", flush=True)
+    rng = np.random.default_rng(102)
+    phase = (rng.random(n) < 0.5).astype(np.uint8)
+    E = [2.0, 5.0]
+    space = so.Space(n)
+    a = sp.fourier(rng.standard_normal((3,) + n), n)
+    a[:, space.Z] = 0
+    e = rng.standard_normal((3, 3)) * 0.1
+    e = 0.5 * (e + e.T)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.25)) as cell:
+        f, sig = cell.apply_fourier(torch.from_numpy(a).cuda(), e)
+        f = f.cpu().numpy()
+    eps = space.field_of(a, np.zeros(0), e)
+    tan = oracle_iso(phase, E, 0.25)
+    r, dc = space.divergence_residual(tan.stress(eps))
+    assert rel(f, -r) < 1e-12
+    assert rel(sig, dc) < 1e-12
+
+
+def test_config1_sphere_solve_parity(gpu):
+    """16^3 centred sphere at 20 %, contrast 10, uniaxial strain 1e-3."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (16, 16, 16)
+    print("case config1 solve", flush=True)
+    phase = ms.centred_sphere(n, 0.2)
+    E = [1.0, 10.0]
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3
+    tan = oracle_iso(phase, E, 0.3)
+    ref8 = so.solve_linear(n, tan, load)
+    ref12 = so.solve_linear(n, tan, load, tol=1e-12, tol_load=1e-12)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3)) as cell:
+        i8 = cell.solve(load)
+        i12 = cell.solve(load, tol=1e-12, tol_load=1e-12)
+        h = cell.homogenize(strain=True)
+        a, _ = cell.solution()
+        a = a.cpu().numpy()
+        strain = h["strain"].cpu().numpy()
+    assert abs(i8["pcg_iters"] - ref8.info.iterations) <= 2
+    assert i8["eq_res"] < 1.01e-8
+    assert rel(h["sigma_bar"], ref12.sigma_bar) < 1e-10
+    assert rel(a, ref12.a) < 1e-10
+    eps_ref = ref12.strain_field()
+    E6 = np.stack([strain[0], strain[1], strain[2], strain[3], strain[4], strain[5]])
+    R6 = np.stack([eps_ref[0, 0], eps_ref[1, 1], eps_ref[2, 2], eps_ref[1, 2], eps_ref[0, 2], eps_ref[0, 1]])
+    assert rel(E6, R6) < 1e-10
+
+
+def test_mixed_control_parity(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (16, 12, 10)
+    print("case mixed control", flush=True)
+    rng = np.random.default_rng(103)
+    phase = (rng.random(n) < 0.3).astype(np.uint8)
+    E = [1.0, 20.0]
+    mask = np.ones((3, 3), bool)
+    mask[0, 0] = False
+    mask[0, 1] = mask[1, 0] = False
+    load = np.zeros((3, 3))
+    load[0, 0] = 1e-3
+    load[0, 1] = load[1, 0] = 2e-4
+    load[2, 2] = 5e-3  # prescribed stress
+    tan = oracle_iso(phase, E, 0.3)
+    ref = so.solve_linear(n, tan, load, mask, tol=1e-12, tol_load=1e-12)
+    ref8 = so.solve_linear(n, tan, load, mask)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3)) as cell:
+        i12 = cell.solve(load, mask, tol=1e-12, tol_load=1e-12)
+        h = cell.homogenize()
+        i8 = cell.solve(load, mask)
+    assert rel(h["sigma_bar"], ref.sigma_bar) < 1e-10
+    assert rel(h["eps_bar"], ref.eps_bar) < 1e-10
+    assert abs(i8["pcg_iters"] - ref8.info.iterations) <= 2
+    assert abs(h["sigma_bar"][2, 2] - 5e-3) < 1e-12 * 5e-3 * 10
+
+
+def test_fp32_mixed_solve_accuracy(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (32, 32, 32)
+    print("case fp32 mixed", flush=True)
+    phase, _, _ = ms.random_spheres(n, 2, 2.0, 4.0, 0.3)
+    E = [1.0, 100.0]
+    load = np.zeros((3, 3)); load[0, 1] = load[1, 0] = 1e-3
+    ref = so.solve_linear(n, oracle_iso(phase, E, 0.3), load, tol=1e-12, tol_load=1e-12)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3), precision="fp32_mixed") as cell:
+        info = cell.solve(load)
+        sig = cell.homogenize()["sigma_bar"]
+    assert info["eq_res"] < 1e-8
+    assert rel(sig, ref.sigma_bar) < 1e-6
+
+
+def test_laminate_closed_form_gpu(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    from tests.test_oracle_solver import laminate_closed_form
+    n = (8, 4, 6)
+    print("case laminate", flush=True)
+    phase = ms.laminate(n, 0, [2, 4, 2])
+    E, nu = [1.0, 25.0], 0.3
+    L = np.array([[1e-3, 3e-4, -2e-4], [3e-4, 5e-4, 1e-4], [-2e-4, 1e-4, -7e-4]])
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, nu)) as cell:
+        cell.solve(L, tol=1e-13, tol_load=1e-13)
+        sig = cell.homogenize()["sigma_bar"]
+    f1 = float(phase.mean())
+    C = [mt.isotropic_tensor(*mt.lame(e, nu)) for e in E]
+    expect = laminate_closed_form(C, [1 - f1, f1], 0, L)
+    assert rel(sig, expect) < 1e-11
+
+
+def test_homogeneous_zero_iterations_gpu(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (8, 8, 8)
+    with Cell(n, "iso_phase", torch.zeros(n, dtype=torch.uint8), [2.0, 0.25]) as cell:
+        info = cell.solve(np.diag([1e-3, 0, 0]))
+    assert info["pcg_iters"] == 0
+    lam, mu = mt.lame(2.0, 0.25)
+    assert np.isclose(info["sigma_bar"][0, 0], (lam + 2 * mu) * 1e-3, rtol=1e-14)
+
+
+def test_deterministic_reductions(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (24, 24, 24)
+    phase = ms.centred_sphere(n, 0.2)
+    outs = []
+    for _ in range(2):
+        with Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 10.0, 0.3]) as cell:
+            cell.solve(np.diag([1e-3, 0, 0]))
+            a, _ = cell.solution()
+            outs.append(a.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
