@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Benchmark of the DBFFT hot path on one MI355X.
+
+Workload: 128^3 voxel periodic cell, seeded random non-overlapping spheres
+(radius 6-10 voxels, 30 % volume fraction, seed 2), stiffness contrast 100
+(E = 1 / 100, nu = 0.3), six independent macroscopic strain load cases
+(1e-3 times the Mandel basis tensors) giving the effective stiffness.
+One step = the six preconditioned-CG solves to the paper's equilibrium
+tolerance 1e-8 (right-hand sides, mean stiffness, all CG iterations and
+the final residual check), inputs resident in HBM.
+
+Prints one JSON line.  `value` is operator applications per second over
+the timed steps in FP64 (every CG iteration applies the operator once).
+Also reported: voxel-DOFs per second, per-kernel HIP-event durations and
+the roofline of the dominant kernel, the FP32-mixed (FP32 transforms and
+pointwise work, FP64 dots and outer corrections) solve time against FP64
+at equal homogenized-stress accuracy, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DBFFT operator applies/s (Gvoxel-DOF/s, %HBM) + solve time FP32-mixed vs FP64"
+
+
+def mandel_loads(scale=1e-3):
+    loads = []
+    pairs = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+    for (i, j) in pairs:
+        L = np.zeros((3, 3))
+        if i == j:
+            L[i, i] = scale
+        else:
+            L[i, j] = L[j, i] = scale / np.sqrt(2.0)
+        loads.append(L)
+    return loads
+
+
+def kernel_bytes(n, kind, wbytes):
+    """Algorithmic HBM bytes of one launch of each kernel kind (small strain,
+    phase-map material): complex half-spectrum fields of nh = n1 n2 (n3/2+1)
+    entries, 2*wbytes each."""
+    n1, n2, n3 = n
+    nh = n1 * n2 * (n3 // 2 + 1)
+    c = 2 * wbytes
+    N = n1 * n2 * n3
+    return {
+        "x_inverse_grad": (3 + 6) * nh * c,
+        "y_inverse": 12 * nh * c,
+        "z_fused_tangent": 12 * nh * c + N * 1,
+        "y_forward": 12 * nh * c,
+        "x_forward_div": (6 + 3) * nh * c,
+        "cg_alpha": 0,
+        "cg_update": 6 * 3 * nh * c,
+        "cg_beta": 0,
+        "cg_direction": 3 * 3 * nh * c,
+    }[kind]
+
+
+def run_cases(cell, loads, **opts):
+    cols, iters, refine = [], 0, 0
+    for L in loads:
+        info = cell.solve(L, **opts)
+        iters += info["pcg_iters"]
+        refine += info["refine_steps"]
+        cols.append(info["sigma_bar"].copy())
+    return cols, iters, refine
+
+
+def ceff(cols):
+    """Effective stiffness in the Mandel basis from the six responses."""
+    r2 = np.sqrt(2.0)
+    M = np.zeros((6, 6))
+    pairs = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+    for b, s in enumerate(cols):
+        for a, (i, j) in enumerate(pairs):
+            M[a, b] = s[i, j] * (1.0 if i == j else r2)
+    return M / 1e-3
+
+
+def cpu_baseline(n, phase, E, nu, loads, seconds):
+    """The oracle (NumPy, FP64) doing CG iterations of the same problem."""
+    import psutil
+    from oracle import materials as omt, solver as oso
+    lam, mu = omt.lame(np.asarray(E)[phase], nu)
+    tan = oso.IsoTangent(lam, mu)
+    space = oso.Space(n)
+    proc = psutil.Process()
+    L = loads[0]
+    t0 = time.perf_counter()
+    (ka, _), dc0 = space.apply(space.zeros(), tan, L)
+    b = (-ka, np.zeros(0))
+    M = space.preconditioner(tan.mean())
+    t1 = time.perf_counter()
+    # one iteration to size the sample
+    c0 = proc.cpu_times()
+    w0 = time.perf_counter()
+    _, _, info = oso.pcg(space, tan, M, b, dc0, tol=0.0, tol_load=0.0, max_iter=1)
+    one = time.perf_counter() - w0
+    k = max(2, int(seconds / max(one, 1e-3)))
+    c0 = proc.cpu_times()
+    w0 = time.perf_counter()
+    _, _, info = oso.pcg(space, tan, M, b, dc0, tol=0.0, tol_load=0.0, max_iter=k)
+    wall = time.perf_counter() - w0
+    c1 = proc.cpu_times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    cores = max(1, int(round(cpu / wall)))
+    return {
+        "value": info.iterations / wall,
+        "unit": "applies/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{info.iterations} CG iterations (one operator application each) of load case 11 "
+                  f"of the same {n[0]}^3 cell, FP64 NumPy oracle, {wall:.1f} s wall; "
+                  f"setup {t1 - t0:.1f} s not counted",
+        "host_cpu_count": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU: the DBFFT hot path here is a single-GPU build "
+              "(no multi-GPU sharding); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1905_12725_amd import microstructure as ms
+    from paper_1905_12725_amd.api import Cell
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    n = (args.n,) * 3
+    phase, _, _ = ms.random_spheres(n, 2, 6.0, 10.0, 0.30)
+    E, nu = [1.0, 100.0], 0.3
+    params = [E[0], nu, E[1], nu]
+    loads = mandel_loads()
+    N = int(np.prod(n))
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    log(f"[bench] {n} spheres vf={phase.mean():.4f}, contrast 100, 6 load cases")
+
+    cell = Cell(n, "iso_phase", torch.from_numpy(phase), params)
+    for _ in range(args.warmup):
+        run_cases(cell, loads, tol=1e-8)
+    log("[bench] warmup done")
+
+    cell.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_iters = 0
+    cols64 = None
+    for s in range(args.steps):
+        cols64, it, _ = run_cases(cell, loads, tol=1e-8)
+        total_iters += it
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktime = cell.kernel_timing(False)
+    log(f"[bench] timed {args.steps} steps: {elapsed:.3f} s, {total_iters} applies")
+
+    applies_per_s = total_iters / elapsed
+    per_kernel = {}
+    for k, (ms_tot, cnt) in ktime.items():
+        if cnt > 0:
+            avg = ms_tot / cnt * 1e-3
+            b = kernel_bytes(n, k, 8)
+            per_kernel[k] = {"avg_us": avg * 1e6, "launches": cnt, "total_ms": ms_tot,
+                             "bytes_per_launch": b, "GBps": (b / avg / 1e9) if b else None}
+    dom = max((k for k in per_kernel if per_kernel[k]["bytes_per_launch"] > 0),
+              key=lambda k: per_kernel[k]["total_ms"])
+    dk = per_kernel[dom]
+    apply_kinds = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div")
+    apply_us = sum(per_kernel[k]["avg_us"] for k in apply_kinds if k in per_kernel)
+    apply_bytes = sum(kernel_bytes(n, k, 8) for k in apply_kinds)
+    iter_kinds = apply_kinds + ("cg_alpha", "cg_update", "cg_beta", "cg_direction")
+    iter_us = sum(per_kernel[k]["avg_us"] for k in iter_kinds if k in per_kernel)
+    iter_bytes = sum(kernel_bytes(n, k, 8) for k in iter_kinds)
+
+    out = {
+        "metric": METRIC,
+        "value": applies_per_s,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n[0]}^3 two-phase random spheres (radius 6-10 voxels, 30 % volume fraction, seed 2), "
+                        "stiffness contrast 100, nu 0.3, six Mandel strain load cases, PCG tol 1e-8, FP64",
+            "grid": list(n),
+            "volume_fraction": float(phase.mean()),
+            "load_cases": 6,
+            "pcg_iterations_per_step": total_iters // args.steps,
+        },
+        "gvoxel_dof_per_s": 3.0 * N * applies_per_s / 1e9,
+        "hbm_model": {
+            "apply_bytes": apply_bytes,
+            "apply_us_events": apply_us,
+            "apply_frac_of_peak": apply_bytes / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "iteration_bytes": iter_bytes,
+            "iteration_us_events": iter_us,
+            "iteration_frac_of_peak": iter_bytes / (iter_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "whole_job_frac_of_peak": iter_bytes * applies_per_s / 1e9 / HBM_PEAK_GBS,
+        },
+        "kernels": per_kernel,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": dk["GBps"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dk["GBps"] / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+
+    # tight FP64 reference for accuracy, then FP32-mixed vs FP64 at equal accuracy
+    if not args.no_mixed:
+        ref_cols, _, _ = run_cases(cell, loads, tol=1e-10, tol_load=1e-10)
+        Cref = ceff(ref_cols)
+
+        def err(cols):
+            return float(np.max(np.abs(ceff(cols) - Cref)) / np.max(np.abs(Cref)))
+
+        mixed = Cell(n, "iso_phase", torch.from_numpy(phase), params, precision="fp32_mixed")
+        run_cases(mixed, loads, tol=1e-8)  # warm
+        res = {}
+        for name, c in (("fp64", cell), ("fp32_mixed", mixed)):
+            best = None
+            for tol in (1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                cols, it, rf = run_cases(c, loads, tol=tol)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                e = err(cols)
+                log(f"[bench] {name} tol={tol:g}: {dt:.3f} s, {it} iters, Ceff rel err {e:.2e}")
+                if e <= 1e-6:
+                    best = {"tol": tol, "time_s": dt, "pcg_iters": it, "refine_steps": rf, "ceff_rel_err": e}
+                    break
+            res[name] = best
+        mixed.close()
+        if res.get("fp64") and res.get("fp32_mixed"):
+            res["speedup_fp32_mixed_vs_fp64"] = res["fp64"]["time_s"] / res["fp32_mixed"]["time_s"]
+        res["target_ceff_rel_err"] = 1e-6
+        out["equal_accuracy_1e-6"] = res
+        out["ceff_rel_err_fp64_tol1e-8"] = err(cols64)
+    cell.close()
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(n, phase, E, nu, loads, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

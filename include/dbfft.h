@@ -175,6 +175,20 @@ dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]);
  * J_out (host, may be NULL) receives J. */
 dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out);
 
+/* Per-kernel timing of PCG iterations with HIP events recorded on the
+ * context's stream around every kernel of every iteration (only iterations
+ * that ran to completion are counted).  Slot k of ms_total / launches
+ * (host arrays of 16, either may be NULL) receives the accumulated
+ * milliseconds and launch count of kernel kind k:
+ *   0 x pass inverse + gradient      1 y pass inverse
+ *   2 z pass C2R + tangent + R2C     3 y pass forward
+ *   4 x pass forward + divergence    5 CG step length (scalar)
+ *   6 CG update x, r, <r, M r>       7 CG direction scalars (scalar)
+ *   8 CG direction p = M r + beta p
+ * The current totals are returned first; enable = 1 then starts (and, if
+ * timing was off, resets) the counters, enable = 0 stops them. */
+dbfft_status dbfft_kernel_timing(dbfft_ctx* ctx, int32_t enable, double ms_total[16], int64_t launches[16]);
+
 /* Releases the context and its device memory. */
 void dbfft_destroy(dbfft_ctx* ctx);
 

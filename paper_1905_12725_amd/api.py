@@ -143,6 +143,14 @@ class Cell:
         nat.check(nat.lib().dbfft_get_solution(self._h, _ptr(a), e))
         return a, np.array(e[:]).reshape(3, 3)
 
+    def kernel_timing(self, enable):
+        """Returns {kind: (total_ms, launches)} accumulated so far, then
+        switches event timing on (enable=True, counters reset) or off."""
+        ms = (ct.c_double * 16)()
+        n = (ct.c_int64 * 16)()
+        nat.check(nat.lib().dbfft_kernel_timing(self._h, 1 if enable else 0, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(nat.KERNEL_KINDS)}
+
     def adjoint(self, G, H=None):
         G = np.asarray(G, dtype=np.float64).reshape(9)
         H = np.zeros(9) if H is None else np.asarray(H, dtype=np.float64).reshape(9)

@@ -174,6 +174,14 @@ struct Ctx {
   // current tangent for apply: 0 elastic, 1 field (after a nonlinear solve)
   int tangent_from_field = 0;
 
+  // optional per-kernel timing of PCG iterations with HIP events
+  int prof_on = 0;
+  int prof_tag = -1;  // iteration index within the enqueued chunk, -1 = not timed
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind, ev_iter;
+  double prof_ms[16] = {0};
+  long long prof_n[16] = {0};
+
   // solution state
   bool solved = false;
   int last_mask[9] = {0};
@@ -182,6 +190,38 @@ struct Ctx {
   double sig_rm[9] = {0}, eps_rm[9] = {0};
   bool linear_material() const { return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE; }
 };
+
+enum ProfKind { PK_XINV = 0, PK_YINV, PK_ZFUSED, PK_YFWD, PK_XFWD, PK_ALPHA, PK_UPDATE, PK_BETA, PK_PUPDATE, PK_END };
+
+// records an event that marks the start of a kernel of `kind` (PK_END closes)
+static void prof_mark(Ctx& c, int kind) {
+  if (!c.prof_on || c.prof_tag < 0) return;
+  const size_t i = c.ev_kind.size();
+  if (i >= c.ev_pool.size()) {
+    hipEvent_t e;
+    HIPCK(hipEventCreate(&e));
+    c.ev_pool.push_back(e);
+  }
+  HIPCK(hipEventRecord(c.ev_pool[i], c.st));
+  c.ev_kind.push_back(kind);
+  c.ev_iter.push_back(c.prof_tag);
+}
+
+// after a stream sync: attribute elapsed times of the first `executed`
+// iterations of the chunk
+static void prof_collect(Ctx& c, int executed) {
+  const size_t n = c.ev_kind.size();
+  for (size_t i = 0; i + 1 < n; ++i) {
+    const int k = c.ev_kind[i];
+    if (k < 0 || k >= PK_END || c.ev_iter[i] >= executed) continue;
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));
+    c.prof_ms[k] += ms;
+    c.prof_n[k] += 1;
+  }
+  c.ev_kind.clear();
+  c.ev_iter.clear();
+}
 
 static void* dalloc(size_t bytes) {
   void* p = nullptr;
@@ -311,12 +351,17 @@ static void apply_K(Ctx& c, const void* a, void* out, const double* macro_dev, c
   const StridedGeom sx = xgeom(c), sy = ygeom(c);
   const int gm = (c.kin == KIN_SMALL) ? SP_GRAD_SMALL : SP_GRAD_FINITE;
   const int dm = (c.kin == KIN_SMALL) ? SP_DIV_SMALL : SP_DIV_FINITE;
+  prof_mark(c, PK_XINV);
   launch_strided<T>(gm, a, c.W, 0, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, stop);
+  prof_mark(c, PK_YINV);
   launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, stop);
   int nb = 0;
+  prof_mark(c, PK_ZFUSED);
   launch_line<T>(LP_FUSED, c.kin, c.W, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, macro_dev, macro_add, energy_partials,
                  c.ncomp, c.st, &nb, stop);
+  prof_mark(c, PK_YFWD);
   launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
+  prof_mark(c, PK_XFWD);
   launch_strided<T>(dm, c.W, out, 0, sx, c.g, c.p1, tb.tw1, -1, dc_out, c.st, stop);
 }
 
@@ -538,16 +583,25 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
   const int* stop = reinterpret_cast<const int*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, converged));
   if (check_every < 1) check_every = 1;
   while (!c.sc_host->converged) {
+    const int iter0 = c.sc_host->iter;
     for (int k = 0; k < check_every; ++k) {
+      c.prof_tag = k;
       apply_K<T>(c, p, q, pmac, nullptr, tan, c.partA, c.dc_dev, stop);
+      prof_mark(c, PK_ALPHA);
       launch_pcg_alpha(c.sc_dev, c.partA, neb, c.dc_dev, pc, c.st);
+      prof_mark(c, PK_UPDATE);
       launch_pcg_update<T>(x, r, p, q, c.sc_dev, pa, c.g, c.partB, nb, c.st);
+      prof_mark(c, PK_BETA);
       launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 0, c.st);
+      prof_mark(c, PK_PUPDATE);
       launch_pcg_pupdate<T>(p, r, c.sc_dev, pa, c.g, nb, c.st);
     }
+    prof_mark(c, PK_END);
+    c.prof_tag = -1;
     HIPCK(hipGetLastError());
     HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
     HIPCK(hipStreamSynchronize(c.st));
+    if (c.prof_on) prof_collect(c, c.sc_host->iter - iter0 - (c.sc_host->converged ? 1 : 0));
   }
   PcgOut o;
   o.iters = h.iter;
@@ -883,6 +937,7 @@ static void release(Ctx* c) {
     if (p) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->red_host) (void)hipHostFree(c->red_host);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
 }
 
 static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const void* field, const double* params,
@@ -1138,6 +1193,26 @@ void dbfft_default_opts(dbfft_opts* o) {
 }
 
 const char* dbfft_last_error(void) { return g_err.c_str(); }
+
+dbfft_status dbfft_kernel_timing(dbfft_ctx* ctx, int32_t enable, double ms_total[16], int64_t launches[16]) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx) DB_THROW(DBFFT_EINVAL, "null context");
+  Ctx& c = *C(ctx);
+  if (ms_total)
+    for (int k = 0; k < 16; ++k) ms_total[k] = c.prof_ms[k];
+  if (launches)
+    for (int k = 0; k < 16; ++k) launches[k] = c.prof_n[k];
+  if (enable && !c.prof_on) {
+    for (int k = 0; k < 16; ++k) {
+      c.prof_ms[k] = 0.0;
+      c.prof_n[k] = 0;
+    }
+  }
+  c.prof_on = enable ? 1 : 0;
+  return DBFFT_OK;
+  API_END
+}
 
 dbfft_status dbfft_setup(dbfft_ctx** out, const int64_t n[3], int32_t kinematics, int32_t precision, int32_t material,
                          const void* field_dev, const double* params, int32_t nparams, void* hip_stream) {

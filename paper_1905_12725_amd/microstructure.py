@@ -56,6 +56,28 @@ def _periodic_dist2(n, centre):
     return d2
 
 
+def _mark_sphere(phase, centre, r):
+    """Set phase = 1 on voxels whose centre lies within periodic distance r
+    of `centre` (voxel units), visiting only the sphere's bounding box."""
+    n = phase.shape
+    idx, d2 = [], []
+    for ax in range(3):
+        lo = int(np.floor(centre[ax] - r - 0.5)) - 1
+        hi = int(np.ceil(centre[ax] + r - 0.5)) + 1
+        k = np.arange(lo, hi + 1)
+        k = np.unique(np.mod(k, n[ax]))
+        dd = k + 0.5 - centre[ax]
+        dd = dd - n[ax] * np.round(dd / n[ax])
+        idx.append(k)
+        d2.append(dd * dd)
+    D = d2[0][:, None, None] + d2[1][None, :, None] + d2[2][None, None, :]
+    sub = np.ix_(idx[0], idx[1], idx[2])
+    old = phase[sub]
+    inside = D <= r * r
+    phase[sub] = np.where(inside, np.uint8(1), old)
+    return int(np.count_nonzero(inside & (old == 0)))
+
+
 def centred_sphere(n, volume_fraction=0.2):
     """uint8 phase map: 1 inside a sphere centred in the cell, 0 elsewhere.
 
@@ -78,7 +100,9 @@ def random_spheres(n, seed, rmin, rmax, volume_fraction, max_tries=200000):
     n = tuple(int(v) for v in n)
     rng = np.random.default_rng(seed)
     phase = np.zeros(n, dtype=np.uint8)
-    centres, radii = [], []
+    centres = np.zeros((0, 3))
+    radii = np.zeros(0)
+    nn = np.array(n, dtype=float)
     nvox = float(np.prod(n))
     filled = 0
     tries = 0
@@ -87,22 +111,16 @@ def random_spheres(n, seed, rmin, rmax, volume_fraction, max_tries=200000):
         if tries > max_tries:
             raise RuntimeError("random_spheres: could not reach the volume fraction")
         r = rng.uniform(rmin, rmax)
-        c = rng.uniform(0.0, 1.0, size=3) * np.array(n, dtype=float)
-        ok = True
-        for c2, r2 in zip(centres, radii):
-            d = c - c2
-            d = d - np.array(n) * np.round(d / np.array(n))
-            if np.sqrt(np.sum(d * d)) < r + r2:
-                ok = False
-                break
-        if not ok:
-            continue
-        centres.append(c)
-        radii.append(r)
-        inside = _periodic_dist2(n, c) <= r * r
-        phase[inside] = 1
-        filled = int(phase.sum())
-    return phase, np.array(centres), np.array(radii)
+        c = rng.uniform(0.0, 1.0, size=3) * nn
+        if len(radii):
+            d = c[None, :] - centres
+            d = d - nn * np.round(d / nn)
+            if np.any(np.sqrt(np.sum(d * d, axis=1)) < r + radii):
+                continue
+        centres = np.vstack([centres, c[None, :]])
+        radii = np.append(radii, r)
+        filled += _mark_sphere(phase, c, r)
+    return phase, centres, radii
 
 
 def voronoi_grains(n, ngrains, seed):
