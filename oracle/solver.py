@@ -320,6 +320,8 @@ def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
             M = space.preconditioner(Cbar)
             d, _, pinfo = pcg(space, tan, M, r, dc, tol, tol_load, max_iter)
             pits += pinfo.iterations
+            if pinfo.breakdown or not pinfo.converged:
+                break
             a = a + d[0]
             e = e + d[1]
             new_fld = space.field_of(a, e, E_U)

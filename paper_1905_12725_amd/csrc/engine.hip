@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -19,6 +20,10 @@
 namespace dbfft {
 
 static thread_local std::string g_err;
+static const bool g_verbose = [] {
+  const char* v = std::getenv("DBFFT_VERBOSE");
+  return v != nullptr && v[0] != '0';
+}();
 
 struct Err {
   int code;
@@ -603,6 +608,9 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
     HIPCK(hipStreamSynchronize(c.st));
     if (c.prof_on) prof_collect(c, c.sc_host->iter - iter0 - (c.sc_host->converged ? 1 : 0));
   }
+  if (g_verbose)
+    std::fprintf(stderr, "[dbfft] pcg: iters %d status %d eq %.3e load %.3e rz %.3e pq %.3e\n", h.iter, h.converged,
+                 h.eq_res, h.load_res, h.rz, h.pq);
   PcgOut o;
   o.iters = h.iter;
   o.status = h.converged;
@@ -838,6 +846,12 @@ static int newton_solve(Ctx& c, const double load_rm[9], const int mask[9], int 
       read_dc(c, sig_st);
       double re[kMaxMacro] = {0};
       for (int a = 0; a < ms.nS; ++a) re[a] = sbar[a] - bdot(c.kin, ms.bst[a], sig_st);
+      if (g_verbose) {
+        double rl = 0.0;
+        for (int a = 0; a < ms.nS; ++a) rl += re[a] * re[a];
+        std::fprintf(stderr, "[dbfft] newton inc %d it %d dmax %.3e |r_e| %.3e sig0 %.4e\n", k, i, dmax,
+                     std::sqrt(rl), sig_st[0]);
+      }
       if (i > 0 && dmax < o.newton_tol) {
         conv = true;
         break;

@@ -149,11 +149,13 @@ def test_newton_finite_stress_control_homogeneous():
     shape = (4, 4, 4)
     mu, lam = 1.0, 7.0 / 3.0
     law = so.NeoHookeLaw(np.full(shape, mu), np.full(shape, lam))
-    mask = np.ones((3, 3), bool)
-    mask[0, 0] = False
+    # upper triangle of F prescribed (no free rigid rotation), diagonal and
+    # lower triangle of P prescribed
+    mask = np.array([[0, 0, 0], [1, 1, 0], [1, 1, 1]], dtype=bool)
     L = np.zeros((3, 3)); L[0, 0] = 0.1
     a, e, st, info = so.newton(shape, law, [L], mask, kin=so.FINITE, tol=1e-12, tol_load=1e-12,
                                newton_tol=1e-13)
+    assert info.converged
     # 0-D: F = diag(1.1, s, s) by symmetry, P22(s) = 0
     s = 1.0
     for _ in range(60):
