@@ -129,6 +129,20 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
                  const int* stop);
 
 int line_block_count(const Geom& g);
+// number of blocks (= energy partials) of the fused z pass for this grid
+int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes);
+
+// register-resident kernels for power-of-two transform lengths
+bool fast_strided_supported(int n);
+bool fast_line_supported(int n3);
+int fast_line_blocks(const Geom& g);
+template <typename T>
+void launch_strided_fast(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
+                         const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop);
+template <typename T>
+void launch_line_fast(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
+                      const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
+                      const int* stop);
 int line_lines_per_block(const Geom& g, int ncomp, int elem_bytes);
 
 // PCG vector kernels (3 half-spectrum components).

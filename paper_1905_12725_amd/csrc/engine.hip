@@ -372,8 +372,7 @@ static void apply_K(Ctx& c, const void* a, void* out, const double* macro_dev, c
 
 template <typename T>
 static int energy_blocks(Ctx& c) {
-  const int L = line_lines_per_block(c.g, c.ncomp, (int)(2 * sizeof(T)));
-  return (int)(((long long)c.g.n1 * c.g.n2 + L - 1) / L);
+  return fused_line_blocks(c.g, c.ncomp, (int)(2 * sizeof(T)));
 }
 
 // K [0; E] (stress of a uniform strain E): -> out (3 comps), dc

@@ -190,6 +190,10 @@ template <typename T>
 void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
                     const FftPlan& plan, const void* tw, int dir, double* dc_out, hipStream_t st,
                     const int* stop) {
+  if (fast_strided_supported(sg.nline)) {
+    launch_strided_fast<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop);
+    return;
+  }
   const int eb = (int)sizeof(cpx<T>);
   const int TZ = strided_tile(sg.nline, eb, mode != SP_PLAIN);
   const int ntiles = (sg.ncols + TZ - 1) / TZ;
@@ -541,6 +545,11 @@ template <typename T>
 void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, const FftPlan& plan, const void* tw,
                  const void* rtw, const TangentArgs<T>& tan, const double* macro_dev, const double* macro_add,
                  double* partials, int ncomp, hipStream_t st, int* nblocks_out, const int* stop) {
+  if (mode == LP_FUSED && macro_add == nullptr && fast_line_supported(g.n3)) {
+    if (nblocks_out) *nblocks_out = fast_line_blocks(g);
+    launch_line_fast<T>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
+    return;
+  }
   const int eb = (int)sizeof(cpx<T>);
   const int L = line_lines_per_block(g, ncomp, eb);
   const long long nlines = (long long)g.n1 * g.n2;
@@ -580,6 +589,12 @@ template void launch_line<double>(int, int, const void*, void*, const Geom&, con
 template void launch_line<float>(int, int, const void*, void*, const Geom&, const FftPlan&, const void*,
                                  const void*, const TangentArgs<float>&, const double*, const double*, double*,
                                  int, hipStream_t, int*, const int*);
+
+int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes) {
+  if (fast_line_supported(g.n3)) return fast_line_blocks(g);
+  const int L = line_lines_per_block(g, ncomp, elem_bytes);
+  return (int)(((long long)g.n1 * g.n2 + L - 1) / L);
+}
 
 int line_block_count(const Geom& g) {
   const int L = line_lines_per_block(g, 9, 16);

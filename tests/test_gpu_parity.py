@@ -29,7 +29,8 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("n", [(8, 8, 8), (16, 12, 10), (6, 10, 4), (32, 32, 32), (20, 18, 30)])
+@pytest.mark.parametrize("n", [(8, 8, 8), (16, 12, 10), (6, 10, 4), (32, 32, 32), (20, 18, 30),
+                               (64, 16, 128), (128, 8, 16), (16, 256, 32), (8, 16, 256)])
 def test_real_apply_iso_phase(gpu, n):
     import torch
     from paper_1905_12725_amd.api import Cell
@@ -48,7 +49,7 @@ def test_real_apply_iso_phase(gpu, n):
     assert rel(f, ref) < 1e-12
 
 
-@pytest.mark.parametrize("n", [(8, 8, 8), (12, 10, 16)])
+@pytest.mark.parametrize("n", [(8, 8, 8), (12, 10, 16), (32, 64, 64)])
 def test_real_apply_aniso_grain(gpu, n):
     import torch
     from paper_1905_12725_amd.api import Cell
@@ -70,10 +71,10 @@ def test_real_apply_aniso_grain(gpu, n):
     assert rel(f, ref) < 1e-12
 
 
-def test_fourier_apply_with_macro(gpu):
+@pytest.mark.parametrize("n", [(12, 10, 8), (16, 32, 64), (32, 16, 128)])
+def test_fourier_apply_with_macro(gpu, n):
     import torch
     from paper_1905_12725_amd.api import Cell
-    n = (12, 10, 8)
     print(f"case fourier_apply n={n}", flush=True)
     rng = np.random.default_rng(102)
     phase = (rng.random(n) < 0.5).astype(np.uint8)
@@ -207,3 +208,20 @@ def test_deterministic_reductions(gpu):
             a, _ = cell.solution()
             outs.append(a.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("n,prec", [((64, 64, 64), "fp64"), ((32, 64, 128), "fp32_mixed")])
+def test_solve_parity_power_of_two(gpu, n, prec):
+    """Register-resident kernels inside a full solve, against the oracle."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case solve {n} {prec}", flush=True)
+    phase, _, _ = ms.random_spheres(n, 7, 3.0, 6.0, 0.25)
+    E = [1.0, 30.0]
+    load = np.zeros((3, 3)); load[1, 2] = load[2, 1] = 1e-3; load[0, 0] = 5e-4
+    mask = np.zeros((3, 3), bool); mask[2, 2] = True
+    ref = so.solve_linear(n, oracle_iso(phase, E, 0.3), load, mask, tol=1e-11, tol_load=1e-11)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3), precision=prec) as cell:
+        info = cell.solve(load, mask, tol=1e-11, tol_load=1e-11)
+        sig = cell.homogenize()["sigma_bar"]
+    assert rel(sig, ref.sigma_bar) < (1e-9 if prec == "fp64" else 1e-6)
