@@ -130,7 +130,7 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
 
 int line_block_count(const Geom& g);
 // number of blocks (= energy partials) of the fused z pass for this grid
-int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes);
+int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes, int tan_kind);
 
 // register-resident kernels for power-of-two transform lengths
 bool fast_strided_supported(int n);

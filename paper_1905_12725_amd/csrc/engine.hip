@@ -371,8 +371,8 @@ static void apply_K(Ctx& c, const void* a, void* out, const double* macro_dev, c
 }
 
 template <typename T>
-static int energy_blocks(Ctx& c) {
-  return fused_line_blocks(c.g, c.ncomp, (int)(2 * sizeof(T)));
+static int energy_blocks(Ctx& c, int tan_kind) {
+  return fused_line_blocks(c.g, c.ncomp, (int)(2 * sizeof(T)), tan_kind);
 }
 
 // K [0; E] (stress of a uniform strain E): -> out (3 comps), dc
@@ -578,7 +578,7 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
   for (int a = 0; a < kMaxMacro; ++a) h.re[a] = re0[a];
   HIPCK(hipMemcpyAsync(c.sc_dev, c.sc_host, sizeof(PcgScalars), hipMemcpyHostToDevice, c.st));
   const int nb = pcg_block_count(c.g);
-  const int neb = energy_blocks<T>(c);
+  const int neb = energy_blocks<T>(c, tan.kind);
   launch_precond_init<T>(p, r, pa, c.g, c.partB, nb, c.st);
   launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 1, c.st);
   HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));

@@ -219,11 +219,13 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
     T xi1[8];
 #pragma unroll
     for (int gq = 0; gq < 8; ++gq) xi1[gq] = (T)xi_of(t + TL * fast_out_pos<N>(gq), g.n1);
-    cpx<T> a0[8], a1[8], a2[8];
+    cpx<T> a0[8], a1[8], a2[8];  // rows of -i xi_j s_ij before the factor -i
 #pragma unroll
     for (int r = 0; r < 8; ++r) a0[r] = a1[r] = a2[r] = mk<T>(0, 0);
     constexpr int NC = (MODE == SP_DIV_SMALL) ? 6 : 9;
-#pragma unroll
+    // one component live at a time (keeps the three accumulators the only
+    // long-lived registers)
+#pragma unroll 1
     for (int c = 0; c < NC; ++c) {
       cpx<T> v[8];
       load8(in + c * sg.cstride_in, v);
@@ -323,18 +325,94 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
   return mk<T>(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
-template <typename T, int M, int KIN>
+template <typename T, int M>
+struct LineCtx {
+  static constexpr int TL = M / 8;
+  static constexpr int LB = 64 / TL;
+  static constexpr int PITCH = M + 1;
+};
+
+// inverse real transform of component c for the 8 lines of the wave:
+// e[m] = packed pair at position t + TL m
+template <typename T, int M>
+__device__ __forceinline__ void line_inverse(const cpx<T>* src, bool valid, int t, int partner, cpx<T>* lds, int off,
+                                             const cpx<T>* tw, const cpx<T>* rtw, cpx<T>* e) {
+  constexpr int TL = M / 8;
+  cpx<T> X[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) X[r] = valid ? src[t + TL * r] : mk<T>(0, 0);
+  const cpx<T> XN = (valid && t == 0) ? src[M] : mk<T>(0, 0);
+  cpx<T> Z[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    // X[M - k] for k = t + TL r: lane (TL - t), register 7 - r; for t = 0 own register 8 - r (XN when r = 0)
+    const cpx<T> sh = shfl_c(X[7 - r], partner);
+    const cpx<T> own = (r == 0) ? XN : X[(8 - r) & 7];
+    const cpx<T> Xm = conj((t == 0) ? own : sh);
+    const cpx<T> Ev = add(X[r], Xm);
+    const cpx<T> Od = mul(sub(X[r], Xm), conj(rtw[t + TL * r]));
+    Z[r] = add(Ev, muli(Od, (T)1));
+  }
+  fast_fft<T, M>(Z, t, lds, 1, off, tw, (T)1);
+#pragma unroll
+  for (int gq = 0; gq < 8; ++gq) e[fast_out_pos<M>(gq)] = Z[gq];
+}
+
+// forward real transform of packed pairs e (positions t + TL m), scaled, stored
+template <typename T, int M>
+__device__ __forceinline__ void line_forward(cpx<T>* dst, bool valid, int t, int partner, cpx<T>* lds, int off,
+                                             const cpx<T>* tw, const cpx<T>* rtw, const cpx<T>* e, T scale) {
+  constexpr int TL = M / 8;
+  cpx<T> Z[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) Z[m] = e[m];
+  fast_fft<T, M>(Z, t, lds, 1, off, tw, (T)-1);
+  cpx<T> Zp[8];
+#pragma unroll
+  for (int gq = 0; gq < 8; ++gq) Zp[fast_out_pos<M>(gq)] = Z[gq];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int k = t + TL * m;
+    const cpx<T> sh = shfl_c(Zp[7 - m], partner);
+    const cpx<T> own = Zp[(8 - m) & 7];
+    const cpx<T> Zm = conj((t == 0) ? own : sh);
+    const cpx<T> Ev = scl(add(Zp[m], Zm), (T)0.5);
+    const cpx<T> Od = mul(rtw[k], scl(sub(Zp[m], Zm), (T)0.5));
+    if (valid) dst[k] = scl(sub(Ev, muli(Od, (T)1)), scale);
+  }
+  if (valid && t == 0) {
+    const cpx<T> Z0 = Zp[0], Zm = conj(Zp[0]);
+    const cpx<T> Ev = scl(add(Z0, Zm), (T)0.5);
+    const cpx<T> Od = mul(rtw[M], scl(sub(Z0, Zm), (T)0.5));
+    dst[M] = scl(sub(Ev, muli(Od, (T)1)), scale);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void iso_coeffs(const TangentArgs<T>& tn, long long vox, T& lam, T& mu2) {
+  if (tn.kind == TAN_ISO_PHASE) {
+    const int p = tn.phase[vox];
+    lam = (T)tn.lam[p];
+    mu2 = (T)(2.0 * tn.mu[p]);
+  } else {
+    const T E = tn.field[vox];
+    lam = (T)tn.lam1 * E;
+    mu2 = (T)(2.0 * tn.mu1) * E;
+  }
+}
+
+// ISO = 1: isotropic tangent; only the three normal components couple
+// (through the trace), so they are transformed together and every shear
+// component on its own, which keeps at most three components in registers.
+template <typename T, int M, int KIN, int ISO>
 __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out, Geom g, const cpx<T>* __restrict__ twg,
                                                   const cpx<T>* __restrict__ rtwg, TangentArgs<T> tn,
                                                   const double* __restrict__ macro_dev, double* __restrict__ partials,
                                                   const int* __restrict__ stop) {
   if (stop != nullptr && *stop) return;
-  constexpr int TL = M / 8;
-  constexpr int LB = 64 / TL;
+  using LC = LineCtx<T, M>;
+  constexpr int TL = LC::TL, LB = LC::LB, PITCH = LC::PITCH;
   constexpr int NC = (KIN == KIN_SMALL) ? 6 : 9;
-  constexpr int PITCH = M + 1;
-  constexpr int RL = fast_radix<M>(fast_nstages<M>() - 1);
-  constexpr int NBL = 8 / RL;
   __shared__ cpx<T> tw[M];
   __shared__ cpx<T> rtw[M + 1];
   __shared__ cpx<T> lds[LB * PITCH];
@@ -349,70 +427,83 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
   const bool valid = gl < nlines;
   const int partner = line * TL + ((TL - t) % TL);
   const int off = line * PITCH;
-
-  // position n = t + TL*m of register g after the inverse transform: m = q + NBL*r
-  // forward stage-0 register m must hold position t + TL*m.
-  cpx<T> e[NC][8];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const cpx<T>* src = in + c * g.nh + gl * nh3;
-    cpx<T> X[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) X[r] = valid ? src[t + TL * r] : mk<T>(0, 0);
-    const cpx<T> XN = (valid && t == 0) ? src[M] : mk<T>(0, 0);
-    cpx<T> Z[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      // X[M - k] for k = t + TL r: lane (TL - t), register 7 - r; for t = 0: own register 8 - r (XN for r = 0)
-      const cpx<T> sh = shfl_c(X[7 - r], partner);
-      const cpx<T> own = (r == 0) ? XN : X[(8 - r) & 7];
-      const cpx<T> Xm = conj((t == 0) ? own : sh);
-      const cpx<T> Ev = add(X[r], Xm);
-      const cpx<T> Od = mul(sub(X[r], Xm), conj(rtw[t + TL * r]));
-      Z[r] = add(Ev, muli(Od, (T)1));
-    }
-    fast_fft<T, M>(Z, t, lds, 1, off, tw, (T)1);
-    // rename to forward stage-0 order
-#pragma unroll
-    for (int gq = 0; gq < 8; ++gq) e[c][fast_out_pos<M>(gq)] = Z[gq];
-  }
-
-  // pointwise tangent on the 16 voxels of this thread
+  const T scale = (T)g.inv_nvox;
   double mac[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) mac[c] = macro_dev ? macro_dev[c] : 0.0;
   double energy = 0.0;
-  if (valid) {
+  const cpx<T>* inl = in + gl * nh3;
+  cpx<T>* outl = out + gl * nh3;
+
+  if constexpr (ISO == 1) {
+    // normal components 11 22 33
+    cpx<T> e[3][8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int n = t + TL * m;
+    for (int c = 0; c < 3; ++c) line_inverse<T, M>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c]);
+    if (valid) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const long long vox = gl * n3 + 2 * n + h;
-        T ev[NC], sv[NC];
+      for (int m = 0; m < 8; ++m) {
+        const int n = t + TL * m;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) ev[c] = (h == 0 ? e[c][m].x : e[c][m].y) + (T)mac[c];
-        if constexpr (KIN == KIN_SMALL) {
-          if (tn.kind == TAN_ISO_PHASE || tn.kind == TAN_ISO_FIELD) {
-            T lam, mu;
-            if (tn.kind == TAN_ISO_PHASE) {
-              const int p = tn.phase[vox];
-              lam = (T)tn.lam[p];
-              mu = (T)tn.mu[p];
-            } else {
-              const T E = tn.field[vox];
-              lam = (T)tn.lam1 * E;
-              mu = (T)tn.mu1 * E;
-            }
-            const T tr = ev[0] + ev[1] + ev[2];
-            const T m2 = mu + mu;
-            sv[0] = lam * tr + m2 * ev[0];
-            sv[1] = lam * tr + m2 * ev[1];
-            sv[2] = lam * tr + m2 * ev[2];
-            sv[3] = m2 * ev[3];
-            sv[4] = m2 * ev[4];
-            sv[5] = m2 * ev[5];
-          } else {
+        for (int h = 0; h < 2; ++h) {
+          const long long vox = gl * n3 + 2 * n + h;
+          T lam, mu2;
+          iso_coeffs<T>(tn, vox, lam, mu2);
+          T ev[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) ev[c] = (h == 0 ? e[c][m].x : e[c][m].y) + (T)mac[c];
+          const T tr = ev[0] + ev[1] + ev[2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T sv = lam * tr + mu2 * ev[c];
+            energy += (double)(ev[c] * sv);
+            if (h == 0) e[c][m].x = sv;
+            else e[c][m].y = sv;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) line_forward<T, M>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c], scale);
+    // shear components 23 13 12, one at a time: sigma = 2 mu eps
+#pragma unroll 1
+    for (int c = 3; c < 6; ++c) {
+      cpx<T> e1[8];
+      line_inverse<T, M>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e1);
+      if (valid) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int n = t + TL * m;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const long long vox = gl * n3 + 2 * n + h;
+            T lam, mu2;
+            iso_coeffs<T>(tn, vox, lam, mu2);
+            const T ev = (h == 0 ? e1[m].x : e1[m].y) + (T)mac[c];
+            const T sv = mu2 * ev;
+            energy += 2.0 * (double)(ev * sv);
+            if (h == 0) e1[m].x = sv;
+            else e1[m].y = sv;
+          }
+        }
+      }
+      line_forward<T, M>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e1, scale);
+    }
+  } else {
+    cpx<T> e[NC][8];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) line_inverse<T, M>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c]);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int n = t + TL * m;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const long long vox = gl * n3 + 2 * n + h;
+          T ev[NC], sv[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) ev[c] = (h == 0 ? e[c][m].x : e[c][m].y) + (T)mac[c];
+          if constexpr (KIN == KIN_SMALL) {
             const T r2 = (T)1.41421356237309504880, ir2 = (T)0.70710678118654752440;
             const T vv[6] = {ev[0], ev[1], ev[2], r2 * ev[3], r2 * ev[4], r2 * ev[5]};
             T o6[6] = {0, 0, 0, 0, 0, 0};
@@ -433,86 +524,55 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
             sv[3] = o6[3] * ir2;
             sv[4] = o6[4] * ir2;
             sv[5] = o6[5] * ir2;
+            energy += (double)(ev[0] * sv[0] + ev[1] * sv[1] + ev[2] * sv[2]) +
+                      2.0 * (double)(ev[3] * sv[3] + ev[4] * sv[4] + ev[5] * sv[5]);
+          } else {
+            T Fi[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Fi[i] = tn.field[(long long)i * g.nvox + vox];
+            const T lnJ = tn.field[9LL * g.nvox + vox];
+            const int p = tn.phase[vox];
+            const T mu = (T)tn.mu[p], lam = (T)tn.lam[p];
+            T tr = 0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int J = 0; J < 3; ++J) tr += Fi[J * 3 + i] * ev[i * 3 + J];
+            T T1[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int J = 0; J < 3; ++J) {
+                T acc = 0;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) acc += ev[b * 3 + a] * Fi[J * 3 + b];
+                T1[a * 3 + J] = acc;
+              }
+            const T c2 = mu - lam * lnJ;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int J = 0; J < 3; ++J) {
+                T acc = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) acc += Fi[a * 3 + i] * T1[a * 3 + J];
+                sv[i * 3 + J] = mu * ev[i * 3 + J] + c2 * acc + lam * tr * Fi[J * 3 + i];
+              }
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc += (double)(ev[c] * sv[c]);
+            energy += acc;
           }
-          energy += (double)(ev[0] * sv[0] + ev[1] * sv[1] + ev[2] * sv[2]) +
-                    2.0 * (double)(ev[3] * sv[3] + ev[4] * sv[4] + ev[5] * sv[5]);
-        } else {
-          T Fi[9];
 #pragma unroll
-          for (int i = 0; i < 9; ++i) Fi[i] = tn.field[(long long)i * g.nvox + vox];
-          const T lnJ = tn.field[9LL * g.nvox + vox];
-          const int p = tn.phase[vox];
-          const T mu = (T)tn.mu[p], lam = (T)tn.lam[p];
-          T tr = 0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int J = 0; J < 3; ++J) tr += Fi[J * 3 + i] * ev[i * 3 + J];
-          T T1[9];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int J = 0; J < 3; ++J) {
-              T acc = 0;
-#pragma unroll
-              for (int b = 0; b < 3; ++b) acc += ev[b * 3 + a] * Fi[J * 3 + b];
-              T1[a * 3 + J] = acc;
-            }
-          const T c2 = mu - lam * lnJ;
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int J = 0; J < 3; ++J) {
-              T acc = 0;
-#pragma unroll
-              for (int a = 0; a < 3; ++a) acc += Fi[a * 3 + i] * T1[a * 3 + J];
-              sv[i * 3 + J] = mu * ev[i * 3 + J] + c2 * acc + lam * tr * Fi[J * 3 + i];
-            }
-          double acc = 0.0;
-#pragma unroll
-          for (int c = 0; c < 9; ++c) acc += (double)(ev[c] * sv[c]);
-          energy += acc;
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          if (h == 0) e[c][m].x = sv[c];
-          else e[c][m].y = sv[c];
+          for (int c = 0; c < NC; ++c) {
+            if (h == 0) e[c][m].x = sv[c];
+            else e[c][m].y = sv[c];
+          }
         }
       }
     }
-  }
-
-  // forward real transforms, scaled by 1/N
-  const T scale = (T)g.inv_nvox;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    cpx<T> Z[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) Z[m] = e[c][m];
-    fast_fft<T, M>(Z, t, lds, 1, off, tw, (T)-1);
-    cpx<T> Zp[8];  // Zp[m] = Z at position t + TL m
-#pragma unroll
-    for (int gq = 0; gq < 8; ++gq) Zp[fast_out_pos<M>(gq)] = Z[gq];
-    cpx<T>* dst = out + c * g.nh + gl * nh3;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int k = t + TL * m;
-      const cpx<T> sh = shfl_c(Zp[7 - m], partner);
-      const cpx<T> own = Zp[(8 - m) & 7];
-      const cpx<T> Zm = conj((t == 0) ? own : sh);
-      const cpx<T> Ev = scl(add(Zp[m], Zm), (T)0.5);
-      const cpx<T> Od = mul(rtw[k], scl(sub(Zp[m], Zm), (T)0.5));
-      const cpx<T> X = sub(Ev, muli(Od, (T)1));
-      if (valid) dst[k] = scl(X, scale);
-    }
-    if (valid && t == 0) {
-      // Nyquist bin k = M from Z[0]
-      const cpx<T> Z0 = Zp[0];
-      const cpx<T> Zm = conj(Z0);
-      const cpx<T> Ev = scl(add(Z0, Zm), (T)0.5);
-      const cpx<T> Od = mul(rtw[M], scl(sub(Z0, Zm), (T)0.5));
-      dst[M] = scl(sub(Ev, muli(Od, (T)1)), scale);
-    }
+    for (int c = 0; c < NC; ++c) line_forward<T, M>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c], scale);
   }
   if (partials != nullptr) {
 #pragma unroll
@@ -538,11 +598,14 @@ static void launch_line_fast_m(int kin, const void* in, void* out, const Geom& g
   auto o = static_cast<cpx<T>*>(out);
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
-  if (kin == KIN_SMALL)
-    hipLaunchKernelGGL((k_line_fast<T, M, KIN_SMALL>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+  if (kin == KIN_SMALL && (tan.kind == TAN_ISO_PHASE || tan.kind == TAN_ISO_FIELD))
+    hipLaunchKernelGGL((k_line_fast<T, M, KIN_SMALL, 1>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+                       partials, stop);
+  else if (kin == KIN_SMALL)
+    hipLaunchKernelGGL((k_line_fast<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else
-    hipLaunchKernelGGL((k_line_fast<T, M, KIN_FINITE>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+    hipLaunchKernelGGL((k_line_fast<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
 }
 
