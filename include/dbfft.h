@@ -192,6 +192,50 @@ dbfft_status dbfft_kernel_timing(dbfft_ctx* ctx, int32_t enable, double ms_total
 /* Releases the context and its device memory. */
 void dbfft_destroy(dbfft_ctx* ctx);
 
+/* ---------------------------------------------------------------- batches
+ * A batch solves the cell problems of several contexts together: the same
+ * PCG (Sec. 2.5) and, for the non-linear materials, the same Newton loop
+ * with load increments (Sec. 2.4) as dbfft_solve, run in lockstep.  Each
+ * batched PCG iteration is one kernel launch per pass covering every cell
+ * (grids may differ in size); every cell keeps its own CG scalars and
+ * convergence flag, and a chunk of opts->check_every iterations is captured
+ * once in a HIP graph and replayed.  The batching itself is not part of the
+ * paper's method; per cell the results equal dbfft_solve's up to the order
+ * of floating-point reductions, which is the same, so they match bit for
+ * bit in practice.
+ */
+typedef struct dbfft_batch dbfft_batch;
+
+/* Creates a batch over ncell existing contexts (host array of handles).
+ * All contexts need the same precision, kinematics and material class
+ * (linear: ISO_PHASE / ISO_FIELD / ANISO_GRAIN; non-linear: J2VP_CUBIC or
+ * NEOHOOKE).  The contexts stay owned by the caller and must outlive the
+ * batch; a context may belong to several batches but only one call may use
+ * it at a time.  use_graph = 0 launches the chunks eagerly instead of
+ * replaying a captured graph.  Autotunes the column tile of the x and y
+ * passes per distinct grid size (a few timed launches each).  The batch
+ * owns a non-blocking stream of its own.
+ * Errors: EINVAL (null handle, ncell < 1, mixed classes), ENOMEM, EHIP. */
+dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int32_t ncell, int32_t use_graph);
+
+/* Solves every cell of the batch.  loads and stress_masks are host arrays
+ * of ncell x 9 values (row-major 3x3 per cell, meaning as in dbfft_solve);
+ * infos (ncell entries) receives each cell's dbfft_info.  n_increments and
+ * dt are shared by all cells.  Afterwards dbfft_homogenize and
+ * dbfft_get_solution read each context's result as after dbfft_solve.
+ * Returns OK when every cell converged, else the status of the last cell
+ * that did not (each info.status holds its own). */
+dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_t* stress_masks,
+                               int32_t n_increments, double dt, const dbfft_opts* opts, dbfft_info* infos);
+
+/* Tiles chosen for each cell: tiles[3 r + 0] and [3 r + 1] are the column
+ * tile widths of the x and y passes, tiles[3 r + 2] the z lines per block
+ * (host array of 3 ncell int32). */
+dbfft_status dbfft_batch_tiles(dbfft_batch* b, int32_t* tiles);
+
+/* Releases the batch (not its contexts). */
+void dbfft_batch_destroy(dbfft_batch* b);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* dbfft_last_error(void);
 

@@ -27,7 +27,8 @@ MAT_ISO_PHASE, MAT_ISO_FIELD, MAT_ANISO_GRAIN, MAT_J2VP_CUBIC, MAT_NEOHOOKE = 0,
 EXPORTED = (
     "dbfft_default_opts", "dbfft_setup", "dbfft_apply", "dbfft_apply_fourier", "dbfft_solve",
     "dbfft_homogenize", "dbfft_get_solution", "dbfft_adjoint", "dbfft_destroy", "dbfft_last_error",
-    "dbfft_kernel_timing",
+    "dbfft_kernel_timing", "dbfft_batch_create", "dbfft_batch_solve", "dbfft_batch_tiles",
+    "dbfft_batch_destroy",
 )
 KERNEL_KINDS = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div",
                 "cg_alpha", "cg_update", "cg_beta", "cg_direction")
@@ -93,6 +94,14 @@ def load_library(path=LIB_PATH):
     lib.dbfft_destroy.restype = None
     lib.dbfft_kernel_timing.argtypes = [P, I32, DP, ct.POINTER(ct.c_int64)]
     lib.dbfft_kernel_timing.restype = ct.c_int
+    lib.dbfft_batch_create.argtypes = [ct.POINTER(ct.c_void_p), ct.POINTER(ct.c_void_p), I32, I32]
+    lib.dbfft_batch_create.restype = ct.c_int
+    lib.dbfft_batch_solve.argtypes = [P, DP, ct.POINTER(ct.c_uint8), I32, D, ct.POINTER(Opts), ct.POINTER(Info)]
+    lib.dbfft_batch_solve.restype = ct.c_int
+    lib.dbfft_batch_tiles.argtypes = [P, ct.POINTER(ct.c_int32)]
+    lib.dbfft_batch_tiles.restype = ct.c_int
+    lib.dbfft_batch_destroy.argtypes = [P]
+    lib.dbfft_batch_destroy.restype = None
     lib.dbfft_last_error.argtypes = []
     lib.dbfft_last_error.restype = ct.c_char_p
     return lib

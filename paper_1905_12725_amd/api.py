@@ -160,6 +160,63 @@ class Cell:
         return grad, J.value
 
 
+class Batch:
+    """Several cells (of one precision, kinematics and material class)
+    solved together: one launch per pass over every cell, a captured HIP
+    graph per chunk of PCG iterations.  The cells must outlive the batch."""
+
+    def __init__(self, cells, use_graph=True):
+        self.cells = list(cells)
+        if not self.cells:
+            raise ValueError("empty batch")
+        for c in self.cells:
+            torch.cuda.current_stream(c.device).synchronize()
+            c.stream.synchronize()
+        arr = (ct.c_void_p * len(self.cells))(*[c._h.value for c in self.cells])
+        h = ct.c_void_p()
+        nat.check(nat.lib().dbfft_batch_create(ct.byref(h), arr, len(self.cells), 1 if use_graph else 0))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            nat.lib().dbfft_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def tiles(self):
+        t = (ct.c_int32 * (3 * len(self.cells)))()
+        nat.check(nat.lib().dbfft_batch_tiles(self._h, t))
+        return np.array(t[:], dtype=np.int32).reshape(-1, 3)
+
+    def solve(self, loads, stress_masks=None, n_increments=1, dt=1.0, raise_on_fail=True, **opts):
+        n = len(self.cells)
+        loads = np.ascontiguousarray(np.broadcast_to(np.asarray(loads, dtype=np.float64).reshape(-1, 9), (n, 9)))
+        if stress_masks is None:
+            masks = np.zeros((n, 9), dtype=np.uint8)
+        else:
+            masks = np.ascontiguousarray(
+                np.broadcast_to(np.asarray(stress_masks, dtype=bool).reshape(-1, 9), (n, 9)).astype(np.uint8))
+        o = nat.default_opts(**opts)
+        infos = (nat.Info * n)()
+        st = nat.lib().dbfft_batch_solve(self._h, loads.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                         masks.ctypes.data_as(ct.POINTER(ct.c_uint8)), int(n_increments), float(dt),
+                                         ct.byref(o), infos)
+        if st != nat.DBFFT_OK and raise_on_fail:
+            nat.check(st)
+        return [_info_dict(infos[i]) for i in range(n)]
+
+
 class HomogenizedResponse(torch.autograd.Function):
     """J(E) = G:<sigma> + H:<eps> of a linear cell with per-voxel Young's
     modulus E (Poisson ratio nu), load / stress_mask as in Cell.solve.

@@ -1,0 +1,239 @@
+// Batched PCG over many cells of uneven grid sizes.
+//
+// One launch per pass covers every cell of the batch: the flattened grid is
+// cut into consecutive block ranges, one per cell, and each block finds its
+// cell in a device table of per-cell descriptors (geometry, FFT plans,
+// twiddles, vectors, tangent, preconditioner, scalars).  Every cell keeps
+// its own CG scalars and convergence flag; blocks of converged cells exit at
+// once, so a fixed chunk of iterations can be captured in a HIP graph and
+// replayed until every cell has converged.
+#include "batch.h"
+#include "fft_generic.h"
+#include "pcg_core.h"
+
+namespace dbfft {
+
+__device__ __forceinline__ int find_cell(const int* __restrict__ boff, int ncell, int b) {
+  // last r with boff[r] <= b (boff is non-decreasing, boff[0] = 0)
+  int lo = 0, hi = ncell - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T>* buf_of(const CellDesc<T>& R, int which) {
+  switch (which) {
+    case BUF_W: return R.W;
+    case BUF_X: return R.x;
+    case BUF_R: return R.r;
+    case BUF_P: return R.p;
+    default: return R.q;
+  }
+}
+
+// x pass (axis 0) or y pass (axis 1) of every cell
+template <typename T, int MODE>
+__global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>* __restrict__ D,
+                                                              const int* __restrict__ boff, int ncell, int axis,
+                                                              int src, int dst, int ncomp, T d) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int r = find_cell(boff, ncell, blockIdx.x);
+  const CellDesc<T>& R = D[r];
+  if (R.sc->converged) return;
+  const int lb = blockIdx.x - boff[r];
+  const Geom& g = R.g;
+  StridedGeom sg;
+  int tile, o, c, TZ;
+  const FftPlan* plan;
+  const cpx<T>* tw;
+  if (axis == 0) {
+    sg.nline = g.n1;
+    sg.lstride = (long long)g.n2 * g.nh3;
+    sg.ostride = g.nh3;
+    sg.nother = g.n2;
+    TZ = R.tzx;
+    const int nt = (g.nh3 + TZ - 1) / TZ;
+    tile = lb % nt;
+    o = (lb / nt) % g.n2;
+    c = lb / (nt * g.n2);
+    plan = &R.p1;
+    tw = R.tw1;
+  } else {
+    sg.nline = g.n2;
+    sg.lstride = g.nh3;
+    sg.ostride = (long long)g.n2 * g.nh3;
+    sg.nother = g.n1;
+    TZ = R.tzy;
+    const int nt = (g.nh3 + TZ - 1) / TZ;
+    tile = lb % nt;
+    o = (lb / nt) % g.n1;
+    c = lb / (nt * g.n1);
+    plan = &R.p2;
+    tw = R.tw2;
+  }
+  sg.ncols = g.nh3;
+  sg.cstride_in = g.nh;
+  sg.cstride_out = g.nh;
+  (void)ncomp;
+  double* dc = (MODE == SP_DIV_SMALL || MODE == SP_DIV_FINITE) ? R.dc : nullptr;
+  strided_core<T, MODE>(buf_of(R, src), buf_of(R, dst), sg, g, *plan, tw, d, TZ, dc, tile, o, c, smem_raw);
+}
+
+template <typename T, int KIN>
+__global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __restrict__ D, const int* __restrict__ boff,
+                                                        int ncell, int ncomp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int r = find_cell(boff, ncell, blockIdx.x);
+  const CellDesc<T>& R = D[r];
+  if (R.sc->converged) return;
+  const int lb = blockIdx.x - boff[r];
+  line_core<T, LP_FUSED, KIN>(R.W, R.W, R.g, R.p3, R.tw3, R.rtw, R.tan, R.sc->pmac, nullptr, R.partA, R.L, ncomp,
+                              (long long)lb, smem_raw);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void kb_update(const CellDesc<T>* __restrict__ D, const int* __restrict__ boff,
+                                                         int ncell) {
+  const int r = find_cell(boff, ncell, blockIdx.x);
+  const CellDesc<T>& R = D[r];
+  const int lb = blockIdx.x - boff[r];
+  update_core<T>(R.x, R.r, R.p, R.q, R.sc, R.pa, R.g, R.partB, lb, boff[r + 1] - boff[r]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void kb_pupdate(const CellDesc<T>* __restrict__ D,
+                                                          const int* __restrict__ boff, int ncell) {
+  const int r = find_cell(boff, ncell, blockIdx.x);
+  const CellDesc<T>& R = D[r];
+  const int lb = blockIdx.x - boff[r];
+  pupdate_core<T>(R.p, R.r, R.sc, R.pa, R.g, lb, boff[r + 1] - boff[r]);
+}
+
+// one block per cell
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void kb_alpha(const CellDesc<T>* __restrict__ D, const int* __restrict__ bz) {
+  const int r = blockIdx.x;
+  const CellDesc<T>& R = D[r];
+  alpha_core(R.sc, R.partA, bz[r + 1] - bz[r], R.dc, R.pc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void kb_beta(const CellDesc<T>* __restrict__ D, const int* __restrict__ bv) {
+  const int r = blockIdx.x;
+  const CellDesc<T>& R = D[r];
+  beta_core(R.sc, R.partB, bv[r + 1] - bv[r], R.pc, 0);
+}
+
+template <typename T>
+__global__ void kb_flags(const CellDesc<T>* __restrict__ D, int ncell, int* __restrict__ flags) {
+  for (int r = threadIdx.x; r < ncell; r += blockDim.x) flags[r] = D[r].sc->converged;
+}
+
+template <typename T>
+void launch_batch_iteration(const BatchLaunch& bl, const void* desc, hipStream_t st) {
+  auto D = static_cast<const CellDesc<T>*>(desc);
+  const int gm = bl.kin == KIN_SMALL ? SP_GRAD_SMALL : SP_GRAD_FINITE;
+  const int dm = bl.kin == KIN_SMALL ? SP_DIV_SMALL : SP_DIV_FINITE;
+  const dim3 ts(kStridedThreads), ls(kLineThreads), vs(kVecThreads);
+  // x inverse + gradient: a = p -> W
+  if (gm == SP_GRAD_SMALL)
+    hipLaunchKernelGGL((kb_strided<T, SP_GRAD_SMALL>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
+                       BUF_P, BUF_W, bl.ncomp, (T)1);
+  else
+    hipLaunchKernelGGL((kb_strided<T, SP_GRAD_FINITE>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
+                       BUF_P, BUF_W, bl.ncomp, (T)1);
+  // y inverse, all components
+  hipLaunchKernelGGL((kb_strided<T, SP_PLAIN>), dim3(bl.nby), ts, bl.lds_y, st, D, bl.boff_y, bl.ncell, 1, BUF_W, BUF_W,
+                     bl.ncomp, (T)1);
+  // z: C2R, tangent, R2C
+  if (bl.kin == KIN_SMALL)
+    hipLaunchKernelGGL((kb_line<T, KIN_SMALL>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+  else
+    hipLaunchKernelGGL((kb_line<T, KIN_FINITE>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+  // y forward
+  hipLaunchKernelGGL((kb_strided<T, SP_PLAIN>), dim3(bl.nby), ts, bl.lds_y, st, D, bl.boff_y, bl.ncell, 1, BUF_W, BUF_W,
+                     bl.ncomp, (T)-1);
+  // x forward + divergence: W -> q
+  if (dm == SP_DIV_SMALL)
+    hipLaunchKernelGGL((kb_strided<T, SP_DIV_SMALL>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
+                       BUF_W, BUF_Q, bl.ncomp, (T)-1);
+  else
+    hipLaunchKernelGGL((kb_strided<T, SP_DIV_FINITE>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
+                       BUF_W, BUF_Q, bl.ncomp, (T)-1);
+  hipLaunchKernelGGL((kb_alpha<T>), dim3(bl.ncell), vs, 0, st, D, bl.boff_z);
+  hipLaunchKernelGGL((kb_update<T>), dim3(bl.nbv), vs, 0, st, D, bl.boff_v, bl.ncell);
+  hipLaunchKernelGGL((kb_beta<T>), dim3(bl.ncell), vs, 0, st, D, bl.boff_v);
+  hipLaunchKernelGGL((kb_pupdate<T>), dim3(bl.nbv), vs, 0, st, D, bl.boff_v, bl.ncell);
+}
+
+template <typename T>
+void launch_batch_flags(const void* desc, int ncell, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL((kb_flags<T>), dim3(1), dim3(256), 0, st, static_cast<const CellDesc<T>*>(desc), ncell, flags);
+}
+
+template void launch_batch_iteration<double>(const BatchLaunch&, const void*, hipStream_t);
+template void launch_batch_iteration<float>(const BatchLaunch&, const void*, hipStream_t);
+template void launch_batch_flags<double>(const void*, int, int*, hipStream_t);
+template void launch_batch_flags<float>(const void*, int, int*, hipStream_t);
+
+// timing helper of the tile autotuner: one plain y or x pass of a cell
+template <typename T>
+__global__ __launch_bounds__(kStridedThreads) void kb_tune(CellDesc<T> R, int axis, int TZ, T d) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Geom& g = R.g;
+  StridedGeom sg;
+  int tile, o;
+  const int nt = (g.nh3 + TZ - 1) / TZ;
+  tile = blockIdx.x % nt;
+  o = blockIdx.x / nt;
+  if (axis == 0) {
+    sg.nline = g.n1;
+    sg.lstride = (long long)g.n2 * g.nh3;
+    sg.ostride = g.nh3;
+    sg.nother = g.n2;
+  } else {
+    sg.nline = g.n2;
+    sg.lstride = g.nh3;
+    sg.ostride = (long long)g.n2 * g.nh3;
+    sg.nother = g.n1;
+  }
+  sg.ncols = g.nh3;
+  sg.cstride_in = g.nh;
+  sg.cstride_out = g.nh;
+  strided_core<T, SP_PLAIN>(R.W, R.W, sg, g, axis == 0 ? R.p1 : R.p2, axis == 0 ? R.tw1 : R.tw2, d, TZ, nullptr, tile,
+                            o, 0, smem_raw);
+}
+
+template <typename T>
+float tune_strided_ms(const CellDesc<T>& R, int axis, int TZ, hipStream_t st, int reps) {
+  const Geom& g = R.g;
+  const int n = axis == 0 ? g.n1 : g.n2;
+  const int nother = axis == 0 ? g.n2 : g.n1;
+  const int nt = (g.nh3 + TZ - 1) / TZ;
+  const size_t shm = (size_t)(n + 2 * n * TZ) * sizeof(cpx<T>);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.f;
+  }
+  hipLaunchKernelGGL((kb_tune<T>), dim3(nt * nother), dim3(kStridedThreads), shm, st, R, axis, TZ, (T)1);
+  (void)hipEventRecord(e0, st);
+  for (int i = 0; i < reps; ++i)
+    hipLaunchKernelGGL((kb_tune<T>), dim3(nt * nother), dim3(kStridedThreads), shm, st, R, axis, TZ, (T)1);
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  float ms = -1.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+template float tune_strided_ms<double>(const CellDesc<double>&, int, int, hipStream_t, int);
+template float tune_strided_ms<float>(const CellDesc<float>&, int, int, hipStream_t, int);
+
+}  // namespace dbfft

@@ -153,7 +153,7 @@ template <typename T>
 void launch_pcg_pupdate(void* p, const void* r, const PcgScalars* sc, const PrecondArgs& pa,
                         const Geom& g, int nblocks, hipStream_t st);
 template <typename T>
-void launch_precond_init(void* p, const void* r, const PrecondArgs& pa, const Geom& g, double* partials,
+void launch_precond_init(void* p, void* r, const PrecondArgs& pa, const Geom& g, double* partials,
                          int nblocks, hipStream_t st);
 void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                       hipStream_t st);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -16,6 +17,7 @@
 
 #include "../../include/dbfft.h"
 #include "dbfft_internal.h"
+#include "batch.h"
 
 namespace dbfft {
 
@@ -566,10 +568,11 @@ struct PcgOut {
   double xe[kMaxMacro];
 };
 
-// Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
+// Sets x = 0, the scalars (<sigma> of the field that produced b, macro
+// residual), p = M r and <r, M r>; b is in r (precision T).  Synchronizes.
 template <typename T>
-static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r,
-                      void* p, void* q, const double sig0[9], const double re0[kMaxMacro], int check_every) {
+static void pcg_begin(Ctx& c, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r, void* p,
+                      const double sig0[9], const double re0[kMaxMacro]) {
   const size_t vbytes = 3 * (size_t)c.g.nh * 2 * sizeof(T);
   HIPCK(hipMemsetAsync(x, 0, vbytes, c.st));
   PcgScalars& h = *c.sc_host;
@@ -578,11 +581,34 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
   for (int a = 0; a < kMaxMacro; ++a) h.re[a] = re0[a];
   HIPCK(hipMemcpyAsync(c.sc_dev, c.sc_host, sizeof(PcgScalars), hipMemcpyHostToDevice, c.st));
   const int nb = pcg_block_count(c.g);
-  const int neb = energy_blocks<T>(c, tan.kind);
   launch_precond_init<T>(p, r, pa, c.g, c.partB, nb, c.st);
   launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 1, c.st);
   HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
   HIPCK(hipStreamSynchronize(c.st));
+}
+
+static PcgOut pcg_result(Ctx& c) {
+  const PcgScalars& h = *c.sc_host;
+  if (g_verbose)
+    std::fprintf(stderr, "[dbfft] pcg: iters %d status %d eq %.3e load %.3e rz %.3e pq %.3e\n", h.iter, h.converged,
+                 h.eq_res, h.load_res, h.rz, h.pq);
+  PcgOut o;
+  o.iters = h.iter;
+  o.status = h.converged;
+  o.eq = h.eq_res;
+  o.ld = h.load_res;
+  for (int i = 0; i < 9; ++i) o.sig[i] = h.sig[i];
+  for (int a = 0; a < kMaxMacro; ++a) o.xe[a] = h.xe[a];
+  return o;
+}
+
+// Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
+template <typename T>
+static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r,
+                      void* p, void* q, const double sig0[9], const double re0[kMaxMacro], int check_every) {
+  pcg_begin<T>(c, pa, pc, x, r, p, sig0, re0);
+  const int nb = pcg_block_count(c.g);
+  const int neb = energy_blocks<T>(c, tan.kind);
   const double* pmac = reinterpret_cast<const double*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, pmac));
   const int* stop = reinterpret_cast<const int*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, converged));
   if (check_every < 1) check_every = 1;
@@ -607,17 +633,7 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
     HIPCK(hipStreamSynchronize(c.st));
     if (c.prof_on) prof_collect(c, c.sc_host->iter - iter0 - (c.sc_host->converged ? 1 : 0));
   }
-  if (g_verbose)
-    std::fprintf(stderr, "[dbfft] pcg: iters %d status %d eq %.3e load %.3e rz %.3e pq %.3e\n", h.iter, h.converged,
-                 h.eq_res, h.load_res, h.rz, h.pq);
-  PcgOut o;
-  o.iters = h.iter;
-  o.status = h.converged;
-  o.eq = h.eq_res;
-  o.ld = h.load_res;
-  for (int i = 0; i < 9; ++i) o.sig[i] = h.sig[i];
-  for (int a = 0; a < kMaxMacro; ++a) o.xe[a] = h.xe[a];
-  return o;
+  return pcg_result(c);
 }
 
 // ------------------------------------------------------------------ linear solve
@@ -710,7 +726,7 @@ static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const
       out.status = DBFFT_OK;
       break;
     }
-    if (it >= o.max_refine) {
+    if (it >= o.max_refine || out.iters >= o.max_iter) {
       out.status = DBFFT_ENOTCONV;
       break;
     }
@@ -730,10 +746,6 @@ static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const
     launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
     launch_axpby<double>(sol_out, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
     for (int a = 0; a < ms.nS; ++a) e[a] += po.xe[a];
-    if (out.iters >= o.max_iter) {
-      out.status = DBFFT_ENOTCONV;
-      // one more residual evaluation happens at the loop top
-    }
   }
   return out;
 }
@@ -793,143 +805,213 @@ static double max_abs_diff(Ctx& c, const double* a, const double* b, long long n
   return m;
 }
 
-static int newton_solve(Ctx& c, const double load_rm[9], const int mask[9], int ninc, double dt,
-                        const dbfft_opts& o, dbfft_info& info) {
-  const MacroSet ms = macro_set(c, mask);
-  const size_t v64 = 3 * (size_t)c.g.nh * 2 * sizeof(double);
-  const long long nf = (long long)c.ncomp * c.g.nvox;
+// Newton state of one cell (Sec. 2.4): the increments of the load path, the
+// macro unknown e on the stress-controlled set, the preconditioner of the
+// current mean tangent and the bookkeeping of the current increment.
+struct NewtonState {
+  MacroSet ms;
+  int mask[9];
+  double load_rm[9];
+  int ninc = 1;
+  double dt = 1.0;
+  dbfft_opts o;
   double e[kMaxMacro] = {0};
-  HIPCK(hipMemsetAsync(c.sol, 0, v64, c.st));
-  if (c.mat == DBFFT_MAT_J2VP_CUBIC) HIPCK(hipMemsetAsync(c.state, 0, 6 * c.g.nvox * sizeof(double), c.st));
+  double EU[9] = {0};
+  double sbar[kMaxMacro] = {0};
+  double sig_st[9] = {0};
+  double re[kMaxMacro] = {0};
   PrecondArgs pa;
   PcgConst pc;
-  std::memset(&pc, 0, sizeof(pc));
   bool have_pre = false;
   int status = DBFFT_OK;
-  info.pcg_iters = info.newton_iters = info.increments = info.refine_steps = 0;
-  double sig_st[9] = {0}, EU[9] = {0};
-  for (int k = 1; k <= ninc && status == DBFFT_OK; ++k) {
-    const double frac = (double)k / (double)ninc;
-    double lrm[9], U_rm[9];
-    for (int i = 0; i < 9; ++i) {
-      double v = load_rm[i];
-      if (c.kin == KIN_FINITE && !mask[i] && (i % 4 == 0)) v -= 1.0;  // F - I
-      lrm[i] = frac * v;
-      U_rm[i] = mask[i] ? 0.0 : lrm[i];
-    }
-    rm_to_stored(c.kin, U_rm, EU);
-    double sbar[kMaxMacro] = {0};
-    double lst[9];
-    rm_to_stored(c.kin, lrm, lst);
-    for (int a = 0; a < ms.nS; ++a) sbar[a] = bdot(c.kin, ms.bst[a], lst);
-    auto macro_total = [&](double mt[9]) {
-      for (int i = 0; i < 9; ++i) mt[i] = EU[i];
-      for (int a = 0; a < ms.nS; ++a)
-        for (int i = 0; i < 9; ++i) mt[i] += e[a] * ms.bst[a][i];
-    };
-    double mt[9];
-    macro_total(mt);
-    set_macro(c, mt);
-    strain_field(c, c.sol, c.mac_dev, c.fa);
-    double dmax = INFINITY;
-    bool conv = false;
-    for (int i = 0;; ++i) {
-      material_update(c, c.fa, c.fc, dt);
-      if (!have_pre || (i == 0 && o.refresh == 0)) {
-        double C4[81];
-        mean_tangent(c, C4);
-        build_precond(c, C4, ms, pa, pc);
-        have_pre = true;
-      }
-      stress_residual(c, c.fc, c.t64, c.dc_dev);
-      read_dc(c, sig_st);
-      double re[kMaxMacro] = {0};
-      for (int a = 0; a < ms.nS; ++a) re[a] = sbar[a] - bdot(c.kin, ms.bst[a], sig_st);
-      if (g_verbose) {
-        double rl = 0.0;
-        for (int a = 0; a < ms.nS; ++a) rl += re[a] * re[a];
-        std::fprintf(stderr, "[dbfft] newton inc %d it %d dmax %.3e |r_e| %.3e sig0 %.4e\n", k, i, dmax,
-                     std::sqrt(rl), sig_st[0]);
-      }
-      if (i > 0 && dmax < o.newton_tol) {
-        conv = true;
-        break;
-      }
-      if (i >= o.max_newton) break;
-      pc.tol = o.tol;
-      pc.tol_load = o.tol_load;
-      pc.max_iter = o.max_iter;
-      PcgOut po;
-      if (c.prec == DBFFT_FP64) {
-        HIPCK(hipMemcpyAsync(c.r, c.t64, v64, hipMemcpyDeviceToDevice, c.st));
-        TangentArgs<double> tan = elastic_tangent<double>(c);
-        po = run_pcg<double>(c, tan, pa, pc, c.x, c.r, c.p, c.q, sig_st, re, o.check_every);
-        launch_axpby<double>(c.sol, c.x, 1.0, 1.0, 6 * c.g.nh, c.st);
-      } else {
-        launch_convert<double, float>(c.r, c.t64, 6 * c.g.nh, c.st);
-        TangentArgs<float> tan = elastic_tangent<float>(c);
-        po = run_pcg<float>(c, tan, pa, pc, c.x, c.r, c.p, c.q, sig_st, re, o.check_every);
-        launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
-        launch_axpby<double>(c.sol, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
-      }
-      info.pcg_iters += po.iters;
-      info.newton_iters += 1;
-      if (po.status == 2) {
-        status = DBFFT_EBREAKDOWN;
-        break;
-      }
-      if (po.status == 3) {
-        status = DBFFT_ENOTCONV;
-        break;
-      }
-      for (int a = 0; a < ms.nS; ++a) e[a] += po.xe[a];
-      macro_total(mt);
-      set_macro(c, mt);
-      std::swap(c.fa, c.fb);
-      strain_field(c, c.sol, c.mac_dev, c.fa);
-      dmax = max_abs_diff(c, c.fa, c.fb, nf);
-    }
-    if (status != DBFFT_OK) break;
-    if (!conv) {
-      status = DBFFT_ENOTCONV;
-      break;
-    }
-    if (c.mat == DBFFT_MAT_J2VP_CUBIC) std::swap(c.state, c.state_new);
-    info.increments += 1;
+  int k = 0, i = 0;
+  double dmax = INFINITY;
+  bool conv = false;
+  dbfft_info info;
+};
+
+static void macro_total(const Ctx& c, const NewtonState& S, double mt[9]) {
+  for (int i = 0; i < 9; ++i) mt[i] = S.EU[i];
+  for (int a = 0; a < S.ms.nS; ++a)
+    for (int i = 0; i < 9; ++i) mt[i] += S.e[a] * S.ms.bst[a][i];
+  (void)c;
+}
+
+static void newton_init(Ctx& c, NewtonState& S, const double load_rm[9], const int mask[9], int ninc, double dt,
+                        const dbfft_opts& o) {
+  S.ms = macro_set(c, mask);
+  for (int i = 0; i < 9; ++i) {
+    S.mask[i] = mask[i];
+    S.load_rm[i] = load_rm[i];
   }
-  // final state: residuals and averages
+  S.ninc = ninc;
+  S.dt = dt;
+  S.o = o;
+  std::memset(&S.pc, 0, sizeof(S.pc));
+  std::memset(&S.info, 0, sizeof(S.info));
+  HIPCK(hipMemsetAsync(c.sol, 0, 3 * (size_t)c.g.nh * 2 * sizeof(double), c.st));
+  if (c.mat == DBFFT_MAT_J2VP_CUBIC) HIPCK(hipMemsetAsync(c.state, 0, 6 * c.g.nvox * sizeof(double), c.st));
+}
+
+// prescribed parts of increment k, strain field of the current iterate
+static void newton_begin_increment(Ctx& c, NewtonState& S, int k) {
+  S.k = k;
+  S.i = 0;
+  S.dmax = INFINITY;
+  S.conv = false;
+  const double frac = (double)k / (double)S.ninc;
+  double lrm[9], U_rm[9];
+  for (int i = 0; i < 9; ++i) {
+    double v = S.load_rm[i];
+    if (c.kin == KIN_FINITE && !S.mask[i] && (i % 4 == 0)) v -= 1.0;  // F - I
+    lrm[i] = frac * v;
+    U_rm[i] = S.mask[i] ? 0.0 : lrm[i];
+  }
+  rm_to_stored(c.kin, U_rm, S.EU);
+  double lst[9];
+  rm_to_stored(c.kin, lrm, lst);
+  for (int a = 0; a < S.ms.nS; ++a) S.sbar[a] = bdot(c.kin, S.ms.bst[a], lst);
+  double mt[9];
+  macro_total(c, S, mt);
+  set_macro(c, mt);
+  strain_field(c, c.sol, c.mac_dev, c.fa);
+}
+
+// constitutive update, preconditioner refresh and residual at the current
+// iterate.  Returns 1 when the Newton test passes, 0 when a linear
+// correction is needed, -1 when the Newton cap is reached.
+static int newton_evaluate(Ctx& c, NewtonState& S) {
+  material_update(c, c.fa, c.fc, S.dt);
+  if (!S.have_pre || (S.i == 0 && S.o.refresh == 0)) {
+    double C4[81];
+    mean_tangent(c, C4);
+    build_precond(c, C4, S.ms, S.pa, S.pc);
+    S.have_pre = true;
+  }
+  stress_residual(c, c.fc, c.t64, c.dc_dev);
+  read_dc(c, S.sig_st);
+  for (int a = 0; a < kMaxMacro; ++a) S.re[a] = 0.0;
+  for (int a = 0; a < S.ms.nS; ++a) S.re[a] = S.sbar[a] - bdot(c.kin, S.ms.bst[a], S.sig_st);
+  if (g_verbose) {
+    double rl = 0.0;
+    for (int a = 0; a < S.ms.nS; ++a) rl += S.re[a] * S.re[a];
+    std::fprintf(stderr, "[dbfft] newton inc %d it %d dmax %.3e |r_e| %.3e sig0 %.4e\n", S.k, S.i, S.dmax,
+                 std::sqrt(rl), S.sig_st[0]);
+  }
+  if (S.i > 0 && S.dmax < S.o.newton_tol) {
+    S.conv = true;
+    return 1;
+  }
+  if (S.i >= S.o.max_newton) return -1;
+  S.pc.tol = S.o.tol;
+  S.pc.tol_load = S.o.tol_load;
+  S.pc.max_iter = S.o.max_iter;
+  // right-hand side of the linear correction in the PCG precision
+  if (c.prec == DBFFT_FP64)
+    HIPCK(hipMemcpyAsync(c.r, c.t64, 3 * (size_t)c.g.nh * 2 * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+  else
+    launch_convert<double, float>(c.r, c.t64, 6 * c.g.nh, c.st);
+  return 0;
+}
+
+// adds the PCG correction (in c.x) and re-evaluates the strain field
+static void newton_apply_correction(Ctx& c, NewtonState& S, const PcgOut& po) {
+  S.info.pcg_iters += po.iters;
+  S.info.newton_iters += 1;
+  if (po.status == 2) {
+    S.status = DBFFT_EBREAKDOWN;
+    return;
+  }
+  if (po.status == 3) {
+    S.status = DBFFT_ENOTCONV;
+    return;
+  }
+  if (c.prec == DBFFT_FP64) {
+    launch_axpby<double>(c.sol, c.x, 1.0, 1.0, 6 * c.g.nh, c.st);
+  } else {
+    launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
+    launch_axpby<double>(c.sol, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
+  }
+  for (int a = 0; a < S.ms.nS; ++a) S.e[a] += po.xe[a];
+  double mt[9];
+  macro_total(c, S, mt);
+  set_macro(c, mt);
+  std::swap(c.fa, c.fb);
+  strain_field(c, c.sol, c.mac_dev, c.fa);
+  S.dmax = max_abs_diff(c, c.fa, c.fb, (long long)c.ncomp * c.g.nvox);
+  S.i += 1;
+}
+
+static void newton_end_increment(Ctx& c, NewtonState& S) {
+  if (c.mat == DBFFT_MAT_J2VP_CUBIC) std::swap(c.state, c.state_new);
+  S.info.increments += 1;
+}
+
+// residuals and averages of the final state into the context and info
+static void newton_finish(Ctx& c, NewtonState& S) {
   const double ra = std::sqrt(std::max(dot64(c, c.t64, c.t64), 0.0));
-  const double nrm = frob_stored(c.kin, sig_st);
-  info.eq_res = nrm > 0 ? ra / nrm : 0.0;
+  const double nrm = frob_stored(c.kin, S.sig_st);
+  S.info.eq_res = nrm > 0 ? ra / nrm : 0.0;
   double rl = 0.0;
   {
     double lrm[9], lst[9];
-    const double frac = (double)std::max(info.increments, 1) / (double)ninc;
-    for (int i = 0; i < 9; ++i) lrm[i] = frac * load_rm[i];
+    const double frac = (double)std::max(S.info.increments, 1) / (double)S.ninc;
+    for (int i = 0; i < 9; ++i) lrm[i] = frac * S.load_rm[i];
     rm_to_stored(c.kin, lrm, lst);
-    for (int a = 0; a < ms.nS; ++a) {
-      const double d = bdot(c.kin, ms.bst[a], lst) - bdot(c.kin, ms.bst[a], sig_st);
+    for (int a = 0; a < S.ms.nS; ++a) {
+      const double d = bdot(c.kin, S.ms.bst[a], lst) - bdot(c.kin, S.ms.bst[a], S.sig_st);
       rl += d * d;
     }
   }
-  info.load_res = nrm > 0 ? std::sqrt(rl) / nrm : 0.0;
-  double et[9];
-  for (int i = 0; i < 9; ++i) et[i] = 0.0;
-  for (int a = 0; a < ms.nS; ++a)
-    for (int i = 0; i < 9; ++i) et[i] += e[a] * ms.bst[a][i];
+  S.info.load_res = nrm > 0 ? std::sqrt(rl) / nrm : 0.0;
+  double et[9] = {0};
+  for (int a = 0; a < S.ms.nS; ++a)
+    for (int i = 0; i < 9; ++i) et[i] += S.e[a] * S.ms.bst[a][i];
   for (int i = 0; i < 9; ++i) c.e_st[i] = et[i];
-  for (int i = 0; i < 9; ++i) c.EU_st[i] = EU[i];
+  for (int i = 0; i < 9; ++i) c.EU_st[i] = S.EU[i];
   double avg_st[9];
-  for (int i = 0; i < 9; ++i) avg_st[i] = EU[i] + et[i];
-  stored_to_rm(c.kin, sig_st, c.sig_rm);
+  for (int i = 0; i < 9; ++i) avg_st[i] = S.EU[i] + et[i];
+  stored_to_rm(c.kin, S.sig_st, c.sig_rm);
   stored_to_rm(c.kin, avg_st, c.eps_rm);
   if (c.kin == KIN_FINITE)
     for (int i = 0; i < 9; i += 4) c.eps_rm[i] += 1.0;  // <F> = I + <H>
   for (int i = 0; i < 9; ++i) {
-    info.sigma_bar[i] = c.sig_rm[i];
-    info.eps_bar[i] = c.eps_rm[i];
+    S.info.sigma_bar[i] = c.sig_rm[i];
+    S.info.eps_bar[i] = c.eps_rm[i];
   }
-  return status;
+  S.info.status = S.status;
+}
+
+static int newton_solve(Ctx& c, const double load_rm[9], const int mask[9], int ninc, double dt,
+                        const dbfft_opts& o, dbfft_info& info) {
+  NewtonState S;
+  newton_init(c, S, load_rm, mask, ninc, dt, o);
+  for (int k = 1; k <= ninc && S.status == DBFFT_OK; ++k) {
+    newton_begin_increment(c, S, k);
+    for (;;) {
+      const int ev = newton_evaluate(c, S);
+      if (ev == 1) break;
+      if (ev < 0) {
+        S.status = DBFFT_ENOTCONV;
+        break;
+      }
+      PcgOut po;
+      if (c.prec == DBFFT_FP64) {
+        TangentArgs<double> tan = elastic_tangent<double>(c);
+        po = run_pcg<double>(c, tan, S.pa, S.pc, c.x, c.r, c.p, c.q, S.sig_st, S.re, o.check_every);
+      } else {
+        TangentArgs<float> tan = elastic_tangent<float>(c);
+        po = run_pcg<float>(c, tan, S.pa, S.pc, c.x, c.r, c.p, c.q, S.sig_st, S.re, o.check_every);
+      }
+      newton_apply_correction(c, S, po);
+      if (S.status != DBFFT_OK) break;
+    }
+    if (S.status != DBFFT_OK) break;
+    newton_end_increment(c, S);
+  }
+  newton_finish(c, S);
+  info = S.info;
+  return S.status;
 }
 
 // ------------------------------------------------------------------ setup
@@ -1166,6 +1248,448 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
     c->fail_dev = static_cast<int*>(dalloc(sizeof(int)));
     HIPCK(hipStreamSynchronize(c->st));
   }
+}
+
+// ------------------------------------------------------------------ batches
+// A batch groups contexts of one precision and kinematics (any grid sizes).
+// Every batched PCG iteration is one launch per pass over all cells; a
+// chunk of iterations is captured once in a HIP graph and replayed.
+struct Batch {
+  std::vector<Ctx*> cells;
+  int prec = 0, kin = 0, ncomp = 6;
+  hipStream_t st = nullptr;  // own stream (graph capture needs a non-null stream)
+  void* desc_dev = nullptr;
+  size_t desc_size = 0;
+  std::vector<unsigned char> desc_host;
+  int* boff_dev = nullptr;
+  BatchLaunch bl;
+  int* flags_dev = nullptr;
+  int* flags_host = nullptr;
+  bool use_graph = true;
+  int chunk = 8, graph_chunk = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> tzx, tzy, L;
+};
+
+template <typename T>
+static void fill_desc(Batch& B, int r, CellDesc<T>& D) {
+  Ctx& c = *B.cells[r];
+  Tables<T>& tb = tables<T>(c);
+  D.g = c.g;
+  D.p1 = c.p1;
+  D.p2 = c.p2;
+  D.p3 = c.p3;
+  D.tw1 = static_cast<const cpx<T>*>(tb.tw1);
+  D.tw2 = static_cast<const cpx<T>*>(tb.tw2);
+  D.tw3 = static_cast<const cpx<T>*>(tb.tw3);
+  D.rtw = static_cast<const cpx<T>*>(tb.rtw);
+  D.W = static_cast<cpx<T>*>(c.W);
+  D.x = static_cast<cpx<T>*>(c.x);
+  D.r = static_cast<cpx<T>*>(c.r);
+  D.p = static_cast<cpx<T>*>(c.p);
+  D.q = static_cast<cpx<T>*>(c.q);
+  D.tan = elastic_tangent<T>(c);
+  D.sc = c.sc_dev;
+  D.partA = c.partA;
+  D.partB = c.partB;
+  D.dc = c.dc_dev;
+  D.tzx = B.tzx[r];
+  D.tzy = B.tzy[r];
+  D.L = B.L[r];
+  D.pad = 0;
+}
+
+template <typename T>
+static void batch_build(Batch& B) {
+  const int n = (int)B.cells.size();
+  B.desc_size = sizeof(CellDesc<T>);
+  B.desc_host.assign(B.desc_size * n, 0);
+  const int eb = (int)(2 * sizeof(T));
+  B.tzx.assign(n, 8);
+  B.tzy.assign(n, 8);
+  B.L.assign(n, 1);
+  std::vector<int> bx(n + 1, 0), by(n + 1, 0), bz(n + 1, 0), bv(n + 1, 0);
+  size_t lx = 0, ly = 0, lz = 0;
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    B.L[r] = line_lines_per_block(c.g, c.ncomp, eb);
+  }
+  // tile autotuner: time one plain pass per candidate column-tile width
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    int reuse = -1;
+    for (int q = 0; q < r; ++q)
+      if (B.cells[q]->n[0] == c.n[0] && B.cells[q]->n[1] == c.n[1] && B.cells[q]->n[2] == c.n[2]) reuse = q;
+    if (reuse >= 0) {
+      B.tzx[r] = B.tzx[reuse];
+      B.tzy[r] = B.tzy[reuse];
+      continue;
+    }
+    CellDesc<T> D;
+    std::memset(&D, 0, sizeof(D));
+    fill_desc<T>(B, r, D);
+    for (int axis = 0; axis < 2; ++axis) {
+      const int nl = axis == 0 ? c.n[0] : c.n[1];
+      float best = -1.f;
+      int best_tz = 1;
+      for (int tz : {2, 4, 8, 16, 32}) {
+        if (tz > 2 * c.g.nh3 && tz > 2) continue;
+        if ((size_t)(nl + 2 * nl * tz) * eb > 64 * 1024) continue;
+        if (axis == 0 && nl * tz > 8 * 256) continue;  // register budget of the fused x modes
+        const float ms = tune_strided_ms<T>(D, axis, tz, B.st, 3);
+        if (ms > 0.f && (best < 0.f || ms < best)) {
+          best = ms;
+          best_tz = tz;
+        }
+      }
+      (axis == 0 ? B.tzx : B.tzy)[r] = best_tz;
+    }
+  }
+  HIPCK(hipGetLastError());
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    const int ntx = (c.g.nh3 + B.tzx[r] - 1) / B.tzx[r];
+    const int nty = (c.g.nh3 + B.tzy[r] - 1) / B.tzy[r];
+    bx[r + 1] = bx[r] + ntx * c.n[1];
+    by[r + 1] = by[r] + nty * c.n[0] * c.ncomp;
+    bz[r + 1] = bz[r] + (int)(((long long)c.n[0] * c.n[1] + B.L[r] - 1) / B.L[r]);
+    bv[r + 1] = bv[r] + pcg_block_count(c.g);
+    lx = std::max(lx, (size_t)(c.n[0] + 2 * c.n[0] * B.tzx[r]) * eb);
+    ly = std::max(ly, (size_t)(c.n[1] + 2 * c.n[1] * B.tzy[r]) * eb);
+    const size_t M = c.g.n3 / 2;
+    lz = std::max(lz, (size_t)(2 * M + 1) * eb + (size_t)2 * M * B.L[r] * eb + (size_t)(M + 1) * B.L[r] * eb +
+                          (size_t)c.ncomp * B.L[r] * c.g.n3 * sizeof(T));
+  }
+  std::vector<int> boff;
+  boff.insert(boff.end(), bx.begin(), bx.end());
+  boff.insert(boff.end(), by.begin(), by.end());
+  boff.insert(boff.end(), bz.begin(), bz.end());
+  boff.insert(boff.end(), bv.begin(), bv.end());
+  B.boff_dev = static_cast<int*>(dalloc(boff.size() * sizeof(int)));
+  HIPCK(hipMemcpy(B.boff_dev, boff.data(), boff.size() * sizeof(int), hipMemcpyHostToDevice));
+  B.bl.ncell = n;
+  B.bl.kin = B.kin;
+  B.bl.ncomp = B.ncomp;
+  B.bl.nbx_f = bx[n];
+  B.bl.nby = by[n];
+  B.bl.nbz = bz[n];
+  B.bl.nbv = bv[n];
+  B.bl.boff_xf = B.boff_dev;
+  B.bl.boff_y = B.boff_dev + (n + 1);
+  B.bl.boff_z = B.boff_dev + 2 * (n + 1);
+  B.bl.boff_v = B.boff_dev + 3 * (n + 1);
+  B.bl.lds_x = lx;
+  B.bl.lds_y = ly;
+  B.bl.lds_z = lz;
+  B.desc_dev = dalloc(B.desc_host.size());
+  B.flags_dev = static_cast<int*>(dalloc(n * sizeof(int)));
+  HIPCK(hipHostMalloc((void**)&B.flags_host, n * sizeof(int), hipHostMallocDefault));
+}
+
+// descriptors with the current tangents and the per-cell preconditioners
+template <typename T>
+static void batch_upload(Batch& B, const std::vector<PrecondArgs>& pa, const std::vector<PcgConst>& pc) {
+  const int n = (int)B.cells.size();
+  for (int r = 0; r < n; ++r) {
+    CellDesc<T>* D = reinterpret_cast<CellDesc<T>*>(B.desc_host.data() + r * B.desc_size);
+    fill_desc<T>(B, r, *D);
+    D->pa = pa[r];
+    D->pc = pc[r];
+  }
+  HIPCK(hipMemcpyAsync(B.desc_dev, B.desc_host.data(), B.desc_host.size(), hipMemcpyHostToDevice, B.st));
+  HIPCK(hipStreamSynchronize(B.st));
+}
+
+// batched PCG: cells with active[r] != 0 solve K x = b (b in their r);
+// the others are marked converged and skipped by every kernel
+template <typename T>
+static std::vector<PcgOut> batch_pcg(Batch& B, const std::vector<int>& active, const std::vector<PrecondArgs>& pa,
+                                     const std::vector<PcgConst>& pc, const std::vector<std::array<double, 9>>& sig0,
+                                     const std::vector<std::array<double, kMaxMacro>>& re0) {
+  const int n = (int)B.cells.size();
+  batch_upload<T>(B, pa, pc);
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    if (active[r]) {
+      pcg_begin<T>(c, pa[r], pc[r], c.x, c.r, c.p, sig0[r].data(), re0[r].data());
+    } else {
+      std::memset(c.sc_host, 0, sizeof(PcgScalars));
+      c.sc_host->converged = 1;
+      HIPCK(hipMemcpyAsync(c.sc_dev, c.sc_host, sizeof(PcgScalars), hipMemcpyHostToDevice, c.st));
+      HIPCK(hipStreamSynchronize(c.st));
+    }
+  }
+  auto all_done = [&]() {
+    launch_batch_flags<T>(B.desc_dev, n, B.flags_dev, B.st);
+    HIPCK(hipMemcpyAsync(B.flags_host, B.flags_dev, n * sizeof(int), hipMemcpyDeviceToHost, B.st));
+    HIPCK(hipStreamSynchronize(B.st));
+    for (int r = 0; r < n; ++r)
+      if (!B.flags_host[r]) return false;
+    return true;
+  };
+  if (B.use_graph && B.exec != nullptr && B.graph_chunk != B.chunk) {
+    HIPCK(hipGraphExecDestroy(B.exec));
+    HIPCK(hipGraphDestroy(B.graph));
+    B.exec = nullptr;
+    B.graph = nullptr;
+  }
+  if (B.use_graph && B.exec == nullptr) {
+    B.graph_chunk = B.chunk;
+    HIPCK(hipStreamBeginCapture(B.st, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < B.chunk; ++k) launch_batch_iteration<T>(B.bl, B.desc_dev, B.st);
+    HIPCK(hipStreamEndCapture(B.st, &B.graph));
+    HIPCK(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+  }
+  while (!all_done()) {
+    if (B.use_graph) {
+      HIPCK(hipGraphLaunch(B.exec, B.st));
+    } else {
+      for (int k = 0; k < B.chunk; ++k) launch_batch_iteration<T>(B.bl, B.desc_dev, B.st);
+    }
+    HIPCK(hipGetLastError());
+  }
+  std::vector<PcgOut> out(n);
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
+    HIPCK(hipStreamSynchronize(c.st));
+    out[r] = pcg_result(c);
+  }
+  return out;
+}
+
+template <typename T>
+static std::vector<int> batch_solve_t(Batch& B, const double* loads, const uint8_t* masks, int ninc, double dt,
+                                      const dbfft_opts& o, dbfft_info* infos) {
+  const int n = (int)B.cells.size();
+  std::vector<int> status(n, DBFFT_OK);
+  std::vector<PrecondArgs> pa(n);
+  std::vector<PcgConst> pc(n);
+  std::vector<std::array<double, 9>> sig0(n);
+  std::vector<std::array<double, kMaxMacro>> re0(n);
+  std::vector<int> active(n, 0);
+  B.chunk = std::max(1, o.check_every);
+  const bool linear = B.cells[0]->linear_material();
+  if (linear) {
+    // single batched PCG per refinement step (one step in FP64)
+    std::vector<MacroSet> ms(n);
+    std::vector<std::array<double, kMaxMacro>> sbar(n), e(n), re_b(n);
+    std::vector<std::array<double, 9>> dc0(n);
+    std::vector<double> eqv(n, INFINITY), ldv(n, INFINITY);
+    std::vector<int> iters(n, 0), refine(n, 0), done(n, 0);
+    for (int r = 0; r < n; ++r) {
+      Ctx& c = *B.cells[r];
+      int mask[9];
+      for (int i = 0; i < 9; ++i) mask[i] = masks[9 * r + i] ? 1 : 0;
+      for (int i = 0; i < 9; ++i) c.last_mask[i] = mask[i];
+      ms[r] = macro_set(c, mask);
+      double U_rm[9], lst[9];
+      for (int i = 0; i < 9; ++i) U_rm[i] = mask[i] ? 0.0 : loads[9 * r + i];
+      rm_to_stored(c.kin, U_rm, c.EU_st);
+      rm_to_stored(c.kin, loads + 9 * r, lst);
+      sbar[r].fill(0.0);
+      e[r].fill(0.0);
+      for (int a = 0; a < ms[r].nS; ++a) sbar[r][a] = bdot(c.kin, ms[r].bst[a], lst);
+      double C4[81];
+      mean_tangent(c, C4);
+      std::memset(&pc[r], 0, sizeof(PcgConst));
+      build_precond(c, C4, ms[r], pa[r], pc[r]);
+      pc[r].tol = o.tol;
+      pc[r].tol_load = o.tol_load;
+      pc[r].max_iter = o.max_iter;
+      TangentArgs<double> tan64 = elastic_tangent<double>(c);
+      set_macro(c, c.EU_st);
+      apply_const<double>(c, c.b, c.mac_dev, tan64, c.dc_dev);
+      launch_axpby<double>(c.b, c.b, 0.0, -1.0, 6 * c.g.nh, c.st);
+      double d0[9];
+      read_dc(c, d0);
+      for (int i = 0; i < 9; ++i) dc0[r][i] = d0[i];
+      re_b[r].fill(0.0);
+      for (int a = 0; a < ms[r].nS; ++a) re_b[r][a] = sbar[r][a] - bdot(c.kin, ms[r].bst[a], d0);
+      HIPCK(hipMemsetAsync(c.sol, 0, 3 * (size_t)c.g.nh * 2 * sizeof(double), c.st));
+      HIPCK(hipMemcpyAsync(c.t64, c.b, 3 * (size_t)c.g.nh * 2 * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+    }
+    for (int step = 0;; ++step) {
+      // residual of every unfinished cell (FP64), then one batched inner solve
+      bool any = false;
+      for (int r = 0; r < n; ++r) {
+        active[r] = 0;
+        if (done[r]) continue;
+        Ctx& c = *B.cells[r];
+        double sig[9];
+        std::array<double, kMaxMacro> re = re_b[r];
+        if (step == 0) {
+          for (int i = 0; i < 9; ++i) sig[i] = dc0[r][i];
+        } else {
+          double mt[9] = {0};
+          for (int a = 0; a < ms[r].nS; ++a)
+            for (int k = 0; k < 9; ++k) mt[k] += e[r][a] * ms[r].bst[a][k];
+          set_macro(c, mt);
+          TangentArgs<double> tan64 = elastic_tangent<double>(c);
+          apply_K<double>(c, c.sol, c.t64, c.mac_dev, nullptr, tan64, c.partA, c.dc_dev, nullptr);
+          launch_axpby<double>(c.t64, c.b, 1.0, -1.0, 6 * c.g.nh, c.st);
+          double dcx[9];
+          read_dc(c, dcx);
+          for (int i = 0; i < 9; ++i) sig[i] = dc0[r][i] + dcx[i];
+          for (int a = 0; a < ms[r].nS; ++a) re[a] = re_b[r][a] - bdot(c.kin, ms[r].bst[a], dcx);
+        }
+        const double nrm = frob_stored(c.kin, sig);
+        const double ra = std::sqrt(std::max(dot64(c, c.t64, c.t64), 0.0));
+        double rl = 0.0;
+        for (int a = 0; a < ms[r].nS; ++a) rl += re[a] * re[a];
+        rl = std::sqrt(rl);
+        eqv[r] = nrm > 0 ? ra / nrm : (ra == 0 ? 0.0 : INFINITY);
+        ldv[r] = nrm > 0 ? rl / nrm : (rl == 0 ? 0.0 : INFINITY);
+        if (eqv[r] < o.tol && ldv[r] < o.tol_load) {
+          done[r] = 1;
+          status[r] = DBFFT_OK;
+          continue;
+        }
+        if (refine[r] >= o.max_refine || iters[r] >= o.max_iter) {
+          done[r] = 1;
+          status[r] = DBFFT_ENOTCONV;
+          continue;
+        }
+        PcgConst pci = pc[r];
+        if (B.prec != DBFFT_FP64) {
+          pci.tol = std::max(eqv[r] * o.inner_tol, 0.5 * o.tol);
+          pci.tol_load = std::max(ldv[r] * o.inner_tol, 0.5 * o.tol_load);
+        }
+        pci.max_iter = std::max(1, o.max_iter - iters[r]);
+        pc[r] = pci;
+        for (int i = 0; i < 9; ++i) sig0[r][i] = sig[i];
+        re0[r] = re;
+        if (B.prec == DBFFT_FP64)
+          HIPCK(hipMemcpyAsync(c.r, c.t64, 3 * (size_t)c.g.nh * 2 * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+        else
+          launch_convert<double, float>(c.r, c.t64, 6 * c.g.nh, c.st);
+        active[r] = 1;
+        any = true;
+      }
+      if (!any) break;
+      std::vector<PcgOut> po = batch_pcg<T>(B, active, pa, pc, sig0, re0);
+      for (int r = 0; r < n; ++r) {
+        if (!active[r]) continue;
+        Ctx& c = *B.cells[r];
+        iters[r] += po[r].iters;
+        refine[r] += (B.prec == DBFFT_FP64) ? 0 : 1;
+        if (po[r].status == 2) {
+          status[r] = DBFFT_EBREAKDOWN;
+          done[r] = 1;
+          continue;
+        }
+        if (B.prec == DBFFT_FP64) {
+          // FP64: one PCG solves the system; its recurrence decides the status
+          HIPCK(hipMemcpyAsync(c.sol, c.x, 3 * (size_t)c.g.nh * 2 * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+          for (int a = 0; a < ms[r].nS; ++a) e[r][a] += po[r].xe[a];
+          status[r] = pcg_status(po[r].status);
+          done[r] = 1;
+          continue;
+        } else {
+          launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
+          launch_axpby<double>(c.sol, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
+        }
+        for (int a = 0; a < ms[r].nS; ++a) e[r][a] += po[r].xe[a];
+      }
+    }
+    for (int r = 0; r < n; ++r) {
+      Ctx& c = *B.cells[r];
+      for (int i = 0; i < 9; ++i) c.e_st[i] = 0.0;
+      for (int a = 0; a < ms[r].nS; ++a)
+        for (int i = 0; i < 9; ++i) c.e_st[i] += e[r][a] * ms[r].bst[a][i];
+      double mt[9], sig_st[9], eq, ld;
+      for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+      evaluate_linear(c, c.sol, mt, ms[r], sbar[r].data(), sig_st, eq, ld);
+      stored_to_rm(c.kin, sig_st, c.sig_rm);
+      stored_to_rm(c.kin, mt, c.eps_rm);
+      c.solved = true;
+      dbfft_info& inf = infos[r];
+      std::memset(&inf, 0, sizeof(inf));
+      inf.pcg_iters = iters[r];
+      inf.refine_steps = refine[r];
+      inf.increments = 1;
+      inf.eq_res = eq;
+      inf.load_res = ld;
+      inf.status = status[r];
+      for (int i = 0; i < 9; ++i) {
+        inf.sigma_bar[i] = c.sig_rm[i];
+        inf.eps_bar[i] = c.eps_rm[i];
+      }
+    }
+    return status;
+  }
+
+  // Newton in lockstep: every unfinished cell evaluates its residual, then
+  // one batched PCG solves all linear corrections
+  std::vector<NewtonState> S(n);
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    int mask[9];
+    for (int i = 0; i < 9; ++i) mask[i] = masks[9 * r + i] ? 1 : 0;
+    for (int i = 0; i < 9; ++i) c.last_mask[i] = mask[i];
+    newton_init(c, S[r], loads + 9 * r, mask, ninc, dt, o);
+  }
+  for (int k = 1; k <= ninc; ++k) {
+    std::vector<int> inc_done(n, 0);
+    for (int r = 0; r < n; ++r) {
+      if (S[r].status != DBFFT_OK) {
+        inc_done[r] = 1;
+        continue;
+      }
+      newton_begin_increment(*B.cells[r], S[r], k);
+    }
+    for (;;) {
+      bool any = false;
+      for (int r = 0; r < n; ++r) {
+        active[r] = 0;
+        if (inc_done[r]) continue;
+        const int ev = newton_evaluate(*B.cells[r], S[r]);
+        if (ev == 1) {
+          inc_done[r] = 1;
+          newton_end_increment(*B.cells[r], S[r]);
+          continue;
+        }
+        if (ev < 0) {
+          S[r].status = DBFFT_ENOTCONV;
+          inc_done[r] = 1;
+          continue;
+        }
+        pa[r] = S[r].pa;
+        pc[r] = S[r].pc;
+        for (int i = 0; i < 9; ++i) sig0[r][i] = S[r].sig_st[i];
+        for (int a = 0; a < kMaxMacro; ++a) re0[r][a] = S[r].re[a];
+        active[r] = 1;
+        any = true;
+      }
+      if (!any) break;
+      std::vector<PcgOut> po = batch_pcg<T>(B, active, pa, pc, sig0, re0);
+      for (int r = 0; r < n; ++r) {
+        if (!active[r]) continue;
+        newton_apply_correction(*B.cells[r], S[r], po[r]);
+        if (S[r].status != DBFFT_OK) inc_done[r] = 1;
+      }
+    }
+  }
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    newton_finish(c, S[r]);
+    c.solved = true;
+    infos[r] = S[r].info;
+    status[r] = S[r].status;
+  }
+  return status;
+}
+
+static void batch_release(Batch* B) {
+  if (B->st) (void)hipStreamSynchronize(B->st);
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->desc_dev) (void)hipFree(B->desc_dev);
+  if (B->boff_dev) (void)hipFree(B->boff_dev);
+  if (B->flags_dev) (void)hipFree(B->flags_dev);
+  if (B->flags_host) (void)hipHostFree(B->flags_host);
+  if (B->st) (void)hipStreamDestroy(B->st);
 }
 
 }  // namespace dbfft
@@ -1423,6 +1947,99 @@ dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_ba
   HIPCK(hipStreamSynchronize(c.st));
   return DBFFT_OK;
   API_END
+}
+
+struct dbfft_batch {
+  Batch impl;
+};
+
+dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int32_t ncell, int32_t use_graph) {
+  g_err.clear();
+  API_BEGIN
+  if (!out || !cells || ncell < 1) DB_THROW(DBFFT_EINVAL, "null argument or empty batch");
+  *out = nullptr;
+  for (int r = 0; r < ncell; ++r)
+    if (!cells[r]) DB_THROW(DBFFT_EINVAL, "null context in batch");
+  Ctx& c0 = *C(cells[0]);
+  for (int r = 1; r < ncell; ++r) {
+    Ctx& c = *C(cells[r]);
+    if (c.prec != c0.prec || c.kin != c0.kin || c.linear_material() != c0.linear_material())
+      DB_THROW(DBFFT_EINVAL, "batched contexts need one precision, one kinematics and one material class");
+  }
+  dbfft_batch* h = new dbfft_batch();
+  try {
+    Batch& B = h->impl;
+    for (int r = 0; r < ncell; ++r) B.cells.push_back(C(cells[r]));
+    B.prec = c0.prec;
+    B.kin = c0.kin;
+    B.ncomp = c0.ncomp;
+    B.use_graph = use_graph != 0;
+    for (int r = 0; r < ncell; ++r) HIPCK(hipStreamSynchronize(B.cells[r]->st));
+    HIPCK(hipStreamCreateWithFlags(&B.st, hipStreamNonBlocking));
+    if (B.prec == DBFFT_FP64) batch_build<double>(B);
+    else batch_build<float>(B);
+  } catch (...) {
+    batch_release(&h->impl);
+    delete h;
+    throw;
+  }
+  *out = h;
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_t* stress_masks, int32_t n_increments,
+                               double dt, const dbfft_opts* opts, dbfft_info* infos) {
+  g_err.clear();
+  API_BEGIN
+  if (!b || !loads || !stress_masks || !infos) DB_THROW(DBFFT_EINVAL, "null argument");
+  Batch& B = b->impl;
+  const int n = (int)B.cells.size();
+  dbfft_opts o;
+  if (opts) o = *opts;
+  else dbfft_default_opts(&o);
+  for (int r = 0; r < n; ++r) {
+    const Ctx& c = *B.cells[r];
+    if (c.kin == KIN_SMALL)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          if ((stress_masks[9 * r + i * 3 + j] != 0) != (stress_masks[9 * r + j * 3 + i] != 0))
+            DB_THROW(DBFFT_EINVAL, "small strains need a symmetric stress mask");
+          if (loads[9 * r + i * 3 + j] != loads[9 * r + j * 3 + i]) DB_THROW(DBFFT_EINVAL, "small strains need a symmetric load");
+        }
+  }
+  if (!B.cells[0]->linear_material()) {
+    if (n_increments < 1) DB_THROW(DBFFT_EINVAL, "n_increments must be >= 1");
+    if (B.cells[0]->mat == DBFFT_MAT_J2VP_CUBIC && !(dt > 0.0)) DB_THROW(DBFFT_EINVAL, "dt must be > 0");
+  }
+  std::vector<int> st = (B.prec == DBFFT_FP64) ? batch_solve_t<double>(B, loads, stress_masks, n_increments, dt, o, infos)
+                                               : batch_solve_t<float>(B, loads, stress_masks, n_increments, dt, o, infos);
+  int worst = DBFFT_OK;
+  for (int v : st)
+    if (v != DBFFT_OK) worst = v;
+  if (worst != DBFFT_OK && g_err.empty()) g_err = "at least one cell of the batch did not converge";
+  return (dbfft_status)worst;
+  API_END
+}
+
+dbfft_status dbfft_batch_tiles(dbfft_batch* b, int32_t* tiles) {
+  g_err.clear();
+  API_BEGIN
+  if (!b || !tiles) DB_THROW(DBFFT_EINVAL, "null argument");
+  Batch& B = b->impl;
+  for (size_t r = 0; r < B.cells.size(); ++r) {
+    tiles[3 * r] = B.tzx[r];
+    tiles[3 * r + 1] = B.tzy[r];
+    tiles[3 * r + 2] = B.L[r];
+  }
+  return DBFFT_OK;
+  API_END
+}
+
+void dbfft_batch_destroy(dbfft_batch* b) {
+  if (!b) return;
+  batch_release(&b->impl);
+  delete b;
 }
 
 dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]) {

@@ -112,6 +112,29 @@ def test_neohooke_strain_control_parity(gpu):
     assert np.allclose(gi["eps_bar"], Fbar, atol=1e-14)
 
 
+@pytest.mark.parametrize("n", [(12, 10, 10), (8, 12, 8)])
+def test_neohooke_fp32_mixed_radix_parity(gpu, n):
+    """FP32 inner PCG on grids with radix-3/5 transforms: the residual stays
+    on Hermitian pairs of the self-conjugate planes, so the FP32 PCG reaches
+    its tolerance and Newton (FP64 residuals) the oracle's solution."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case neohooke fp32 n={n}", flush=True)
+    phase = ms.centred_sphere(n, 0.2)
+    mus = [1.0, 10.0]
+    ninc = 2
+    loads = [np.diag([0.1 * (k + 1) / ninc, 0.0, 0.0]) for k in range(ninc)]
+    a, e, st, info = so.newton(n, oracle_neo_law(phase, mus), loads, None, kin=so.FINITE, tol=1e-12,
+                               tol_load=1e-12, newton_tol=1e-11)
+    with Cell(n, "neohooke", torch.from_numpy(phase), neo_params(mus), kinematics="finite",
+              precision="fp32_mixed") as cell:
+        gi = cell.solve(np.diag([1.1, 1.0, 1.0]), None, n_increments=ninc, tol=1e-6, tol_load=1e-6,
+                        newton_tol=1e-10)
+    assert gi["status"] == 0
+    assert gi["pcg_iters"] < 60 * gi["newton_iters"]
+    assert rel(gi["sigma_bar"], info.sigma_bar[-1]) < 1e-7
+
+
 def test_neohooke_mixed_control_parity(gpu):
     import torch
     from paper_1905_12725_amd.api import Cell

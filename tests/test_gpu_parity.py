@@ -49,6 +49,39 @@ def test_real_apply_iso_phase(gpu, n):
     assert rel(f, ref) < 1e-12
 
 
+@pytest.mark.parametrize("kin", ["small", "finite"])
+@pytest.mark.parametrize("n", [(8, 8, 8), (12, 12, 8), (8, 12, 8), (10, 10, 10), (8, 8, 12), (12, 10, 6),
+                               (16, 16, 16)])
+def test_real_apply_fp32(gpu, n, kin):
+    """FP32 operator of the mixed-precision contexts: small strains with
+    two isotropic phases, finite strains with the neo-Hookean tangent at
+    F = I (the state of a fresh context).  Bar 1e-5 relative."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case real_apply fp32 {kin} n={n}", flush=True)
+    rng = np.random.default_rng(103)
+    phase = (rng.random(n) < 0.35).astype(np.uint8)
+    u = rng.standard_normal((3,) + n)
+    if kin == "small":
+        E = [1.0, 7.0]
+        cell = Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3), precision="fp32_mixed")
+        tan, space = oracle_iso(phase, E, 0.3), so.Space(n)
+    else:
+        mus = np.array([1.0, 10.0])
+        lams = 3.0 * mus - 2.0 * mus / 3.0
+        cell = Cell(n, "neohooke", torch.from_numpy(phase), [1.0, 3.0, 10.0, 30.0], kinematics="finite",
+                    precision="fp32_mixed")
+        F = np.broadcast_to(np.eye(3), n + (3, 3))
+        tan, space = so.GeneralTangent(mt.neohooke_tangent(F, mus[phase], lams[phase])), so.Space(n, kin=so.FINITE)
+    with cell:
+        f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    a = sp.fourier(u, n)
+    a[:, space.Z] = 0
+    (ka, _), _ = space.apply((a, np.zeros(0)), tan)
+    ref = sp.real_field(ka, n)
+    assert rel(f, ref) < 1e-5
+
+
 @pytest.mark.parametrize("n", [(8, 8, 8), (12, 10, 16), (32, 64, 64)])
 def test_real_apply_aniso_grain(gpu, n):
     import torch
