@@ -133,10 +133,22 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
   const int s = tid % TZ, t = tid / TZ;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
-  const int col0 = blockIdx.x * TZ;
-  const bool valid = (col0 + s) < sg.ncols;
-  const int o = blockIdx.y;
-  const long long base = (long long)o * sg.ostride + col0 + s;
+  // The (other index, column) pairs are numbered with the column fastest
+  // and cut into tiles of TZ consecutive pairs, so every tile is full (the
+  // half-spectrum column count n3/2 + 1 is not a multiple of TZ).  Tiles
+  // are renumbered so that consecutive tiles, which share cache lines when
+  // rows are not line-aligned, run on the same XCD (blocks are dispatched
+  // to the 8 XCDs round robin).
+  const int nb = gridDim.x;
+  const int per = nb >> 3;
+  const int b = blockIdx.x;
+  const int tile = (b < (per << 3)) ? (b & 7) * per + (b >> 3) : b;
+  const long long npair = (long long)sg.nother * sg.ncols;
+  const long long pr = (long long)tile * TZ + s;
+  const bool valid = pr < npair;
+  const int o = valid ? (int)(pr / sg.ncols) : 0;
+  const int col = valid ? (int)(pr - (long long)o * sg.ncols) : 0;
+  const long long base = (long long)o * sg.ostride + col;
   const long long ls = sg.lstride;
 
   auto load8 = [&](const cpx<T>* src, cpx<T>* v) {
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
     // eps_12 = i/2 (U_2 + xi2 T_1), eps_13 = i/2 (U_3 + xi3 T_1),
     // eps_23 = i/2 (xi3 T_2 + xi2 T_3);  H_i1 = i U_i, H_i2 = i xi2 T_i, H_i3 = i xi3 T_i.
     const T xi2 = (T)xi_of(o, g.n2);
-    const T xi3 = (T)xi_of(col0 + s, g.n3);
+    const T xi3 = (T)xi_of(col, g.n3);
     T xi1[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) xi1[r] = (T)xi_of(t + TL * r, g.n1);
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
   } else {
     // SP_DIV_*: r_i = -i sum_j xi_j s_ij after the forward x transform
     const T xi2 = (T)xi_of(o, g.n2);
-    const T xi3 = (T)xi_of(col0 + s, g.n3);
+    const T xi3 = (T)xi_of(col, g.n3);
     T xi1[8];
 #pragma unroll
     for (int gq = 0; gq < 8; ++gq) xi1[gq] = (T)xi_of(t + TL * fast_out_pos<N>(gq), g.n1);
@@ -230,7 +242,7 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
       cpx<T> v[8];
       load8(in + c * sg.cstride_in, v);
       fast_fft<T, N>(v, t, lds, PITCH, s, tw, d);
-      if (dc_out != nullptr && o == 0 && blockIdx.x == 0 && tid == 0) dc_out[c] = (double)v[0].x;
+      if (dc_out != nullptr && valid && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
       int ii, jj;
       if constexpr (MODE == SP_DIV_SMALL) {
         ii = (c < 3) ? c : (c == 3 ? 1 : 0);
@@ -273,8 +285,9 @@ template <typename T, int N>
 static void launch_fast_n(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,
                           const Geom& g, const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
   using S = StridedShape<N>;
-  const int ntiles = (sg.ncols + S::TZ - 1) / S::TZ;
-  dim3 grid(ntiles, sg.nother, mode == SP_PLAIN ? ncomp_plain : 1);
+  const long long npair = (long long)sg.nother * sg.ncols;
+  const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
+  dim3 grid(ntiles, 1, mode == SP_PLAIN ? ncomp_plain : 1);
   const T d = (T)dir;
   auto i = static_cast<const cpx<T>*>(in);
   auto o = static_cast<cpx<T>*>(out);
