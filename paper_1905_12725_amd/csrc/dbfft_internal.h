@@ -135,7 +135,7 @@ int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes, int tan_kind);
 // register-resident kernels for power-of-two transform lengths
 bool fast_strided_supported(int n);
 bool fast_line_supported(int n3);
-int fast_line_blocks(const Geom& g);
+int fast_line_blocks(const Geom& g, int elem_bytes);
 template <typename T>
 void launch_strided_fast(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
                          const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop);

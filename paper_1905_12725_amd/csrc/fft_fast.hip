@@ -14,36 +14,39 @@
 
 namespace dbfft {
 
-template <int N>
+// Radices of the stages: 8, then 4, then 2 (no radix above E).
+template <int N, int E>
 constexpr int fast_nstages() {
   int m = N, s = 0;
-  while (m % 8 == 0) { m /= 8; ++s; }
+  if (E >= 8)
+    while (m % 8 == 0) { m /= 8; ++s; }
   while (m % 4 == 0) { m /= 4; ++s; }
   while (m % 2 == 0) { m /= 2; ++s; }
   return s;
 }
-template <int N>
+template <int N, int E>
 constexpr int fast_radix(int st) {
   int m = N, s = 0;
-  while (m % 8 == 0) { if (s == st) return 8; m /= 8; ++s; }
+  if (E >= 8)
+    while (m % 8 == 0) { if (s == st) return 8; m /= 8; ++s; }
   while (m % 4 == 0) { if (s == st) return 4; m /= 4; ++s; }
   while (m % 2 == 0) { if (s == st) return 2; m /= 2; ++s; }
   return 1;
 }
-template <int N>
+template <int N, int E>
 constexpr int fast_ns(int st) {
   int p = 1;
-  for (int s = 0; s < st; ++s) p *= fast_radix<N>(s);
+  for (int s = 0; s < st; ++s) p *= fast_radix<N, E>(s);
   return p;
 }
 
-// radix-R butterflies of stage ST on the 8 registers of thread t
-template <typename T, int N, int ST>
+// radix-R butterflies of stage ST on the E registers of thread t
+template <typename T, int N, int E, int ST>
 __device__ __forceinline__ void fast_stage(cpx<T>* v, int t, const cpx<T>* __restrict__ tw, T d) {
-  constexpr int R = fast_radix<N>(ST);
-  constexpr int NS = fast_ns<N>(ST);
-  constexpr int TL = N / 8;
-  constexpr int NB = 8 / R;
+  constexpr int R = fast_radix<N, E>(ST);
+  constexpr int NS = fast_ns<N, E>(ST);
+  constexpr int TL = N / E;
+  constexpr int NB = E / R;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     cpx<T>* b = v + q * R;
@@ -63,11 +66,11 @@ __device__ __forceinline__ void fast_stage(cpx<T>* v, int t, const cpx<T>* __res
 
 // write the outputs of stage ST to LDS and read the inputs of stage ST+1;
 // element index i of a sequence lives at lds[i * pitch + lane_off]
-template <typename T, int N, int ST>
+template <typename T, int N, int E, int ST>
 __device__ __forceinline__ void fast_exchange(cpx<T>* v, int t, cpx<T>* lds, int pitch, int off) {
-  constexpr int R = fast_radix<N>(ST), NS = fast_ns<N>(ST), NB = 8 / R;
-  constexpr int R2 = fast_radix<N>(ST + 1), NB2 = 8 / R2;
-  constexpr int TL = N / 8;
+  constexpr int R = fast_radix<N, E>(ST), NS = fast_ns<N, E>(ST), NB = E / R;
+  constexpr int R2 = fast_radix<N, E>(ST + 1), NB2 = E / R2;
+  constexpr int TL = N / E;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int j = t + TL * q;
@@ -85,47 +88,70 @@ __device__ __forceinline__ void fast_exchange(cpx<T>* v, int t, cpx<T>* lds, int
   __syncthreads();
 }
 
-template <typename T, int N, int ST>
+template <typename T, int N, int E, int ST>
 __device__ __forceinline__ void fast_fft_from(cpx<T>* v, int t, cpx<T>* lds, int pitch, int off,
                                               const cpx<T>* __restrict__ tw, T d) {
-  fast_stage<T, N, ST>(v, t, tw, d);
-  if constexpr (ST + 1 < fast_nstages<N>()) {
-    fast_exchange<T, N, ST>(v, t, lds, pitch, off);
-    fast_fft_from<T, N, ST + 1>(v, t, lds, pitch, off, tw, d);
+  fast_stage<T, N, E, ST>(v, t, tw, d);
+  if constexpr (ST + 1 < fast_nstages<N, E>()) {
+    fast_exchange<T, N, E, ST>(v, t, lds, pitch, off);
+    fast_fft_from<T, N, E, ST + 1>(v, t, lds, pitch, off, tw, d);
   }
 }
 
-// full transform of the 8 registers (stage-0 input -> last-stage output)
-template <typename T, int N>
+// full transform of the E registers (stage-0 input -> last-stage output)
+template <typename T, int N, int E>
 __device__ __forceinline__ void fast_fft(cpx<T>* v, int t, cpx<T>* lds, int pitch, int off,
                                          const cpx<T>* __restrict__ tw, T d) {
-  fast_fft_from<T, N, 0>(v, t, lds, pitch, off, tw, d);
+  fast_fft_from<T, N, E, 0>(v, t, lds, pitch, off, tw, d);
 }
 
 // index of output register g (= q*R + r) of thread t
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ constexpr int fast_out_pos(int g) {
-  constexpr int R = fast_radix<N>(fast_nstages<N>() - 1);
-  constexpr int NB = 8 / R;
+  constexpr int R = fast_radix<N, E>(fast_nstages<N, E>() - 1);
+  constexpr int NB = E / R;
   return (g / R) + NB * (g % R);  // q + NB r, times TL plus t
 }
 
 // ------------------------------------------------------------------ x / y passes
-template <int N>
+// Elements per thread: 4 for the FP64 passes that keep several vectors
+// live (gradient, divergence), 8 otherwise.
+template <typename T, int N, int MODE>
+constexpr int strided_E() {
+  return (sizeof(T) == 8 && MODE != SP_PLAIN && N <= 128) ? 4 : 8;
+}
+template <int N, int E>
 struct StridedShape {
-  static constexpr int TL = N / 8;
-  static constexpr int TZ = (N >= 256) ? 8 : (N >= 128 ? 16 : 32);
+  static constexpr int TL = N / E;
+  static constexpr int TZ = (256 / TL) < 32 ? (256 / TL) : 32;
   static constexpr int NT = TL * TZ;
   static constexpr int PITCH = TZ + 1;
 };
 
+#ifndef DBFFT_GRAD_WAVES
+#define DBFFT_GRAD_WAVES 1
+#endif
+#ifndef DBFFT_DIV_WAVES
+#define DBFFT_DIV_WAVES 1
+#endif
+// minimum waves per SIMD the register allocation must allow (FP64 fused
+// passes; the FP32 ones fit three or more waves anyway)
+template <typename T>
+constexpr int strided_min_waves(int mode) {
+  if (sizeof(T) == 4) return 1;
+  if (mode == SP_GRAD_SMALL || mode == SP_GRAD_FINITE) return DBFFT_GRAD_WAVES;
+  if (mode == SP_DIV_SMALL || mode == SP_DIV_FINITE) return DBFFT_DIV_WAVES;
+  return 1;
+}
+
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<T>* in, cpx<T>* out, StridedGeom sg,
+__global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT), (strided_min_waves<T>(MODE))) void k_strided_fast(const cpx<T>* in, cpx<T>* out, StridedGeom sg,
                                                                       Geom g, const cpx<T>* __restrict__ twg, T d,
                                                                       double* __restrict__ dc_out,
                                                                       const int* __restrict__ stop) {
   if (stop != nullptr && *stop) return;
-  using S = StridedShape<N>;
+  constexpr int E = strided_E<T, N, MODE>();
+  using S = StridedShape<N, E>;
   constexpr int TL = S::TL, TZ = S::TZ, NT = S::NT, PITCH = S::PITCH;
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> lds[N * PITCH];
@@ -151,115 +177,108 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
   const long long base = (long long)o * sg.ostride + col;
   const long long ls = sg.lstride;
 
-  auto load8 = [&](const cpx<T>* src, cpx<T>* v) {
+  auto loadv = [&](const cpx<T>* src, cpx<T>* v) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = valid ? src[base + (long long)(t + TL * r) * ls] : mk<T>(0, 0);
+    for (int r = 0; r < E; ++r) v[r] = valid ? src[base + (long long)(t + TL * r) * ls] : mk<T>(0, 0);
   };
-  auto store8 = [&](cpx<T>* dst, const cpx<T>* v) {
+  auto storev = [&](cpx<T>* dst, const cpx<T>* v) {
     if (!valid) return;
 #pragma unroll
-    for (int gq = 0; gq < 8; ++gq) dst[base + (long long)(t + TL * fast_out_pos<N>(gq)) * ls] = v[gq];
+    for (int gq = 0; gq < E; ++gq) dst[base + (long long)(t + TL * fast_out_pos<N, E>(gq)) * ls] = v[gq];
   };
 
   if constexpr (MODE == SP_PLAIN) {
     const int c = blockIdx.z;
-    cpx<T> v[8];
-    load8(in + c * sg.cstride_in, v);
-    fast_fft<T, N>(v, t, lds, PITCH, s, tw, d);
-    store8(out + c * sg.cstride_out, v);
-  } else if constexpr (MODE == SP_GRAD_SMALL || MODE == SP_GRAD_FINITE) {
-    // x pass, line = k1, other = k2, column = k3.  With T_i = FFT(a_i) and
-    // U_i = FFT(xi1 a_i):  eps_11 = i U_1, eps_22 = i xi2 T_2, eps_33 = i xi3 T_3,
-    // eps_12 = i/2 (U_2 + xi2 T_1), eps_13 = i/2 (U_3 + xi3 T_1),
-    // eps_23 = i/2 (xi3 T_2 + xi2 T_3);  H_i1 = i U_i, H_i2 = i xi2 T_i, H_i3 = i xi3 T_i.
+    cpx<T> v[E];
+    loadv(in + c * sg.cstride_in, v);
+    fast_fft<T, N, E>(v, t, lds, PITCH, s, tw, d);
+    storev(out + c * sg.cstride_out, v);
+  } else if constexpr (MODE == SP_GRAD_SMALL) {
+    // x pass, line = k1, other = k2, column = k3: each strain component
+    // eps_ij = i/2 (xi_j a_i + xi_i a_j) is formed on the coefficients (xi1
+    // varies along the line) and transformed on its own; the three
+    // displacement components are loaded once, up front.
     const T xi2 = (T)xi_of(o, g.n2);
     const T xi3 = (T)xi_of(col, g.n3);
-    T xi1[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) xi1[r] = (T)xi_of(t + TL * r, g.n1);
     const long long co = sg.cstride_out;
-    cpx<T> T1[8], T2[8], Tc[8], U[8];
+    cpx<T> A0[E], A1[E], A2[E];
+    loadv(in, A0);
+    loadv(in + sg.cstride_in, A1);
+    loadv(in + 2 * sg.cstride_in, A2);
+    auto emit = [&](int c, auto&& form) {
+      cpx<T> v[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = form(r, (T)xi_of(t + TL * r, g.n1));
+      fast_fft<T, N, E>(v, t, lds, PITCH, s, tw, d);
+      storev(out + c * co, v);
+    };
+    // stored order 11 22 33 23 13 12
+    emit(0, [&](int r, T x1) { return muli(scl(A0[r], x1), (T)1); });
+    emit(1, [&](int r, T) { return muli(scl(A1[r], xi2), (T)1); });
+    emit(2, [&](int r, T) { return muli(scl(A2[r], xi3), (T)1); });
+    emit(3, [&](int r, T) { return muli(scl(add(scl(A1[r], xi3), scl(A2[r], xi2)), (T)0.5), (T)1); });
+    emit(4, [&](int r, T x1) { return muli(scl(add(scl(A0[r], xi3), scl(A2[r], x1)), (T)0.5), (T)1); });
+    emit(5, [&](int r, T x1) { return muli(scl(add(scl(A0[r], xi2), scl(A1[r], x1)), (T)0.5), (T)1); });
+  } else if constexpr (MODE == SP_GRAD_FINITE) {
+    // With T_i = FFT(a_i) and U_i = FFT(xi1 a_i): H_i1 = i U_i,
+    // H_i2 = i xi2 T_i, H_i3 = i xi3 T_i (six transforms for nine outputs).
+    const T xi2 = (T)xi_of(o, g.n2);
+    const T xi3 = (T)xi_of(col, g.n3);
+    T xi1[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) xi1[r] = (T)xi_of(t + TL * r, g.n1);
+    const long long co = sg.cstride_out;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      cpx<T>* Ti = (i == 0) ? T1 : (i == 1 ? T2 : Tc);
-      load8(in + i * sg.cstride_in, Ti);
+      cpx<T> Ti[E], U[E];
+      loadv(in + i * sg.cstride_in, Ti);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) U[r] = scl(Ti[r], xi1[r]);
-      fast_fft<T, N>(Ti, t, lds, PITCH, s, tw, d);
-      fast_fft<T, N>(U, t, lds, PITCH, s, tw, d);
-      cpx<T> w[8];
-      if constexpr (MODE == SP_GRAD_FINITE) {
+      for (int r = 0; r < E; ++r) U[r] = scl(Ti[r], xi1[r]);
+      fast_fft<T, N, E>(Ti, t, lds, PITCH, s, tw, d);
+      fast_fft<T, N, E>(U, t, lds, PITCH, s, tw, d);
+      cpx<T> w[E];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) w[r] = muli(U[r], (T)1);
-        store8(out + (3 * i + 0) * co, w);
+      for (int r = 0; r < E; ++r) w[r] = muli(U[r], (T)1);
+      storev(out + (3 * i + 0) * co, w);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) w[r] = muli(scl(Ti[r], xi2), (T)1);
-        store8(out + (3 * i + 1) * co, w);
+      for (int r = 0; r < E; ++r) w[r] = muli(scl(Ti[r], xi2), (T)1);
+      storev(out + (3 * i + 1) * co, w);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) w[r] = muli(scl(Ti[r], xi3), (T)1);
-        store8(out + (3 * i + 2) * co, w);
-      } else {
-        // stored order 11 22 33 23 13 12
-        if (i == 0) {
-#pragma unroll
-          for (int r = 0; r < 8; ++r) w[r] = muli(U[r], (T)1);
-          store8(out + 0 * co, w);
-        } else if (i == 1) {
-#pragma unroll
-          for (int r = 0; r < 8; ++r) w[r] = muli(scl(T2[r], xi2), (T)1);
-          store8(out + 1 * co, w);
-#pragma unroll
-          for (int r = 0; r < 8; ++r) w[r] = muli(scl(add(U[r], scl(T1[r], xi2)), (T)0.5), (T)1);
-          store8(out + 5 * co, w);
-        } else {
-#pragma unroll
-          for (int r = 0; r < 8; ++r) w[r] = muli(scl(Tc[r], xi3), (T)1);
-          store8(out + 2 * co, w);
-#pragma unroll
-          for (int r = 0; r < 8; ++r) w[r] = muli(scl(add(U[r], scl(T1[r], xi3)), (T)0.5), (T)1);
-          store8(out + 4 * co, w);
-#pragma unroll
-          for (int r = 0; r < 8; ++r) w[r] = muli(scl(add(scl(T2[r], xi3), scl(Tc[r], xi2)), (T)0.5), (T)1);
-          store8(out + 3 * co, w);
-        }
-      }
+      for (int r = 0; r < E; ++r) w[r] = muli(scl(Ti[r], xi3), (T)1);
+      storev(out + (3 * i + 2) * co, w);
     }
-  } else {
-    // SP_DIV_*: r_i = -i sum_j xi_j s_ij after the forward x transform
+  } else if constexpr (MODE == SP_DIV_SMALL) {
+    // r_i = -i sum_j xi_j s_ij after the forward x transform; three row
+    // accumulators, the next stress component loaded while the current one
+    // is transformed.
     const T xi2 = (T)xi_of(o, g.n2);
     const T xi3 = (T)xi_of(col, g.n3);
-    T xi1[8];
+    cpx<T> a0[E], a1[E], a2[E];
 #pragma unroll
-    for (int gq = 0; gq < 8; ++gq) xi1[gq] = (T)xi_of(t + TL * fast_out_pos<N>(gq), g.n1);
-    cpx<T> a0[8], a1[8], a2[8];  // rows of -i xi_j s_ij before the factor -i
-#pragma unroll
-    for (int r = 0; r < 8; ++r) a0[r] = a1[r] = a2[r] = mk<T>(0, 0);
-    constexpr int NC = (MODE == SP_DIV_SMALL) ? 6 : 9;
-    // one component live at a time (keeps the three accumulators the only
-    // long-lived registers)
+    for (int r = 0; r < E; ++r) a0[r] = a1[r] = a2[r] = mk<T>(0, 0);
+    cpx<T> nx[E];
+    loadv(in, nx);
 #pragma unroll 1
-    for (int c = 0; c < NC; ++c) {
-      cpx<T> v[8];
-      load8(in + c * sg.cstride_in, v);
-      fast_fft<T, N>(v, t, lds, PITCH, s, tw, d);
-      if (dc_out != nullptr && valid && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
-      int ii, jj;
-      if constexpr (MODE == SP_DIV_SMALL) {
-        ii = (c < 3) ? c : (c == 3 ? 1 : 0);
-        jj = (c < 3) ? c : (c == 5 ? 1 : 2);
-      } else {
-        ii = c / 3;
-        jj = c % 3;
-      }
+    for (int c = 0; c < 6; ++c) {
+      cpx<T> v[E];
 #pragma unroll
-      for (int gq = 0; gq < 8; ++gq) {
-        const T xj = (jj == 0) ? xi1[gq] : (jj == 1 ? xi2 : xi3);
+      for (int r = 0; r < E; ++r) v[r] = nx[r];
+      if (c + 1 < 6) loadv(in + (c + 1) * sg.cstride_in, nx);
+      fast_fft<T, N, E>(v, t, lds, PITCH, s, tw, d);
+      if (dc_out != nullptr && valid && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
+      // stored order 11 22 33 23 13 12
+      const int ii = (c < 3) ? c : (c == 3 ? 1 : 0);
+      const int jj = (c < 3) ? c : (c == 5 ? 1 : 2);
+#pragma unroll
+      for (int gq = 0; gq < E; ++gq) {
+        const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
+        const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
+        const T xi_ = (ii == 0) ? x1 : (ii == 1 ? xi2 : xi3);
         const cpx<T> t1 = scl(v[gq], xj);
         if (ii == 0) a0[gq] = add(a0[gq], t1);
         else if (ii == 1) a1[gq] = add(a1[gq], t1);
         else a2[gq] = add(a2[gq], t1);
-        if (MODE == SP_DIV_SMALL && ii != jj) {
-          const T xi_ = (ii == 0) ? xi1[gq] : (ii == 1 ? xi2 : xi3);
+        if (ii != jj) {
           const cpx<T> t2 = scl(v[gq], xi_);
           if (jj == 0) a0[gq] = add(a0[gq], t2);
           else if (jj == 1) a1[gq] = add(a1[gq], t2);
@@ -268,46 +287,97 @@ __global__ __launch_bounds__(StridedShape<N>::NT) void k_strided_fast(const cpx<
       }
     }
 #pragma unroll
-    for (int gq = 0; gq < 8; ++gq) {
+    for (int gq = 0; gq < E; ++gq) {
       a0[gq] = muli(a0[gq], (T)-1);
       a1[gq] = muli(a1[gq], (T)-1);
       a2[gq] = muli(a2[gq], (T)-1);
     }
-    store8(out, a0);
-    store8(out + sg.cstride_out, a1);
-    store8(out + 2 * sg.cstride_out, a2);
+    storev(out, a0);
+    storev(out + sg.cstride_out, a1);
+    storev(out + 2 * sg.cstride_out, a2);
+  } else {
+    // SP_DIV_FINITE, row by row: r_i = -i (xi1 F[P_i1] + F[xi2 P_i2 + xi3 P_i3])
+    // (xi2, xi3 are constant along the line, so they are applied before the
+    // transform): six transforms for the nine components, one row live, the
+    // next row's components loaded while the current row is transformed.
+    const T xi2 = (T)xi_of(o, g.n2);
+    const T xi3 = (T)xi_of(col, g.n3);
+    const bool dcl = dc_out != nullptr && valid && o == 0 && col == 0;
+    cpx<T> P1[E], P2[E], P3[E];
+    loadv(in, P1);
+    loadv(in + sg.cstride_in, P2);
+    loadv(in + 2 * sg.cstride_in, P3);
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      cpx<T> C[E], A[E];
+      T dsum[3] = {0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        C[r] = add(scl(P2[r], xi2), scl(P3[r], xi3));
+        A[r] = P1[r];
+        if (dcl) {
+          dsum[0] += P1[r].x;
+          dsum[1] += P2[r].x;
+          dsum[2] += P3[r].x;
+        }
+      }
+      if (dcl) {
+        // line sums (the k1 = 0 coefficient) of P_i1, P_i2, P_i3: the 16
+        // threads of the line reduce through the exchange buffer
+#pragma unroll
+        for (int j = 0; j < 3; ++j) lds[t * PITCH + j] = mk<T>(dsum[j], 0);
+      }
+      if (i + 1 < 3) {
+        loadv(in + (3 * i + 3) * sg.cstride_in, P1);
+        loadv(in + (3 * i + 4) * sg.cstride_in, P2);
+        loadv(in + (3 * i + 5) * sg.cstride_in, P3);
+      }
+      if (dc_out != nullptr && blockIdx.x == 0) {
+        __syncthreads();
+        if (dcl && t == 0) {
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int u = 0; u < TL; ++u) acc += (double)lds[u * PITCH + j].x;
+            dc_out[3 * i + j] = acc;
+          }
+        }
+        __syncthreads();
+      }
+      fast_fft<T, N, E>(C, t, lds, PITCH, s, tw, d);
+      fast_fft<T, N, E>(A, t, lds, PITCH, s, tw, d);
+#pragma unroll
+      for (int gq = 0; gq < E; ++gq) {
+        const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
+        A[gq] = muli(add(scl(A[gq], x1), C[gq]), (T)-1);
+      }
+      storev(out + i * sg.cstride_out, A);
+    }
   }
 }
 
 bool fast_strided_supported(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
+template <typename T, int N, int MODE>
+static void launch_fast_nm(const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
+                           const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+  using S = StridedShape<N, strided_E<T, N, MODE>()>;
+  const long long npair = (long long)sg.nother * sg.ncols;
+  const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
+  dim3 grid(ntiles, 1, MODE == SP_PLAIN ? ncomp_plain : 1);
+  hipLaunchKernelGGL((k_strided_fast<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
+                     static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop);
+}
+
 template <typename T, int N>
 static void launch_fast_n(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,
                           const Geom& g, const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
-  using S = StridedShape<N>;
-  const long long npair = (long long)sg.nother * sg.ncols;
-  const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
-  dim3 grid(ntiles, 1, mode == SP_PLAIN ? ncomp_plain : 1);
-  const T d = (T)dir;
-  auto i = static_cast<const cpx<T>*>(in);
-  auto o = static_cast<cpx<T>*>(out);
-  auto t = static_cast<const cpx<T>*>(tw);
   switch (mode) {
-    case SP_PLAIN:
-      hipLaunchKernelGGL((k_strided_fast<T, N, SP_PLAIN>), grid, dim3(S::NT), 0, st, i, o, sg, g, t, d, dc_out, stop);
-      break;
-    case SP_GRAD_SMALL:
-      hipLaunchKernelGGL((k_strided_fast<T, N, SP_GRAD_SMALL>), grid, dim3(S::NT), 0, st, i, o, sg, g, t, d, dc_out, stop);
-      break;
-    case SP_GRAD_FINITE:
-      hipLaunchKernelGGL((k_strided_fast<T, N, SP_GRAD_FINITE>), grid, dim3(S::NT), 0, st, i, o, sg, g, t, d, dc_out, stop);
-      break;
-    case SP_DIV_SMALL:
-      hipLaunchKernelGGL((k_strided_fast<T, N, SP_DIV_SMALL>), grid, dim3(S::NT), 0, st, i, o, sg, g, t, d, dc_out, stop);
-      break;
-    default:
-      hipLaunchKernelGGL((k_strided_fast<T, N, SP_DIV_FINITE>), grid, dim3(S::NT), 0, st, i, o, sg, g, t, d, dc_out, stop);
-      break;
+    case SP_PLAIN: launch_fast_nm<T, N, SP_PLAIN>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    case SP_GRAD_SMALL: launch_fast_nm<T, N, SP_GRAD_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    case SP_GRAD_FINITE: launch_fast_nm<T, N, SP_GRAD_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    case SP_DIV_SMALL: launch_fast_nm<T, N, SP_DIV_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    default: launch_fast_nm<T, N, SP_DIV_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
   }
 }
 
@@ -338,56 +408,61 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
   return mk<T>(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
-template <typename T, int M>
+// Elements per thread of the z pass: 4 in FP64, 8 in FP32.
+template <typename T>
+constexpr int line_E() {
+  return sizeof(T) == 8 ? 4 : 8;
+}
+template <typename T, int M, int E>
 struct LineCtx {
-  static constexpr int TL = M / 8;
+  static constexpr int TL = M / E;
   static constexpr int LB = 64 / TL;
   static constexpr int PITCH = M + 1;
 };
 
 // inverse real transform of component c for the 8 lines of the wave:
 // e[m] = packed pair at position t + TL m
-template <typename T, int M>
+template <typename T, int M, int E>
 __device__ __forceinline__ void line_inverse(const cpx<T>* src, bool valid, int t, int partner, cpx<T>* lds, int off,
                                              const cpx<T>* tw, const cpx<T>* rtw, cpx<T>* e) {
-  constexpr int TL = M / 8;
-  cpx<T> X[8];
+  constexpr int TL = M / E;
+  cpx<T> X[E];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) X[r] = valid ? src[t + TL * r] : mk<T>(0, 0);
+  for (int r = 0; r < E; ++r) X[r] = valid ? src[t + TL * r] : mk<T>(0, 0);
   const cpx<T> XN = (valid && t == 0) ? src[M] : mk<T>(0, 0);
-  cpx<T> Z[8];
+  cpx<T> Z[E];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
+  for (int r = 0; r < E; ++r) {
     // X[M - k] for k = t + TL r: lane (TL - t), register 7 - r; for t = 0 own register 8 - r (XN when r = 0)
-    const cpx<T> sh = shfl_c(X[7 - r], partner);
-    const cpx<T> own = (r == 0) ? XN : X[(8 - r) & 7];
+    const cpx<T> sh = shfl_c(X[E - 1 - r], partner);
+    const cpx<T> own = (r == 0) ? XN : X[(E - r) & (E - 1)];
     const cpx<T> Xm = conj((t == 0) ? own : sh);
     const cpx<T> Ev = add(X[r], Xm);
     const cpx<T> Od = mul(sub(X[r], Xm), conj(rtw[t + TL * r]));
     Z[r] = add(Ev, muli(Od, (T)1));
   }
-  fast_fft<T, M>(Z, t, lds, 1, off, tw, (T)1);
+  fast_fft<T, M, E>(Z, t, lds, 1, off, tw, (T)1);
 #pragma unroll
-  for (int gq = 0; gq < 8; ++gq) e[fast_out_pos<M>(gq)] = Z[gq];
+  for (int gq = 0; gq < E; ++gq) e[fast_out_pos<M, E>(gq)] = Z[gq];
 }
 
 // forward real transform of packed pairs e (positions t + TL m), scaled, stored
-template <typename T, int M>
+template <typename T, int M, int E>
 __device__ __forceinline__ void line_forward(cpx<T>* dst, bool valid, int t, int partner, cpx<T>* lds, int off,
                                              const cpx<T>* tw, const cpx<T>* rtw, const cpx<T>* e, T scale) {
-  constexpr int TL = M / 8;
-  cpx<T> Z[8];
+  constexpr int TL = M / E;
+  cpx<T> Z[E];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) Z[m] = e[m];
-  fast_fft<T, M>(Z, t, lds, 1, off, tw, (T)-1);
-  cpx<T> Zp[8];
+  for (int m = 0; m < E; ++m) Z[m] = e[m];
+  fast_fft<T, M, E>(Z, t, lds, 1, off, tw, (T)-1);
+  cpx<T> Zp[E];
 #pragma unroll
-  for (int gq = 0; gq < 8; ++gq) Zp[fast_out_pos<M>(gq)] = Z[gq];
+  for (int gq = 0; gq < E; ++gq) Zp[fast_out_pos<M, E>(gq)] = Z[gq];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
+  for (int m = 0; m < E; ++m) {
     const int k = t + TL * m;
-    const cpx<T> sh = shfl_c(Zp[7 - m], partner);
-    const cpx<T> own = Zp[(8 - m) & 7];
+    const cpx<T> sh = shfl_c(Zp[E - 1 - m], partner);
+    const cpx<T> own = Zp[(E - m) & (E - 1)];
     const cpx<T> Zm = conj((t == 0) ? own : sh);
     const cpx<T> Ev = scl(add(Zp[m], Zm), (T)0.5);
     const cpx<T> Od = mul(rtw[k], scl(sub(Zp[m], Zm), (T)0.5));
@@ -423,7 +498,8 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
                                                   const double* __restrict__ macro_dev, double* __restrict__ partials,
                                                   const int* __restrict__ stop) {
   if (stop != nullptr && *stop) return;
-  using LC = LineCtx<T, M>;
+  constexpr int E = line_E<T>();
+  using LC = LineCtx<T, M, E>;
   constexpr int TL = LC::TL, LB = LC::LB, PITCH = LC::PITCH;
   constexpr int NC = (KIN == KIN_SMALL) ? 6 : 9;
   __shared__ cpx<T> tw[M];
@@ -450,12 +526,12 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
 
   if constexpr (ISO == 1) {
     // normal components 11 22 33
-    cpx<T> e[3][8];
+    cpx<T> e[3][E];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) line_inverse<T, M>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c]);
+    for (int c = 0; c < 3; ++c) line_inverse<T, M, E>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c]);
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
+      for (int m = 0; m < E; ++m) {
         const int n = t + TL * m;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -477,15 +553,15 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
       }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) line_forward<T, M>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c], scale);
+    for (int c = 0; c < 3; ++c) line_forward<T, M, E>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c], scale);
     // shear components 23 13 12, one at a time: sigma = 2 mu eps
 #pragma unroll 1
     for (int c = 3; c < 6; ++c) {
-      cpx<T> e1[8];
-      line_inverse<T, M>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e1);
+      cpx<T> e1[E];
+      line_inverse<T, M, E>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e1);
       if (valid) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < E; ++m) {
           const int n = t + TL * m;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
@@ -500,15 +576,15 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
           }
         }
       }
-      line_forward<T, M>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e1, scale);
+      line_forward<T, M, E>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e1, scale);
     }
   } else {
-    cpx<T> e[NC][8];
+    cpx<T> e[NC][E];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) line_inverse<T, M>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c]);
+    for (int c = 0; c < NC; ++c) line_inverse<T, M, E>(inl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c]);
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
+      for (int m = 0; m < E; ++m) {
         const int n = t + TL * m;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -585,7 +661,7 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
       }
     }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) line_forward<T, M>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c], scale);
+    for (int c = 0; c < NC; ++c) line_forward<T, M, E>(outl + c * g.nh, valid, t, partner, lds, off, tw, rtw, e[c], scale);
   }
   if (partials != nullptr) {
 #pragma unroll
@@ -596,9 +672,10 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
 
 bool fast_line_supported(int n3) { return n3 == 16 || n3 == 32 || n3 == 64 || n3 == 128 || n3 == 256; }
 
-int fast_line_blocks(const Geom& g) {
+int fast_line_blocks(const Geom& g, int elem_bytes) {
   const int M = g.n3 / 2;
-  const int LB = 64 / (M / 8);
+  const int E = elem_bytes == 16 ? 4 : 8;
+  const int LB = 64 / (M / E);
   return (int)(((long long)g.n1 * g.n2 + LB - 1) / LB);
 }
 
@@ -606,7 +683,7 @@ template <typename T, int M>
 static void launch_line_fast_m(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
                                const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
                                const int* stop) {
-  const int nb = fast_line_blocks(g);
+  const int nb = fast_line_blocks(g, (int)sizeof(cpx<T>));
   auto i = static_cast<const cpx<T>*>(in);
   auto o = static_cast<cpx<T>*>(out);
   auto t = static_cast<const cpx<T>*>(tw);
