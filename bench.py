@@ -71,25 +71,33 @@ def mandel_loads(scale=1e-3):
     return loads
 
 
-def kernel_bytes(n, kind, wbytes):
+def kernel_bytes(n, kind, wbytes, fused=True):
     """Algorithmic HBM bytes of one launch of each kernel kind (small strain,
     phase-map material): complex half-spectrum fields of nh = n1 n2 (n3/2+1)
-    entries, 2*wbytes each."""
+    entries, 2*wbytes each.  Fused CG iteration: the divergence pass also
+    reads and writes r (no q vector), the plane kernel touches the two
+    self-conjugate planes of r, the direction kernel reads r, p, x and writes
+    p, x; otherwise the update kernel reads x, r, p, q and writes x, r and the
+    direction kernel reads r, p and writes p."""
     n1, n2, n3 = n
     nh = n1 * n2 * (n3 // 2 + 1)
     c = 2 * wbytes
     N = n1 * n2 * n3
-    return {
+    b = {
         "x_inverse_grad": (3 + 6) * nh * c,
         "y_inverse": 12 * nh * c,
         "z_fused_tangent": 12 * nh * c + N * 1,
         "y_forward": 12 * nh * c,
-        "x_forward_div": (6 + 3) * nh * c,
         "cg_alpha": 0,
-        "cg_update": 6 * 3 * nh * c,
         "cg_beta": 0,
-        "cg_direction": 3 * 3 * nh * c,
-    }[kind]
+    }
+    if fused:
+        b.update({"x_forward_div": (6 + 3 + 3) * nh * c, "cg_planes": 2 * 3 * 2 * n1 * n2 * c,
+                  "cg_direction": (9 + 6) * nh * c, "cg_update": 0})
+    else:
+        b.update({"x_forward_div": (6 + 3) * nh * c, "cg_update": 6 * 3 * nh * c,
+                  "cg_direction": 3 * 3 * nh * c, "cg_planes": 0})
+    return b[kind]
 
 
 def run_cases(cell, loads, **opts):
@@ -282,10 +290,11 @@ def main():
 
     applies_per_s = total_iters / elapsed
     per_kernel = {}
+    fused = ktime.get("cg_planes", (0.0, 0))[1] > 0
     for k, (ms_tot, cnt) in ktime.items():
         if cnt > 0:
             avg = ms_tot / cnt * 1e-3
-            b = kernel_bytes(n, k, 8)
+            b = kernel_bytes(n, k, 8, fused)
             per_kernel[k] = {"avg_us": avg * 1e6, "launches": cnt, "total_ms": ms_tot,
                              "bytes_per_launch": b, "GBps": (b / avg / 1e9) if b else None}
     dom = max((k for k in per_kernel if per_kernel[k]["bytes_per_launch"] > 0),
@@ -293,10 +302,10 @@ def main():
     dk = per_kernel[dom]
     apply_kinds = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div")
     apply_us = sum(per_kernel[k]["avg_us"] for k in apply_kinds if k in per_kernel)
-    apply_bytes = sum(kernel_bytes(n, k, 8) for k in apply_kinds)
-    iter_kinds = apply_kinds + ("cg_alpha", "cg_update", "cg_beta", "cg_direction")
+    apply_bytes = sum(kernel_bytes(n, k, 8, fused) for k in apply_kinds)
+    iter_kinds = apply_kinds + ("cg_alpha", "cg_update", "cg_beta", "cg_direction", "cg_planes")
     iter_us = sum(per_kernel[k]["avg_us"] for k in iter_kinds if k in per_kernel)
-    iter_bytes = sum(kernel_bytes(n, k, 8) for k in iter_kinds)
+    iter_bytes = sum(kernel_bytes(n, k, 8, fused) for k in iter_kinds)
 
     out = {
         "metric": METRIC,

@@ -198,7 +198,9 @@ struct Ctx {
   bool linear_material() const { return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE; }
 };
 
-enum ProfKind { PK_XINV = 0, PK_YINV, PK_ZFUSED, PK_YFWD, PK_XFWD, PK_ALPHA, PK_UPDATE, PK_BETA, PK_PUPDATE, PK_END };
+enum ProfKind {
+  PK_XINV = 0, PK_YINV, PK_ZFUSED, PK_YFWD, PK_XFWD, PK_ALPHA, PK_UPDATE, PK_BETA, PK_PUPDATE, PK_PLANES, PK_END
+};
 
 // records an event that marks the start of a kernel of `kind` (PK_END closes)
 static void prof_mark(Ctx& c, int kind) {
@@ -602,6 +604,17 @@ static PcgOut pcg_result(Ctx& c) {
   return o;
 }
 
+// The fused iteration needs the register-FFT x pass (n1 a power of two from
+// 8 to 256) and small strains; DBFFT_UNFUSED=1 selects the separate vector
+// kernels everywhere (same arithmetic, other summation order).
+static bool fused_cg(const Ctx& c) {
+  static const bool off = [] {
+    const char* e = std::getenv("DBFFT_UNFUSED");
+    return e != nullptr && e[0] == '1';
+  }();
+  return !off && c.kin == KIN_SMALL && fast_strided_supported(c.n[0]);
+}
+
 // Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
 template <typename T>
 static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r,
@@ -612,10 +625,37 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
   const double* pmac = reinterpret_cast<const double*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, pmac));
   const int* stop = reinterpret_cast<const int*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, converged));
   if (check_every < 1) check_every = 1;
+  const bool fused = fused_cg(c);
   while (!c.sc_host->converged) {
     const int iter0 = c.sc_host->iter;
     for (int k = 0; k < check_every; ++k) {
       c.prof_tag = k;
+      if (fused) {
+        // gradient | y | z (+ <p, K p>) | alpha | y | divergence with r -= alpha q
+        // | Hermitian planes | beta (+ macroscopic step) | x += alpha p, next p
+        Tables<T>& tb = tables<T>(c);
+        const StridedGeom sx = xgeom(c), sy = ygeom(c);
+        prof_mark(c, PK_XINV);
+        launch_strided<T>(SP_GRAD_SMALL, p, c.W, 0, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, stop);
+        prof_mark(c, PK_YINV);
+        launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, stop);
+        prof_mark(c, PK_ZFUSED);
+        launch_line<T>(LP_FUSED, c.kin, c.W, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, pmac, nullptr, c.partA, c.ncomp,
+                       c.st, nullptr, stop);
+        prof_mark(c, PK_ALPHA);
+        launch_pcg_alpha_only(c.sc_dev, c.partA, neb, c.st);
+        prof_mark(c, PK_YFWD);
+        launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
+        prof_mark(c, PK_XFWD);
+        const int nd = launch_div_update_fast<T>(c.W, r, sx, c.g, tb.tw1, c.sc_dev, pa, c.dc_dev, c.partB, c.st, stop);
+        prof_mark(c, PK_PLANES);
+        launch_pcg_planes<T>(r, pa, c.g, c.partB + 2 * nd, c.st, stop);
+        prof_mark(c, PK_BETA);
+        launch_pcg_beta_step(c.sc_dev, c.partB, nd + kPlaneBlocks, c.dc_dev, pc, c.st);
+        prof_mark(c, PK_PUPDATE);
+        launch_pcg_xp<T>(x, p, r, c.sc_dev, pa, c.g, nb, c.st);
+        continue;
+      }
       apply_K<T>(c, p, q, pmac, nullptr, tan, c.partA, c.dc_dev, stop);
       prof_mark(c, PK_ALPHA);
       launch_pcg_alpha(c.sc_dev, c.partA, neb, c.dc_dev, pc, c.st);
@@ -1232,8 +1272,9 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
       HIPCK(hipMemcpy(c->tanf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
       launch_convert<double, float>(c->tanf32, c->tanf, 10 * N, c->st);
     }
-    const int nparts = std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
-                                tangent_mean_block_count(g) * 81) + 64;
+    const int nparts = std::max(std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
+                                         tangent_mean_block_count(g) * 81),
+                                fused_cg_partials(g)) + 64;
     c->npart = nparts;
     c->partA = static_cast<double*>(dalloc(nparts * sizeof(double)));
     c->partB = static_cast<double*>(dalloc(nparts * sizeof(double)));

@@ -11,6 +11,7 @@
 // transform's input distribution after a register renaming, so the z pass
 // applies the pointwise tangent with no data movement at all.
 #include "fft_common.h"
+#include "pcg_core.h"
 
 namespace dbfft {
 
@@ -123,7 +124,8 @@ constexpr int strided_E() {
 template <int N, int E>
 struct StridedShape {
   static constexpr int TL = N / E;
-  static constexpr int TZ = (256 / TL) < 32 ? (256 / TL) : 32;
+  // at most 256 threads, at most 32 columns unless needed for one full wave
+  static constexpr int TZ = (256 / TL) < 32 ? (256 / TL) : ((64 / TL) > 32 ? (64 / TL) : 32);
   static constexpr int NT = TL * TZ;
   static constexpr int PITCH = TZ + 1;
 };
@@ -355,6 +357,148 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT), (st
     }
   }
 }
+
+// Fused CG step in the last forward pass (small strains): the divergence
+// q = -i xi . sigma_hat of the x-transformed stress stays in registers and
+// r -= alpha q is applied at once; the block's partial sums of <r, M r> and
+// <r, r> (weight 2) skip the self-conjugate planes k3 = 0 and n3/2, whose
+// points the plane kernel projects and sums afterwards.
+template <typename T, int N>
+__global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::NT)) void k_div_update_fast(
+    const cpx<T>* in, cpx<T>* r, StridedGeom sg, Geom g, const cpx<T>* __restrict__ twg,
+    const PcgScalars* __restrict__ sc, PrecondArgs pa, double* __restrict__ dc_out, double* __restrict__ partials,
+    const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
+  constexpr int E = strided_E<T, N, SP_DIV_SMALL>();
+  using S = StridedShape<N, E>;
+  constexpr int TL = S::TL, TZ = S::TZ, NT = S::NT, PITCH = S::PITCH;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[N * PITCH];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int s = tid % TZ, t = tid / TZ;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  __syncthreads();
+  const int nb = gridDim.x;
+  const int per = nb >> 3;
+  const int b = blockIdx.x;
+  const int tile = (b < (per << 3)) ? (b & 7) * per + (b >> 3) : b;
+  const long long npair = (long long)sg.nother * sg.ncols;
+  const long long pr = (long long)tile * TZ + s;
+  const bool valid = pr < npair;
+  const int o = valid ? (int)(pr / sg.ncols) : 0;
+  const int col = valid ? (int)(pr - (long long)o * sg.ncols) : 0;
+  const long long base = (long long)o * sg.ostride + col;
+  const long long ls = sg.lstride;
+  const T d = (T)-1;
+  auto loadv = [&](const cpx<T>* src, cpx<T>* v) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = valid ? src[base + (long long)(t + TL * q) * ls] : mk<T>(0, 0);
+  };
+  const T xi2 = (T)xi_of(o, g.n2);
+  const T xi3 = (T)xi_of(col, g.n3);
+  cpx<T> a0[E], a1[E], a2[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) a0[q] = a1[q] = a2[q] = mk<T>(0, 0);
+  cpx<T> nx[E];
+  loadv(in, nx);
+#pragma unroll 1
+  for (int c = 0; c < 6; ++c) {
+    cpx<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = nx[q];
+    if (c + 1 < 6) loadv(in + (c + 1) * sg.cstride_in, nx);
+    fast_fft<T, N, E>(v, t, lds, PITCH, s, tw, d);
+    if (dc_out != nullptr && valid && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
+    // stored order 11 22 33 23 13 12
+    const int ii = (c < 3) ? c : (c == 3 ? 1 : 0);
+    const int jj = (c < 3) ? c : (c == 5 ? 1 : 2);
+#pragma unroll
+    for (int gq = 0; gq < E; ++gq) {
+      const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
+      const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
+      const T xi_ = (ii == 0) ? x1 : (ii == 1 ? xi2 : xi3);
+      const cpx<T> t1 = scl(v[gq], xj);
+      if (ii == 0) a0[gq] = add(a0[gq], t1);
+      else if (ii == 1) a1[gq] = add(a1[gq], t1);
+      else a2[gq] = add(a2[gq], t1);
+      if (ii != jj) {
+        const cpx<T> t2 = scl(v[gq], xi_);
+        if (jj == 0) a0[gq] = add(a0[gq], t2);
+        else if (jj == 1) a1[gq] = add(a1[gq], t2);
+        else a2[gq] = add(a2[gq], t2);
+      }
+    }
+  }
+  // q = -i a; r -= alpha q
+  const double alpha = sc->alpha;
+  const bool plane = (col == 0) || (2 * col == g.n3);
+  const long long cs = sg.cstride_out;
+  double rz = 0.0, rr = 0.0;
+#pragma unroll
+  for (int gq = 0; gq < E; ++gq) {
+    const int k1 = t + TL * fast_out_pos<N, E>(gq);
+    const long long off = base + (long long)k1 * ls;
+    cpx<double> rv[3];
+    const cpx<T> qv[3] = {muli(a0[gq], (T)-1), muli(a1[gq], (T)-1), muli(a2[gq], (T)-1)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cpx<double> rc = valid ? sub(up(r[off + c * cs]), scl(up(qv[c]), alpha)) : mk<double>(0, 0);
+      if (valid) r[off + c * cs] = down<T>(rc);
+      rv[c] = up(down<T>(rc));
+    }
+    if (valid && !plane) {
+      cpx<double> zv[3];
+      precond(pa, xi_of(k1, g.n1), xi_of(o, g.n2), xi_of(col, g.n3), rv, zv);
+      double a = 0.0, bb = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
+        bb += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
+      }
+      rz += 2.0 * a;
+      rr += 2.0 * bb;
+    }
+  }
+  const double s1 = block_sum<NT>(rz, red);
+  const double s2 = block_sum<NT>(rr, red);
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = s1;
+    partials[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+template <typename T, int N>
+static int launch_div_update_n(const void* W, void* r, const StridedGeom& sg, const Geom& g, const void* tw,
+                               const PcgScalars* sc, const PrecondArgs& pa, double* dc_out, double* partials,
+                               hipStream_t st, const int* stop) {
+  using S = StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>;
+  const long long npair = (long long)sg.nother * sg.ncols;
+  const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
+  hipLaunchKernelGGL((k_div_update_fast<T, N>), dim3(ntiles), dim3(S::NT), 0, st, static_cast<const cpx<T>*>(W),
+                     static_cast<cpx<T>*>(r), sg, g, static_cast<const cpx<T>*>(tw), sc, pa, dc_out, partials, stop);
+  return ntiles;
+}
+
+template <typename T>
+int launch_div_update_fast(const void* W, void* r, const StridedGeom& sg, const Geom& g, const void* tw,
+                           const PcgScalars* sc, const PrecondArgs& pa, double* dc_out, double* partials,
+                           hipStream_t st, const int* stop) {
+  switch (sg.nline) {
+    case 8: return launch_div_update_n<T, 8>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+    case 16: return launch_div_update_n<T, 16>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+    case 32: return launch_div_update_n<T, 32>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+    case 64: return launch_div_update_n<T, 64>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+    case 128: return launch_div_update_n<T, 128>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+    default: return launch_div_update_n<T, 256>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+  }
+}
+template int launch_div_update_fast<double>(const void*, void*, const StridedGeom&, const Geom&, const void*,
+                                            const PcgScalars*, const PrecondArgs&, double*, double*, hipStream_t,
+                                            const int*);
+template int launch_div_update_fast<float>(const void*, void*, const StridedGeom&, const Geom&, const void*,
+                                           const PcgScalars*, const PrecondArgs&, double*, double*, hipStream_t,
+                                           const int*);
 
 bool fast_strided_supported(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 

@@ -238,6 +238,41 @@ __device__ __forceinline__ double frob_stored(const double* t, int ncomp) {
   return sqrt(s);
 }
 
+// macroscopic part of the step: x_e += alpha p_e, r_e -= alpha B:<sigma(p)>,
+// tracked average stress += alpha <sigma(p)> (thread 0)
+__device__ __forceinline__ void macro_step(PcgScalars* __restrict__ sc, double alpha, const double* __restrict__ dc,
+                                           const PcgConst& pc) {
+  for (int a = 0; a < pc.nmacro; ++a) {
+    double qe = 0.0;
+    for (int c = 0; c < pc.ncomp; ++c) qe += pc.basis[a][c] * (pc.ncomp == 6 && c >= 3 ? 2.0 : 1.0) * dc[c];
+    sc->qe[a] = qe;
+    sc->xe[a] += alpha * sc->pe[a];
+    sc->re[a] -= alpha * qe;
+  }
+  for (int c = 0; c < pc.ncomp; ++c) sc->sig[c] += alpha * dc[c];
+}
+
+// fused CG: alpha = <r,z>/<p,Kp> only; `pending` tells the direction kernel
+// whether x still takes this iteration's step
+__device__ __forceinline__ void alpha_only_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
+                                                int nparts) {
+  __shared__ double red[kVecThreads / 64];
+  if (sc->converged) {
+    if (threadIdx.x == 0) sc->pending = 0;
+    return;
+  }
+  const double pq = reduce_fixed(partials, nparts, 1, 0, red);
+  if (threadIdx.x != 0) return;
+  sc->pq = pq;
+  if (!(pq > 0.0)) {
+    sc->converged = 2;
+    sc->pending = 0;
+    return;
+  }
+  sc->alpha = sc->rz / pq;
+  sc->pending = 1;
+}
+
 // alpha = <r,z>/<p,Kp>; macro block of x and r; tracked average stress.
 // partials: energy sums of the z pass (one per block) = <p, K p>.
 __device__ __forceinline__ void alpha_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
@@ -253,25 +288,22 @@ __device__ __forceinline__ void alpha_core(PcgScalars* __restrict__ sc, const do
   }
   const double alpha = sc->rz / pq;
   sc->alpha = alpha;
-  for (int a = 0; a < pc.nmacro; ++a) {
-    double qe = 0.0;
-    for (int c = 0; c < pc.ncomp; ++c) qe += pc.basis[a][c] * (pc.ncomp == 6 && c >= 3 ? 2.0 : 1.0) * dc[c];
-    sc->qe[a] = qe;
-    sc->xe[a] += alpha * sc->pe[a];
-    sc->re[a] -= alpha * qe;
-  }
-  for (int c = 0; c < pc.ncomp; ++c) sc->sig[c] += alpha * dc[c];
+  macro_step(sc, alpha, dc, pc);
 }
 
 // beta, macro block of p, convergence.  first != 0: initial call after
 // p = M r (no beta, iteration counter stays 0).
+// dc != nullptr (fused CG): the macroscopic step of this iteration is taken
+// first, with the average stress of the direction from the divergence pass.
 __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
-                                          int nparts, const PcgConst& pc, int first) {
+                                          int nparts, const PcgConst& pc, int first,
+                                          const double* __restrict__ dc = nullptr) {
   __shared__ double red[kVecThreads / 64];
   if (sc->converged) return;
   const double rz_a = reduce_fixed(partials, nparts, 2, 0, red);
   const double rr = reduce_fixed(partials, nparts, 2, 1, red);
   if (threadIdx.x != 0) return;
+  if (dc != nullptr) macro_step(sc, sc->alpha, dc, pc);
   double ze[kMaxMacro];
   double rz = rz_a, re2 = 0.0;
   for (int a = 0; a < pc.nmacro; ++a) {
@@ -284,6 +316,7 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
   if (first) {
     for (int a = 0; a < pc.nmacro; ++a) sc->pe[a] = ze[a];
     sc->iter = 0;
+    sc->beta = 0.0;
   } else {
     const double beta = rz / sc->rz;
     sc->beta = beta;
@@ -313,6 +346,84 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
   }
   if (eq < pc.tol && ld < pc.tol_load) sc->converged = 1;
   else if (sc->iter >= pc.max_iter) sc->converged = 3;
+}
+
+// fused CG: Hermitian projection of r on the self-conjugate planes and the
+// partial sums of <r, M r>, <r, r> over their points (pairs count twice)
+template <typename T>
+__device__ __forceinline__ void planes_core(cpx<T>* __restrict__ r, const PrecondArgs& pa, const Geom& g,
+                                            double* __restrict__ partials, int chunk, int nchunks) {
+  __shared__ double red[kVecThreads / 64];
+  double rz = 0.0, rr = 0.0;
+  const long long nh = g.nh;
+  const long long plane = (long long)g.n1 * g.n2;
+  for (long long i = (long long)chunk * kVecThreads + threadIdx.x; i < 2 * plane;
+       i += (long long)nchunks * kVecThreads) {
+    FreqIdx f;
+    const long long rem = i % plane;
+    f.k1 = (int)(rem / g.n2);
+    f.k2 = (int)(rem % g.n2);
+    f.k3 = (i < plane) ? 0 : g.n3 / 2;
+    const long long k = ((long long)f.k1 * g.n2 + f.k2) * g.nh3 + f.k3;
+    const long long kp = partner_index(f, g);
+    if (kp < k) continue;
+    cpx<double> rv[3], zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cpx<double> rc = scl(add(up(r[c * nh + k]), conj(up(r[c * nh + kp]))), 0.5);
+      r[c * nh + k] = down<T>(rc);
+      if (kp != k) r[c * nh + kp] = down<T>(conj(rc));
+      rv[c] = up(down<T>(rc));
+    }
+    precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
+    const double w = (kp != k) ? 2.0 : 1.0;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
+      b += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
+    }
+    rz += w * a;
+    rr += w * b;
+  }
+  const double s1 = block_sum<kVecThreads>(rz, red);
+  const double s2 = block_sum<kVecThreads>(rr, red);
+  if (threadIdx.x == 0) {
+    partials[2 * chunk] = s1;
+    partials[2 * chunk + 1] = s2;
+  }
+}
+
+// fused CG: x += alpha p (if this iteration's step is pending), then
+// p = M r + beta p (unless converged)
+template <typename T>
+__device__ __forceinline__ void xp_core(cpx<T>* __restrict__ x, cpx<T>* __restrict__ p, const cpx<T>* __restrict__ r,
+                                        const PcgScalars* __restrict__ sc, const PrecondArgs& pa, const Geom& g,
+                                        int chunk, int nchunks) {
+  const int pending = sc->pending;
+  const int conv = sc->converged;
+  if (!pending && conv) return;
+  const double alpha = sc->alpha, beta = sc->beta;
+  const long long nh = g.nh;
+  for (long long k = (long long)chunk * kVecThreads + threadIdx.x; k < nh;
+       k += (long long)nchunks * kVecThreads) {
+    const FreqIdx f = decode(k, g);
+    cpx<double> pv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pv[c] = up(p[c * nh + k]);
+    if (pending) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[c * nh + k] = down<T>(add(up(x[c * nh + k]), scl(pv[c], alpha)));
+    }
+    if (!conv) {
+      cpx<double> rv[3], zv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rv[c] = up(r[c * nh + k]);
+      precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[c * nh + k] = down<T>(add(zv[c], scl(pv[c], beta)));
+    }
+  }
 }
 
 }  // namespace dbfft
