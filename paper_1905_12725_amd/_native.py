@@ -31,7 +31,7 @@ EXPORTED = (
     "dbfft_batch_destroy",
 )
 KERNEL_KINDS = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div",
-                "cg_alpha", "cg_update", "cg_beta", "cg_direction", "cg_planes")
+                "cg_alpha", "cg_update", "cg_beta", "cg_direction")
 
 
 class Opts(ct.Structure):

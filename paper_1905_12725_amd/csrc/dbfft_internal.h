@@ -156,28 +156,30 @@ void launch_pcg_pupdate(void* p, const void* r, const PcgScalars* sc, const Prec
 template <typename T>
 void launch_precond_init(void* p, void* r, const PrecondArgs& pa, const Geom& g, double* partials,
                          int nblocks, hipStream_t st);
-// Fused CG iteration (small strains, register-FFT x pass): alpha right
-// after the z pass; the divergence pass updates r in place and emits the
-// partial sums of <r, M r> and <r, r> off the self-conjugate planes; the
-// plane kernel projects r onto Hermitian pairs there and adds their sums;
-// beta takes the macroscopic step with the divergence pass's average stress;
-// the direction kernel adds alpha p to x and forms the next p.
-constexpr int kPlaneBlocks = 256;
+// Fused CG iteration (small strains, register-FFT x pass, n2 even): alpha
+// after the z pass (first block of the y pass, or its own kernel); the
+// divergence pass updates r in place, projects it onto Hermitian pairs on
+// the self-conjugate planes and emits the partial sums of <r, M r> and
+// <r, r>; beta takes the macroscopic step with the divergence pass's average
+// stress; the direction kernel adds alpha p to x and forms the next p.
 void launch_pcg_alpha_only(PcgScalars* sc, const double* partials, int nparts, hipStream_t st);
 void launch_pcg_beta_step(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                           hipStream_t st);
 template <typename T>
-void launch_pcg_planes(void* r, const PrecondArgs& pa, const Geom& g, double* partials, hipStream_t st,
-                       const int* stop);
-template <typename T>
 void launch_pcg_xp(void* x, void* p, const void* r, const PcgScalars* sc, const PrecondArgs& pa, const Geom& g,
                    int nblocks, hipStream_t st);
-// x forward transform + divergence + r -= alpha q (T = float or double);
-// returns the number of partial-sum pairs written to `partials`
+// x forward transform + divergence + r -= alpha q + Hermitian planes
+// (T = float or double; n2 even; alpha already in the scalars); returns the number of partial-sum
+// pairs written to `partials`
 template <typename T>
 int launch_div_update_fast(const void* W, void* r, const StridedGeom& sg, const Geom& g, const void* tw,
                            const PcgScalars* sc, const PrecondArgs& pa, double* dc_out, double* partials,
-                           hipStream_t st, const int* stop);
+                           hipStream_t st);
+// plain register-FFT y pass whose first block also computes alpha
+template <typename T>
+void launch_strided_fast_alpha(const void* in, void* out, int ncomp, const StridedGeom& sg, const Geom& g,
+                               const void* tw, int dir, hipStream_t st, const int* stop, PcgScalars* sc,
+                               const double* eparts, int neparts);
 int fused_cg_partials(const Geom& g);
 void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                       hipStream_t st);

@@ -199,7 +199,7 @@ struct Ctx {
 };
 
 enum ProfKind {
-  PK_XINV = 0, PK_YINV, PK_ZFUSED, PK_YFWD, PK_XFWD, PK_ALPHA, PK_UPDATE, PK_BETA, PK_PUPDATE, PK_PLANES, PK_END
+  PK_XINV = 0, PK_YINV, PK_ZFUSED, PK_YFWD, PK_XFWD, PK_ALPHA, PK_UPDATE, PK_BETA, PK_PUPDATE, PK_END
 };
 
 // records an event that marks the start of a kernel of `kind` (PK_END closes)
@@ -605,14 +605,15 @@ static PcgOut pcg_result(Ctx& c) {
 }
 
 // The fused iteration needs the register-FFT x pass (n1 a power of two from
-// 8 to 256) and small strains; DBFFT_UNFUSED=1 selects the separate vector
+// 8 to 256), n2 even (Hermitian partner lines in the same block) and small
+// strains; DBFFT_UNFUSED=1 selects the separate vector
 // kernels everywhere (same arithmetic, other summation order).
 static bool fused_cg(const Ctx& c) {
   static const bool off = [] {
     const char* e = std::getenv("DBFFT_UNFUSED");
     return e != nullptr && e[0] == '1';
   }();
-  return !off && c.kin == KIN_SMALL && fast_strided_supported(c.n[0]);
+  return !off && c.kin == KIN_SMALL && fast_strided_supported(c.n[0]) && c.n[1] % 2 == 0;
 }
 
 // Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
@@ -631,8 +632,9 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
     for (int k = 0; k < check_every; ++k) {
       c.prof_tag = k;
       if (fused) {
-        // gradient | y | z (+ <p, K p>) | alpha | y | divergence with r -= alpha q
-        // | Hermitian planes | beta (+ macroscopic step) | x += alpha p, next p
+        // gradient | y | z (+ <p, K p> partials) | y (its first block: alpha)
+        // | divergence with r -= alpha q and the Hermitian planes | beta (+
+        // macroscopic step) | x += alpha p, next p
         Tables<T>& tb = tables<T>(c);
         const StridedGeom sx = xgeom(c), sy = ygeom(c);
         prof_mark(c, PK_XINV);
@@ -642,16 +644,19 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
         prof_mark(c, PK_ZFUSED);
         launch_line<T>(LP_FUSED, c.kin, c.W, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, pmac, nullptr, c.partA, c.ncomp,
                        c.st, nullptr, stop);
-        prof_mark(c, PK_ALPHA);
-        launch_pcg_alpha_only(c.sc_dev, c.partA, neb, c.st);
-        prof_mark(c, PK_YFWD);
-        launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
+        if (fast_strided_supported(c.n[1])) {
+          prof_mark(c, PK_YFWD);
+          launch_strided_fast_alpha<T>(c.W, c.W, c.ncomp, sy, c.g, tb.tw2, -1, c.st, stop, c.sc_dev, c.partA, neb);
+        } else {
+          prof_mark(c, PK_ALPHA);
+          launch_pcg_alpha_only(c.sc_dev, c.partA, neb, c.st);
+          prof_mark(c, PK_YFWD);
+          launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
+        }
         prof_mark(c, PK_XFWD);
-        const int nd = launch_div_update_fast<T>(c.W, r, sx, c.g, tb.tw1, c.sc_dev, pa, c.dc_dev, c.partB, c.st, stop);
-        prof_mark(c, PK_PLANES);
-        launch_pcg_planes<T>(r, pa, c.g, c.partB + 2 * nd, c.st, stop);
+        const int nd = launch_div_update_fast<T>(c.W, r, sx, c.g, tb.tw1, c.sc_dev, pa, c.dc_dev, c.partB, c.st);
         prof_mark(c, PK_BETA);
-        launch_pcg_beta_step(c.sc_dev, c.partB, nd + kPlaneBlocks, c.dc_dev, pc, c.st);
+        launch_pcg_beta_step(c.sc_dev, c.partB, nd, c.dc_dev, pc, c.st);
         prof_mark(c, PK_PUPDATE);
         launch_pcg_xp<T>(x, p, r, c.sc_dev, pa, c.g, nb, c.st);
         continue;

@@ -115,6 +115,32 @@ __device__ __forceinline__ constexpr int fast_out_pos(int g) {
 }
 
 // ------------------------------------------------------------------ x / y passes
+// Fused CG: alpha = <r, M r> / <p, K p> from the z pass's energy partials
+// (fixed-order sum), done by one block of the following y pass; marks the
+// step pending for the direction kernel, or flags a breakdown.  A converged
+// iteration clears the pending step.
+template <int NT>
+__device__ __forceinline__ void alpha_task(PcgScalars* sc, const double* __restrict__ eparts, int neparts) {
+  __shared__ double red[NT / 64];
+  if (sc->converged) {
+    if (threadIdx.x == 0) sc->pending = 0;
+    return;
+  }
+  double e = 0.0;
+  for (int i = threadIdx.x; i < neparts; i += NT) e += eparts[i];
+  const double pq = block_sum<NT>(e, red);
+  if (threadIdx.x == 0) {
+    sc->pq = pq;
+    if (!(pq > 0.0)) {
+      sc->converged = 2;
+      sc->pending = 0;
+    } else {
+      sc->alpha = sc->rz / pq;
+      sc->pending = 1;
+    }
+  }
+}
+
 // Elements per thread: 4 for the FP64 passes that keep several vectors
 // live (gradient, divergence), 8 otherwise.
 template <typename T, int N, int MODE>
@@ -150,7 +176,11 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT), (strided_min_waves<T>(MODE))) void k_strided_fast(const cpx<T>* in, cpx<T>* out, StridedGeom sg,
                                                                       Geom g, const cpx<T>* __restrict__ twg, T d,
                                                                       double* __restrict__ dc_out,
-                                                                      const int* __restrict__ stop) {
+                                                                      const int* __restrict__ stop,
+                                                                      PcgScalars* alpha_sc, const double* eparts,
+                                                                      int neparts) {
+  if (alpha_sc != nullptr && blockIdx.x == 0 && blockIdx.z == 0)
+    alpha_task<StridedShape<N, strided_E<T, N, MODE>()>::NT>(alpha_sc, eparts, neparts);
   if (stop != nullptr && *stop) return;
   constexpr int E = strided_E<T, N, MODE>();
   using S = StridedShape<N, E>;
@@ -358,17 +388,60 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT), (st
   }
 }
 
-// Fused CG step in the last forward pass (small strains): the divergence
-// q = -i xi . sigma_hat of the x-transformed stress stays in registers and
-// r -= alpha q is applied at once; the block's partial sums of <r, M r> and
-// <r, r> (weight 2) skip the self-conjugate planes k3 = 0 and n3/2, whose
-// points the plane kernel projects and sums afterwards.
+// Fused CG step in the last forward pass (small strains).
+//  * alpha is already in the scalars (computed by the first block of the
+//    preceding y pass, or by the alpha kernel).
+//  * The divergence q = -i xi . sigma_hat stays in registers and
+//    r -= alpha q is applied at once.
+//  * The first tiles take the self-conjugate columns k3 = 0 and n3/2 with
+//    the k2 lines ordered 0, n2/2, 1, n2-1, 2, n2-2, ..., so the Hermitian
+//    partner line (-k2) of every plane line sits in the neighbouring tile
+//    column (or is the line itself); these plane tiles project r onto
+//    Hermitian pairs through LDS before storing it.  The other tiles take
+//    the (k2, k3) pairs in their natural order (line-aligned) and leave the
+//    self-conjugate columns out.
+//  * Block partial sums of <r, M r> and <r, r> (weight 2 off the planes, 1 on
+//    them, where both points of a pair are counted).
+template <int TZ>
+__host__ __device__ __forceinline__ long long div_plane_pad(int n2) {
+  return (2LL * n2 + TZ - 1) / TZ * TZ;
+}
+
+template <int TZ>
+__device__ __forceinline__ void div_pair(long long pr, int n2, int nh3, bool& valid, int& o, int& col,
+                                         int& sp_xor) {
+  const long long Pp = div_plane_pad<TZ>(n2);
+  valid = true;
+  sp_xor = 0;
+  if (pr >= Pp) {
+    // interior tile: natural (k2, k3) order, self-conjugate columns left out
+    const long long q = pr - Pp;
+    o = (int)(q / nh3);
+    col = (int)(q - (long long)o * nh3);
+    if (o >= n2 || col == 0 || col == nh3 - 1) valid = false;
+    if (o >= n2) o = 0;
+    return;
+  }
+  if (pr >= 2LL * n2) {
+    valid = false;
+    o = 0;
+    col = 0;
+    return;
+  }
+  const int plane = (int)(pr / n2), j = (int)(pr - (long long)plane * n2);
+  col = plane ? nh3 - 1 : 0;
+  if (j == 0) o = 0;
+  else if (j == 1) o = n2 / 2;
+  else {
+    o = (j & 1) ? n2 - j / 2 : j / 2;
+    sp_xor = 1;
+  }
+}
+
 template <typename T, int N>
 __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::NT)) void k_div_update_fast(
     const cpx<T>* in, cpx<T>* r, StridedGeom sg, Geom g, const cpx<T>* __restrict__ twg,
-    const PcgScalars* __restrict__ sc, PrecondArgs pa, double* __restrict__ dc_out, double* __restrict__ partials,
-    const int* __restrict__ stop) {
-  if (stop != nullptr && *stop) return;
+    const PcgScalars* __restrict__ sc, PrecondArgs pa, double* __restrict__ dc_out, double* __restrict__ partials) {
   constexpr int E = strided_E<T, N, SP_DIV_SMALL>();
   using S = StridedShape<N, E>;
   constexpr int TL = S::TL, TZ = S::TZ, NT = S::NT, PITCH = S::PITCH;
@@ -376,6 +449,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
   __shared__ cpx<T> lds[N * PITCH];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
+  if (sc->converged) return;
   const int s = tid % TZ, t = tid / TZ;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
@@ -383,11 +457,10 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
   const int per = nb >> 3;
   const int b = blockIdx.x;
   const int tile = (b < (per << 3)) ? (b & 7) * per + (b >> 3) : b;
-  const long long npair = (long long)sg.nother * sg.ncols;
-  const long long pr = (long long)tile * TZ + s;
-  const bool valid = pr < npair;
-  const int o = valid ? (int)(pr / sg.ncols) : 0;
-  const int col = valid ? (int)(pr - (long long)o * sg.ncols) : 0;
+  const bool plane_tile = (long long)tile * TZ < div_plane_pad<TZ>(sg.nother);
+  bool valid;
+  int o, col, sp_xor;
+  div_pair<TZ>((long long)tile * TZ + s, sg.nother, sg.ncols, valid, o, col, sp_xor);
   const long long base = (long long)o * sg.ostride + col;
   const long long ls = sg.lstride;
   const T d = (T)-1;
@@ -430,35 +503,57 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
       }
     }
   }
-  // q = -i a; r -= alpha q
   const double alpha = sc->alpha;
-  const bool plane = (col == 0) || (2 * col == g.n3);
+  // r -= alpha q with q = -i a, rounded to the storage precision
   const long long cs = sg.cstride_out;
+  cpx<T> rn[3][E];
+#pragma unroll
+  for (int gq = 0; gq < E; ++gq) {
+    const long long off = base + (long long)(t + TL * fast_out_pos<N, E>(gq)) * ls;
+    const cpx<T> qv[3] = {muli(a0[gq], (T)-1), muli(a1[gq], (T)-1), muli(a2[gq], (T)-1)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      rn[c][gq] = valid ? down<T>(sub(up(r[off + c * cs]), scl(up(qv[c]), alpha))) : mk<T>(0, 0);
+  }
+  if (plane_tile) {
+    // Hermitian projection: element (k1, line) pairs with (-k1, partner line)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      __syncthreads();
+#pragma unroll
+      for (int gq = 0; gq < E; ++gq) lds[(t + TL * fast_out_pos<N, E>(gq)) * PITCH + s] = rn[c][gq];
+      __syncthreads();
+#pragma unroll
+      for (int gq = 0; gq < E; ++gq) {
+        const int k1 = t + TL * fast_out_pos<N, E>(gq);
+        const int k1p = (k1 == 0) ? 0 : N - k1;
+        const cpx<T> pv = lds[k1p * PITCH + (s ^ sp_xor)];
+        rn[c][gq] = down<T>(scl(add(up(rn[c][gq]), conj(up(pv))), 0.5));
+      }
+    }
+  }
   double rz = 0.0, rr = 0.0;
+  const double w = plane_tile ? 1.0 : 2.0;
 #pragma unroll
   for (int gq = 0; gq < E; ++gq) {
     const int k1 = t + TL * fast_out_pos<N, E>(gq);
     const long long off = base + (long long)k1 * ls;
-    cpx<double> rv[3];
-    const cpx<T> qv[3] = {muli(a0[gq], (T)-1), muli(a1[gq], (T)-1), muli(a2[gq], (T)-1)};
+    if (!valid) continue;
+    cpx<double> rv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cpx<double> rc = valid ? sub(up(r[off + c * cs]), scl(up(qv[c]), alpha)) : mk<double>(0, 0);
-      if (valid) r[off + c * cs] = down<T>(rc);
-      rv[c] = up(down<T>(rc));
+      r[off + c * cs] = rn[c][gq];
+      rv[c] = up(rn[c][gq]);
     }
-    if (valid && !plane) {
-      cpx<double> zv[3];
-      precond(pa, xi_of(k1, g.n1), xi_of(o, g.n2), xi_of(col, g.n3), rv, zv);
-      double a = 0.0, bb = 0.0;
+    precond(pa, xi_of(k1, g.n1), xi_of(o, g.n2), xi_of(col, g.n3), rv, zv);
+    double a = 0.0, bb = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        a += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
-        bb += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
-      }
-      rz += 2.0 * a;
-      rr += 2.0 * bb;
+    for (int c = 0; c < 3; ++c) {
+      a += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
+      bb += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
     }
+    rz += w * a;
+    rr += w * bb;
   }
   const double s1 = block_sum<NT>(rz, red);
   const double s2 = block_sum<NT>(rr, red);
@@ -471,47 +566,66 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
 template <typename T, int N>
 static int launch_div_update_n(const void* W, void* r, const StridedGeom& sg, const Geom& g, const void* tw,
                                const PcgScalars* sc, const PrecondArgs& pa, double* dc_out, double* partials,
-                               hipStream_t st, const int* stop) {
+                               hipStream_t st) {
   using S = StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>;
-  const long long npair = (long long)sg.nother * sg.ncols;
+  const long long npair = div_plane_pad<S::TZ>(sg.nother) + (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
   hipLaunchKernelGGL((k_div_update_fast<T, N>), dim3(ntiles), dim3(S::NT), 0, st, static_cast<const cpx<T>*>(W),
-                     static_cast<cpx<T>*>(r), sg, g, static_cast<const cpx<T>*>(tw), sc, pa, dc_out, partials, stop);
+                     static_cast<cpx<T>*>(r), sg, g, static_cast<const cpx<T>*>(tw), sc, pa, dc_out, partials);
   return ntiles;
 }
 
 template <typename T>
 int launch_div_update_fast(const void* W, void* r, const StridedGeom& sg, const Geom& g, const void* tw,
                            const PcgScalars* sc, const PrecondArgs& pa, double* dc_out, double* partials,
-                           hipStream_t st, const int* stop) {
+                           hipStream_t st) {
   switch (sg.nline) {
-    case 8: return launch_div_update_n<T, 8>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
-    case 16: return launch_div_update_n<T, 16>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
-    case 32: return launch_div_update_n<T, 32>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
-    case 64: return launch_div_update_n<T, 64>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
-    case 128: return launch_div_update_n<T, 128>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
-    default: return launch_div_update_n<T, 256>(W, r, sg, g, tw, sc, pa, dc_out, partials, st, stop);
+    case 8: return launch_div_update_n<T, 8>(W, r, sg, g, tw, sc, pa, dc_out, partials, st);
+    case 16: return launch_div_update_n<T, 16>(W, r, sg, g, tw, sc, pa, dc_out, partials, st);
+    case 32: return launch_div_update_n<T, 32>(W, r, sg, g, tw, sc, pa, dc_out, partials, st);
+    case 64: return launch_div_update_n<T, 64>(W, r, sg, g, tw, sc, pa, dc_out, partials, st);
+    case 128: return launch_div_update_n<T, 128>(W, r, sg, g, tw, sc, pa, dc_out, partials, st);
+    default: return launch_div_update_n<T, 256>(W, r, sg, g, tw, sc, pa, dc_out, partials, st);
   }
 }
 template int launch_div_update_fast<double>(const void*, void*, const StridedGeom&, const Geom&, const void*,
-                                            const PcgScalars*, const PrecondArgs&, double*, double*, hipStream_t,
-                                            const int*);
+                                            const PcgScalars*, const PrecondArgs&, double*, double*, hipStream_t);
 template int launch_div_update_fast<float>(const void*, void*, const StridedGeom&, const Geom&, const void*,
-                                           const PcgScalars*, const PrecondArgs&, double*, double*, hipStream_t,
-                                           const int*);
+                                           const PcgScalars*, const PrecondArgs&, double*, double*, hipStream_t);
 
 bool fast_strided_supported(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
 template <typename T, int N, int MODE>
 static void launch_fast_nm(const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
-                           const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+                           const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                           PcgScalars* alpha_sc = nullptr, const double* eparts = nullptr, int neparts = 0) {
   using S = StridedShape<N, strided_E<T, N, MODE>()>;
   const long long npair = (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
   dim3 grid(ntiles, 1, MODE == SP_PLAIN ? ncomp_plain : 1);
   hipLaunchKernelGGL((k_strided_fast<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
-                     static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop);
+                     static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop, alpha_sc,
+                     eparts, neparts);
 }
+
+// plain y pass whose first block also computes alpha (fused CG)
+template <typename T>
+void launch_strided_fast_alpha(const void* in, void* out, int ncomp, const StridedGeom& sg, const Geom& g,
+                               const void* tw, int dir, hipStream_t st, const int* stop, PcgScalars* sc,
+                               const double* eparts, int neparts) {
+  switch (sg.nline) {
+    case 8: launch_fast_nm<T, 8, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
+    case 16: launch_fast_nm<T, 16, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
+    case 32: launch_fast_nm<T, 32, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
+    case 64: launch_fast_nm<T, 64, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
+    case 128: launch_fast_nm<T, 128, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
+    default: launch_fast_nm<T, 256, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
+  }
+}
+template void launch_strided_fast_alpha<double>(const void*, void*, int, const StridedGeom&, const Geom&, const void*,
+                                                int, hipStream_t, const int*, PcgScalars*, const double*, int);
+template void launch_strided_fast_alpha<float>(const void*, void*, int, const StridedGeom&, const Geom&, const void*,
+                                               int, hipStream_t, const int*, PcgScalars*, const double*, int);
 
 template <typename T, int N>
 static void launch_fast_n(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,

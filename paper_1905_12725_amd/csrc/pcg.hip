@@ -61,13 +61,6 @@ __global__ __launch_bounds__(kVecThreads) void k_beta_step(PcgScalars* __restric
 }
 
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_planes(cpx<T>* __restrict__ r, PrecondArgs pa, Geom g,
-                                                        double* __restrict__ partials, const int* __restrict__ stop) {
-  if (stop != nullptr && *stop) return;
-  planes_core<T>(r, pa, g, partials, blockIdx.x, gridDim.x);
-}
-
-template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_xp(cpx<T>* __restrict__ x, cpx<T>* __restrict__ p,
                                                     const cpx<T>* __restrict__ r, const PcgScalars* __restrict__ sc,
                                                     PrecondArgs pa, Geom g) {
@@ -82,27 +75,20 @@ void launch_pcg_beta_step(PcgScalars* sc, const double* partials, int nparts, co
   hipLaunchKernelGGL(k_beta_step, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
 }
 template <typename T>
-void launch_pcg_planes(void* r, const PrecondArgs& pa, const Geom& g, double* partials, hipStream_t st,
-                       const int* stop) {
-  hipLaunchKernelGGL((k_planes<T>), dim3(kPlaneBlocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(r), pa, g,
-                     partials, stop);
-}
-template <typename T>
 void launch_pcg_xp(void* x, void* p, const void* r, const PcgScalars* sc, const PrecondArgs& pa, const Geom& g,
                    int nblocks, hipStream_t st) {
   hipLaunchKernelGGL((k_xp<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(x),
                      static_cast<cpx<T>*>(p), static_cast<const cpx<T>*>(r), sc, pa, g);
 }
-template void launch_pcg_planes<double>(void*, const PrecondArgs&, const Geom&, double*, hipStream_t, const int*);
-template void launch_pcg_planes<float>(void*, const PrecondArgs&, const Geom&, double*, hipStream_t, const int*);
 template void launch_pcg_xp<double>(void*, void*, const void*, const PcgScalars*, const PrecondArgs&, const Geom&, int,
                                     hipStream_t);
 template void launch_pcg_xp<float>(void*, void*, const void*, const PcgScalars*, const PrecondArgs&, const Geom&, int,
                                    hipStream_t);
 
 int fused_cg_partials(const Geom& g) {
-  // divergence tiles (at least 4 columns each) plus the plane kernel's blocks, two sums each
-  return 2 * (int)(((long long)g.n2 * g.nh3 + 3) / 4 + kPlaneBlocks);
+  // divergence tiles (at least 8 columns each): all (k2, k3) pairs, padding,
+  // then the two plane columns again; two sums each
+  return 2 * (int)(((long long)g.n2 * (g.nh3 + 2) + 7) / 8 + 2);
 }
 
 template <typename T>

@@ -348,52 +348,6 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
   else if (sc->iter >= pc.max_iter) sc->converged = 3;
 }
 
-// fused CG: Hermitian projection of r on the self-conjugate planes and the
-// partial sums of <r, M r>, <r, r> over their points (pairs count twice)
-template <typename T>
-__device__ __forceinline__ void planes_core(cpx<T>* __restrict__ r, const PrecondArgs& pa, const Geom& g,
-                                            double* __restrict__ partials, int chunk, int nchunks) {
-  __shared__ double red[kVecThreads / 64];
-  double rz = 0.0, rr = 0.0;
-  const long long nh = g.nh;
-  const long long plane = (long long)g.n1 * g.n2;
-  for (long long i = (long long)chunk * kVecThreads + threadIdx.x; i < 2 * plane;
-       i += (long long)nchunks * kVecThreads) {
-    FreqIdx f;
-    const long long rem = i % plane;
-    f.k1 = (int)(rem / g.n2);
-    f.k2 = (int)(rem % g.n2);
-    f.k3 = (i < plane) ? 0 : g.n3 / 2;
-    const long long k = ((long long)f.k1 * g.n2 + f.k2) * g.nh3 + f.k3;
-    const long long kp = partner_index(f, g);
-    if (kp < k) continue;
-    cpx<double> rv[3], zv[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cpx<double> rc = scl(add(up(r[c * nh + k]), conj(up(r[c * nh + kp]))), 0.5);
-      r[c * nh + k] = down<T>(rc);
-      if (kp != k) r[c * nh + kp] = down<T>(conj(rc));
-      rv[c] = up(down<T>(rc));
-    }
-    precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
-    const double w = (kp != k) ? 2.0 : 1.0;
-    double a = 0.0, b = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      a += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
-      b += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
-    }
-    rz += w * a;
-    rr += w * b;
-  }
-  const double s1 = block_sum<kVecThreads>(rz, red);
-  const double s2 = block_sum<kVecThreads>(rr, red);
-  if (threadIdx.x == 0) {
-    partials[2 * chunk] = s1;
-    partials[2 * chunk + 1] = s2;
-  }
-}
-
 // fused CG: x += alpha p (if this iteration's step is pending), then
 // p = M r + beta p (unless converged)
 template <typename T>
