@@ -235,6 +235,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--unfused", action="store_true", help="separate CG vector kernels (fused_cg = 0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -270,8 +271,9 @@ def main():
     log(f"[bench] {n} spheres vf={phase.mean():.4f}, contrast 100, 6 load cases")
 
     cell = Cell(n, "iso_phase", torch.from_numpy(phase), params)
+    fo = {"fused_cg": 0 if args.unfused else 1}
     for _ in range(args.warmup):
-        run_cases(cell, loads, tol=1e-8)
+        run_cases(cell, loads, tol=1e-8, **fo)
     log("[bench] warmup done")
 
     cell.kernel_timing(True)
@@ -280,7 +282,7 @@ def main():
     total_iters = 0
     cols64 = None
     for s in range(args.steps):
-        cols64, it, _ = run_cases(cell, loads, tol=1e-8)
+        cols64, it, _ = run_cases(cell, loads, tol=1e-8, **fo)
         total_iters += it
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -351,21 +353,26 @@ def main():
 
     # tight FP64 reference for accuracy, then FP32-mixed vs FP64 at equal accuracy
     if not args.no_mixed:
-        ref_cols, _, _ = run_cases(cell, loads, tol=1e-10, tol_load=1e-10)
+        ref_cols, _, _ = run_cases(cell, loads, tol=1e-10, tol_load=1e-10, **fo)
         Cref = ceff(ref_cols)
 
         def err(cols):
             return float(np.max(np.abs(ceff(cols) - Cref)) / np.max(np.abs(Cref)))
 
         mixed = Cell(n, "iso_phase", torch.from_numpy(phase), params, precision="fp32_mixed")
-        run_cases(mixed, loads, tol=1e-8)  # warm
+        run_cases(mixed, loads, tol=1e-8, **fo)  # warm
+        # per-kernel HIP-event times of the FP32 inner iterations (tol 1e-8 solves)
+        mixed.kernel_timing(True)
+        run_cases(mixed, loads, tol=1e-8, **fo)
+        kt32 = mixed.kernel_timing(False)
+        out["fp32_mixed_kernels_us"] = {k: ms_tot / cnt * 1e3 for k, (ms_tot, cnt) in kt32.items() if cnt > 0}
         res = {}
         for name, c in (("fp64", cell), ("fp32_mixed", mixed)):
             best = None
             for tol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                cols, it, rf = run_cases(c, loads, tol=tol)
+                cols, it, rf = run_cases(c, loads, tol=tol, **fo)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t
                 e = err(cols)

@@ -92,6 +92,10 @@ typedef struct {
   double inner_tol;    /* FP32_MIXED: relative reduction asked of each inner FP32 solve; 1e-4 */
   int32_t max_refine;  /* FP32_MIXED: outer FP64 residual corrections; 30 */
   int32_t check_every; /* PCG iterations enqueued between host convergence polls; 8 */
+  int32_t fused_cg;    /* 1: fused CG iteration where it applies (small strains, n1 a power of two
+                          from 8 to 256, n2 even): the divergence pass updates the residual, no
+                          separate update kernel; 0: separate vector kernels.  Same arithmetic,
+                          other summation order; 1 */
 } dbfft_opts;
 
 typedef struct {

@@ -45,6 +45,7 @@ class Opts(ct.Structure):
         ("inner_tol", ct.c_double),
         ("max_refine", ct.c_int32),
         ("check_every", ct.c_int32),
+        ("fused_cg", ct.c_int32),
     ]
 
 

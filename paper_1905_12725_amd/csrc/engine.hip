@@ -195,6 +195,7 @@ struct Ctx {
   double EU_st[9] = {0};   // prescribed strain part (stored order)
   double e_st[9] = {0};    // macro unknown as a tensor (stored order)
   double sig_rm[9] = {0}, eps_rm[9] = {0};
+  bool use_fused = true;  // opts.fused_cg of the current call
   bool linear_material() const { return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE; }
 };
 
@@ -606,14 +607,9 @@ static PcgOut pcg_result(Ctx& c) {
 
 // The fused iteration needs the register-FFT x pass (n1 a power of two from
 // 8 to 256), n2 even (Hermitian partner lines in the same block) and small
-// strains; DBFFT_UNFUSED=1 selects the separate vector
-// kernels everywhere (same arithmetic, other summation order).
+// strains; opts.fused_cg = 0 selects the separate vector kernels.
 static bool fused_cg(const Ctx& c) {
-  static const bool off = [] {
-    const char* e = std::getenv("DBFFT_UNFUSED");
-    return e != nullptr && e[0] == '1';
-  }();
-  return !off && c.kin == KIN_SMALL && fast_strided_supported(c.n[0]) && c.n[1] % 2 == 0;
+  return c.use_fused && c.kin == KIN_SMALL && fast_strided_supported(c.n[0]) && c.n[1] % 2 == 0;
 }
 
 // Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
@@ -1773,6 +1769,7 @@ void dbfft_default_opts(dbfft_opts* o) {
   o->inner_tol = 1e-4;
   o->max_refine = 30;
   o->check_every = 8;
+  o->fused_cg = 1;
 }
 
 const char* dbfft_last_error(void) { return g_err.c_str(); }
@@ -1901,6 +1898,7 @@ dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t str
   dbfft_opts o;
   if (opts) o = *opts;
   else dbfft_default_opts(&o);
+  c.use_fused = o.fused_cg != 0;
   int mask[9];
   for (int i = 0; i < 9; ++i) mask[i] = stress_mask[i] ? 1 : 0;
   if (c.kin == KIN_SMALL) {

@@ -141,11 +141,17 @@ __device__ __forceinline__ void alpha_task(PcgScalars* sc, const double* __restr
   }
 }
 
-// Elements per thread: 4 for the FP64 passes that keep several vectors
-// live (gradient, divergence), 8 otherwise.
+// Elements per thread: 4 for the passes that keep several vectors live
+// (gradient, divergence), 8 for the plain ones.
+#ifndef DBFFT_F32_FUSED_E
+#define DBFFT_F32_FUSED_E 4
+#endif
+#ifndef DBFFT_F32_LINE_E
+#define DBFFT_F32_LINE_E 4
+#endif
 template <typename T, int N, int MODE>
 constexpr int strided_E() {
-  return (sizeof(T) == 8 && MODE != SP_PLAIN && N <= 128) ? 4 : 8;
+  return (MODE != SP_PLAIN && N <= 128) ? (sizeof(T) == 8 ? 4 : DBFFT_F32_FUSED_E) : 8;
 }
 template <int N, int E>
 struct StridedShape {
@@ -666,10 +672,10 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
   return mk<T>(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
-// Elements per thread of the z pass: 4 in FP64, 8 in FP32.
+// Elements per thread of the z pass.
 template <typename T>
 constexpr int line_E() {
-  return sizeof(T) == 8 ? 4 : 8;
+  return sizeof(T) == 8 ? 4 : DBFFT_F32_LINE_E;
 }
 template <typename T, int M, int E>
 struct LineCtx {
@@ -932,7 +938,7 @@ bool fast_line_supported(int n3) { return n3 == 16 || n3 == 32 || n3 == 64 || n3
 
 int fast_line_blocks(const Geom& g, int elem_bytes) {
   const int M = g.n3 / 2;
-  const int E = elem_bytes == 16 ? 4 : 8;
+  const int E = elem_bytes == 16 ? 4 : DBFFT_F32_LINE_E;
   const int LB = 64 / (M / E);
   return (int)(((long long)g.n1 * g.n2 + LB - 1) / LB);
 }

@@ -258,3 +258,37 @@ def test_solve_parity_power_of_two(gpu, n, prec):
         info = cell.solve(load, mask, tol=1e-11, tol_load=1e-11)
         sig = cell.homogenize()["sigma_bar"]
     assert rel(sig, ref.sigma_bar) < (1e-9 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("n", [(32, 16, 24), (16, 32, 32), (64, 64, 8)])
+def test_fused_cg_matches_separate_kernels(gpu, n, prec):
+    """The fused CG iteration (residual update in the divergence pass,
+    alpha in the y pass, Hermitian planes in-block) against the separate
+    vector kernels and against the oracle, mixed control (uniaxial stress)."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case fused vs separate n={n} {prec}", flush=True)
+    rng = np.random.default_rng(77)
+    phase = (rng.random(n) < 0.3).astype(np.uint8)
+    E = [1.0, 25.0]
+    mask = np.ones((3, 3), bool)
+    mask[0, 0] = False
+    load = np.zeros((3, 3))
+    load[0, 0] = 0.01
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    out = {}
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3), precision=prec) as cell:
+        for fused in (1, 0):
+            info = cell.solve(load, mask, tol=tol, tol_load=tol, fused_cg=fused)
+            a, e = cell.solution()
+            out[fused] = (info, a.cpu().numpy())
+    ref = so.solve_linear(n, oracle_iso(phase, E, 0.3), load, mask, tol=1e-12, tol_load=1e-12)
+    bar = 1e-10 if prec == "fp64" else 1e-6
+    for fused in (1, 0):
+        assert out[fused][0]["status"] == 0
+        assert rel(out[fused][0]["sigma_bar"], ref.sigma_bar) < bar
+    assert rel(out[1][0]["sigma_bar"], out[0][0]["sigma_bar"]) < bar
+    assert rel(out[1][1], out[0][1]) < (1e-9 if prec == "fp64" else 1e-5)
+    if prec == "fp64":
+        assert abs(out[1][0]["pcg_iters"] - out[0][0]["pcg_iters"]) <= 2
