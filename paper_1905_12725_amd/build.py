@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdbfft.so")
-SOURCES = ["fft_passes.hip", "fft_fast.hip", "pcg.hip", "materials.hip", "batch.hip", "engine.hip"]
+SOURCES = ["fft_passes.hip", "fft_fast.hip", "fft_mixed.hip", "pcg.hip", "materials.hip", "batch.hip", "engine.hip"]
 ARCH = os.environ.get("DBFFT_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -29,7 +29,8 @@ struct CellDesc {
   double* dc;     // average stress of the direction (DC bin of the divergence pass)
   int tzx, tzy;   // column tile widths of the x and y passes (autotuned)
   int L;          // z lines per block
-  int pad;
+  int mx, my;     // x / y pass with the two-step register transform
+  int mz;         // z pass: 0 LDS engine, 1 two-step isotropic, 2 two-step general (FP32)
 };
 
 // flattened grids of one batched iteration (block offsets per cell are
@@ -43,6 +44,22 @@ struct BatchLaunch {
   const int* boff_v;
   size_t lds_x, lds_y, lds_z;
 };
+
+// line lengths the batched two-step kernels are compiled for (x/y: n; z: n3/2)
+constexpr bool batch_two_step_xy(int n) {
+  switch (n) {
+    case 12: case 16: case 18: case 20: case 24: case 30: case 32: case 36: case 40: case 48: case 50: case 54:
+    case 60: case 64: case 72: case 80: case 90: case 96: return true;
+    default: return false;
+  }
+}
+constexpr bool batch_two_step_z(int m) {
+  switch (m) {
+    case 12: case 16: case 18: case 20: case 24: case 25: case 27: case 30: case 32: case 36: case 40: case 45:
+    case 48: case 50: case 54: case 60: case 64: return true;
+    default: return false;
+  }
+}
 
 template <typename T>
 void launch_batch_iteration(const BatchLaunch& bl, const void* desc, hipStream_t st);

@@ -9,6 +9,7 @@
 // replayed until every cell has converged.
 #include "batch.h"
 #include "fft_generic.h"
+#include "fft_mixed.h"
 #include "pcg_core.h"
 
 namespace dbfft {
@@ -33,6 +34,24 @@ __device__ __forceinline__ cpx<T>* buf_of(const CellDesc<T>& R, int which) {
     case BUF_P: return R.p;
     default: return R.q;
   }
+}
+
+// two-step tile of a cell's x or y pass; lb = component * tiles + tile
+template <typename T, int N, int MODE>
+__device__ __forceinline__ void batch_mixed_tile(const cpx<T>* in, cpx<T>* out, const StridedGeom& sg, const Geom& g,
+                                                 const cpx<T>* twg, T d, double* dc, int lb,
+                                                 unsigned char* smem_raw) {
+  using S = MixedShape<N>;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* lds = tw + N;
+  for (int i = threadIdx.x; i < N; i += kStridedThreads) tw[i] = twg[i];
+  __syncthreads();
+  const long long npair = (long long)sg.nother * sg.ncols;
+  const long long ntile = (npair + S::TZ - 1) / S::TZ;
+  const long long c = lb / ntile;
+  const long long tile = lb - c * ntile;
+  mixed_strided_tile<T, N, MODE>(in + c * sg.cstride_in, out + c * sg.cstride_out, sg, g, tw, lds, d, dc, tile,
+                                 threadIdx.x);
 }
 
 // x pass (axis 0) or y pass (axis 1) of every cell
@@ -80,7 +99,48 @@ __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>*
   sg.cstride_out = g.nh;
   (void)ncomp;
   double* dc = (MODE == SP_DIV_SMALL || MODE == SP_DIV_FINITE) ? R.dc : nullptr;
+  if (axis == 0 ? R.mx : R.my) {
+    switch (sg.nline) {
+#define DBFFT_BM(NN) \
+  case NN: batch_mixed_tile<T, NN, MODE>(buf_of(R, src), buf_of(R, dst), sg, g, tw, d, dc, lb, smem_raw); return;
+      DBFFT_BM(12) DBFFT_BM(16) DBFFT_BM(18) DBFFT_BM(20) DBFFT_BM(24) DBFFT_BM(30) DBFFT_BM(32) DBFFT_BM(36)
+      DBFFT_BM(40) DBFFT_BM(48) DBFFT_BM(50) DBFFT_BM(54) DBFFT_BM(60) DBFFT_BM(64) DBFFT_BM(72) DBFFT_BM(80)
+      DBFFT_BM(90) DBFFT_BM(96)
+#undef DBFFT_BM
+      default: return;
+    }
+  }
   strided_core<T, MODE>(buf_of(R, src), buf_of(R, dst), sg, g, *plan, tw, d, TZ, dc, tile, o, c, smem_raw);
+}
+
+// two-step z pass of a cell: four waves per block, one energy partial per block
+template <typename T, int M, int KIN>
+__device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, unsigned char* smem_raw) {
+  using L = MixedLine<M>;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* rtw = tw + M;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cpx<T>* lds = rtw + M + 1 + w * L::LB * L::PITCH;
+  __shared__ double ew[kLineThreads / 64];
+  for (int i = threadIdx.x; i < M; i += kLineThreads) tw[i] = R.tw3[i];
+  for (int i = threadIdx.x; i <= M; i += kLineThreads) rtw[i] = R.rtw[i];
+  __syncthreads();
+  const long long blk = (long long)lb * (kLineThreads / 64) + w;
+  double e = 0.0;
+  if constexpr (KIN == KIN_SMALL) {
+    if (R.mz == 1) e = mixed_line_fused<T, M, KIN_SMALL, 1>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
+    else if constexpr (sizeof(T) == 4)
+      e = mixed_line_fused<T, M, KIN_SMALL, 0>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
+  } else if constexpr (sizeof(T) == 4) {
+    e = mixed_line_fused<T, M, KIN_FINITE, 0>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
+  }
+  if (lane == 0) ew[w] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < kLineThreads / 64; ++i) s += ew[i];
+    R.partA[lb] = s;
+  }
 }
 
 template <typename T, int KIN>
@@ -91,6 +151,17 @@ __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __res
   const CellDesc<T>& R = D[r];
   if (R.sc->converged) return;
   const int lb = blockIdx.x - boff[r];
+  if (R.mz) {
+    switch (R.g.n3 / 2) {
+#define DBFFT_BZ(MM) \
+  case MM: batch_mixed_line<T, MM, KIN>(R, lb, smem_raw); return;
+      DBFFT_BZ(12) DBFFT_BZ(16) DBFFT_BZ(18) DBFFT_BZ(20) DBFFT_BZ(24) DBFFT_BZ(25) DBFFT_BZ(27) DBFFT_BZ(30)
+      DBFFT_BZ(32) DBFFT_BZ(36) DBFFT_BZ(40) DBFFT_BZ(45) DBFFT_BZ(48) DBFFT_BZ(50) DBFFT_BZ(54) DBFFT_BZ(60)
+      DBFFT_BZ(64)
+#undef DBFFT_BZ
+      default: return;
+    }
+  }
   line_core<T, LP_FUSED, KIN>(R.W, R.W, R.g, R.p3, R.tw3, R.rtw, R.tan, R.sc->pmac, nullptr, R.partA, R.L, ncomp,
                               (long long)lb, smem_raw);
 }

@@ -135,6 +135,20 @@ int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes, int tan_kind);
 
 // register-resident kernels for power-of-two transform lengths
 bool fast_strided_supported(int n);
+// two-step register z pass (fused tangent) for n3/2 a 2-3-5-smooth length
+// that is not a power of two: isotropic tangents in both precisions, any
+// tangent in FP32
+bool mixed_line_supported(int n3, int elem_bytes, bool iso);
+int mixed_line_blocks(const Geom& g);
+template <typename T>
+void launch_line_mixed(int kin, bool iso, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
+                       const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
+                       const int* stop);
+// two-step register x/y passes for 2-3-5-smooth lengths that are not powers of two
+bool mixed_strided_supported(int n);
+template <typename T>
+void launch_strided_mixed(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
+                          const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop);
 bool fast_line_supported(int n3);
 int fast_line_blocks(const Geom& g, int elem_bytes);
 template <typename T>

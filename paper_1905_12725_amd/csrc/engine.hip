@@ -18,6 +18,7 @@
 #include "../../include/dbfft.h"
 #include "dbfft_internal.h"
 #include "batch.h"
+#include "fft_mixed.h"
 
 namespace dbfft {
 
@@ -1311,7 +1312,7 @@ struct Batch {
   int chunk = 8, graph_chunk = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<int> tzx, tzy, L;
+  std::vector<int> tzx, tzy, L, mx, my, mz;
 };
 
 template <typename T>
@@ -1339,7 +1340,19 @@ static void fill_desc(Batch& B, int r, CellDesc<T>& D) {
   D.tzx = B.tzx[r];
   D.tzy = B.tzy[r];
   D.L = B.L[r];
-  D.pad = 0;
+  D.mx = B.mx[r];
+  D.my = B.my[r];
+  D.mz = B.mz[r];
+}
+
+// two-step shapes (the host side of MixedShape / MixedLine)
+static int two_step_threads(int n) {
+  const int n1 = mixed_n1(n), n2 = n / n1;
+  return n1 > n2 ? n1 : n2;
+}
+static int two_step_tz(int n) {
+  const int tl = two_step_threads(n);
+  return (256 / tl) < 32 ? (256 / tl) : 32;
 }
 
 template <typename T>
@@ -1351,6 +1364,19 @@ static void batch_build(Batch& B) {
   B.tzx.assign(n, 8);
   B.tzy.assign(n, 8);
   B.L.assign(n, 1);
+  B.mx.assign(n, 0);
+  B.my.assign(n, 0);
+  B.mz.assign(n, 0);
+  for (int r = 0; r < n; ++r) {
+    Ctx& c = *B.cells[r];
+    B.mx[r] = batch_two_step_xy(c.n[0]) ? 1 : 0;
+    B.my[r] = batch_two_step_xy(c.n[1]) ? 1 : 0;
+    const int kind = elastic_tangent<T>(c).kind;
+    const bool iso = c.kin == KIN_SMALL && (kind == TAN_ISO_PHASE || kind == TAN_ISO_FIELD);
+    if (batch_two_step_z(c.n[2] / 2) && c.n[2] % 2 == 0) B.mz[r] = iso ? 1 : (sizeof(T) == 4 ? 2 : 0);
+    if (B.mx[r]) B.tzx[r] = two_step_tz(c.n[0]);
+    if (B.my[r]) B.tzy[r] = two_step_tz(c.n[1]);
+  }
   std::vector<int> bx(n + 1, 0), by(n + 1, 0), bz(n + 1, 0), bv(n + 1, 0);
   size_t lx = 0, ly = 0, lz = 0;
   for (int r = 0; r < n; ++r) {
@@ -1372,6 +1398,7 @@ static void batch_build(Batch& B) {
     std::memset(&D, 0, sizeof(D));
     fill_desc<T>(B, r, D);
     for (int axis = 0; axis < 2; ++axis) {
+      if (axis == 0 ? B.mx[r] : B.my[r]) continue;  // two-step pass: the tile follows from the length
       const int nl = axis == 0 ? c.n[0] : c.n[1];
       float best = -1.f;
       int best_tz = 1;
@@ -1391,17 +1418,37 @@ static void batch_build(Batch& B) {
   HIPCK(hipGetLastError());
   for (int r = 0; r < n; ++r) {
     Ctx& c = *B.cells[r];
-    const int ntx = (c.g.nh3 + B.tzx[r] - 1) / B.tzx[r];
-    const int nty = (c.g.nh3 + B.tzy[r] - 1) / B.tzy[r];
-    bx[r + 1] = bx[r] + ntx * c.n[1];
-    by[r + 1] = by[r] + nty * c.n[0] * c.ncomp;
-    bz[r + 1] = bz[r] + (int)(((long long)c.n[0] * c.n[1] + B.L[r] - 1) / B.L[r]);
-    bv[r + 1] = bv[r] + pcg_block_count(c.g);
-    lx = std::max(lx, (size_t)(c.n[0] + 2 * c.n[0] * B.tzx[r]) * eb);
-    ly = std::max(ly, (size_t)(c.n[1] + 2 * c.n[1] * B.tzy[r]) * eb);
+    const long long nlines = (long long)c.n[0] * c.n[1];
+    if (B.mx[r]) {
+      const int tz = B.tzx[r];
+      bx[r + 1] = bx[r] + (int)(((long long)c.n[1] * c.g.nh3 + tz - 1) / tz);
+      lx = std::max(lx, (size_t)(c.n[0] + (size_t)c.n[0] * (tz + 1)) * eb);
+    } else {
+      const int ntx = (c.g.nh3 + B.tzx[r] - 1) / B.tzx[r];
+      bx[r + 1] = bx[r] + ntx * c.n[1];
+      lx = std::max(lx, (size_t)(c.n[0] + 2 * c.n[0] * B.tzx[r]) * eb);
+    }
+    if (B.my[r]) {
+      const int tz = B.tzy[r];
+      by[r + 1] = by[r] + c.ncomp * (int)(((long long)c.n[0] * c.g.nh3 + tz - 1) / tz);
+      ly = std::max(ly, (size_t)(c.n[1] + (size_t)c.n[1] * (tz + 1)) * eb);
+    } else {
+      const int nty = (c.g.nh3 + B.tzy[r] - 1) / B.tzy[r];
+      by[r + 1] = by[r] + nty * c.n[0] * c.ncomp;
+      ly = std::max(ly, (size_t)(c.n[1] + 2 * c.n[1] * B.tzy[r]) * eb);
+    }
     const size_t M = c.g.n3 / 2;
-    lz = std::max(lz, (size_t)(2 * M + 1) * eb + (size_t)2 * M * B.L[r] * eb + (size_t)(M + 1) * B.L[r] * eb +
-                          (size_t)c.ncomp * B.L[r] * c.g.n3 * sizeof(T));
+    if (B.mz[r]) {
+      const int tl = two_step_threads((int)M), lb = 64 / tl;
+      const long long per_block = (long long)(kLineThreads / 64) * lb;
+      bz[r + 1] = bz[r] + (int)((nlines + per_block - 1) / per_block);
+      lz = std::max(lz, (size_t)(2 * M + 1 + (size_t)(kLineThreads / 64) * lb * (M + tl + 1)) * eb);
+    } else {
+      bz[r + 1] = bz[r] + (int)((nlines + B.L[r] - 1) / B.L[r]);
+      lz = std::max(lz, (size_t)(2 * M + 1) * eb + (size_t)2 * M * B.L[r] * eb + (size_t)(M + 1) * B.L[r] * eb +
+                            (size_t)c.ncomp * B.L[r] * c.g.n3 * sizeof(T));
+    }
+    bv[r + 1] = bv[r] + pcg_block_count(c.g);
   }
   std::vector<int> boff;
   boff.insert(boff.end(), bx.begin(), bx.end());

@@ -65,9 +65,16 @@ __device__ __forceinline__ void fast_stage(cpx<T>* v, int t, const cpx<T>* __res
   }
 }
 
+// padded position of element i: one empty slot after every 2^PS elements
+// (PS = 0: no padding), so strided exchange patterns spread over the banks
+template <int PS>
+__device__ __forceinline__ constexpr int fast_pad(int i) {
+  return PS > 0 ? i + (i >> PS) : i;
+}
+
 // write the outputs of stage ST to LDS and read the inputs of stage ST+1;
-// element index i of a sequence lives at lds[i * pitch + lane_off]
-template <typename T, int N, int E, int ST>
+// element index i of a sequence lives at lds[pad(i) * pitch + lane_off]
+template <typename T, int N, int E, int ST, int PS = 0>
 __device__ __forceinline__ void fast_exchange(cpx<T>* v, int t, cpx<T>* lds, int pitch, int off) {
   constexpr int R = fast_radix<N, E>(ST), NS = fast_ns<N, E>(ST), NB = E / R;
   constexpr int R2 = fast_radix<N, E>(ST + 1), NB2 = E / R2;
@@ -77,33 +84,33 @@ __device__ __forceinline__ void fast_exchange(cpx<T>* v, int t, cpx<T>* lds, int
     const int j = t + TL * q;
     const int base = (j / NS) * NS * R + j % NS;
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[(base + r * NS) * pitch + off] = v[q * R + r];
+    for (int r = 0; r < R; ++r) lds[fast_pad<PS>(base + r * NS) * pitch + off] = v[q * R + r];
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NB2; ++q) {
     const int j = t + TL * q;
 #pragma unroll
-    for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[(j + r * (N / R2)) * pitch + off];
+    for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[fast_pad<PS>(j + r * (N / R2)) * pitch + off];
   }
   __syncthreads();
 }
 
-template <typename T, int N, int E, int ST>
+template <typename T, int N, int E, int ST, int PS>
 __device__ __forceinline__ void fast_fft_from(cpx<T>* v, int t, cpx<T>* lds, int pitch, int off,
                                               const cpx<T>* __restrict__ tw, T d) {
   fast_stage<T, N, E, ST>(v, t, tw, d);
   if constexpr (ST + 1 < fast_nstages<N, E>()) {
-    fast_exchange<T, N, E, ST>(v, t, lds, pitch, off);
-    fast_fft_from<T, N, E, ST + 1>(v, t, lds, pitch, off, tw, d);
+    fast_exchange<T, N, E, ST, PS>(v, t, lds, pitch, off);
+    fast_fft_from<T, N, E, ST + 1, PS>(v, t, lds, pitch, off, tw, d);
   }
 }
 
 // full transform of the E registers (stage-0 input -> last-stage output)
-template <typename T, int N, int E>
+template <typename T, int N, int E, int PS = 0>
 __device__ __forceinline__ void fast_fft(cpx<T>* v, int t, cpx<T>* lds, int pitch, int off,
                                          const cpx<T>* __restrict__ tw, T d) {
-  fast_fft_from<T, N, E, 0>(v, t, lds, pitch, off, tw, d);
+  fast_fft_from<T, N, E, 0, PS>(v, t, lds, pitch, off, tw, d);
 }
 
 // index of output register g (= q*R + r) of thread t
@@ -672,6 +679,16 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
   return mk<T>(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
+// Exchange padding of the z pass: one slot per 256 bytes of a line.
+template <typename T>
+constexpr int line_pad() {
+#ifdef DBFFT_Z_NOPAD
+  return 0;
+#else
+  return sizeof(T) == 8 ? 4 : 5;
+#endif
+}
+
 // Elements per thread of the z pass.
 template <typename T>
 constexpr int line_E() {
@@ -681,7 +698,7 @@ template <typename T, int M, int E>
 struct LineCtx {
   static constexpr int TL = M / E;
   static constexpr int LB = 64 / TL;
-  static constexpr int PITCH = M + 1;
+  static constexpr int PITCH = M + (M >> line_pad<T>()) + 1;
 };
 
 // inverse real transform of component c for the 8 lines of the wave:
@@ -705,7 +722,7 @@ __device__ __forceinline__ void line_inverse(const cpx<T>* src, bool valid, int 
     const cpx<T> Od = mul(sub(X[r], Xm), conj(rtw[t + TL * r]));
     Z[r] = add(Ev, muli(Od, (T)1));
   }
-  fast_fft<T, M, E>(Z, t, lds, 1, off, tw, (T)1);
+  fast_fft<T, M, E, line_pad<T>()>(Z, t, lds, 1, off, tw, (T)1);
 #pragma unroll
   for (int gq = 0; gq < E; ++gq) e[fast_out_pos<M, E>(gq)] = Z[gq];
 }
@@ -718,7 +735,7 @@ __device__ __forceinline__ void line_forward(cpx<T>* dst, bool valid, int t, int
   cpx<T> Z[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) Z[m] = e[m];
-  fast_fft<T, M, E>(Z, t, lds, 1, off, tw, (T)-1);
+  fast_fft<T, M, E, line_pad<T>()>(Z, t, lds, 1, off, tw, (T)-1);
   cpx<T> Zp[E];
 #pragma unroll
   for (int gq = 0; gq < E; ++gq) Zp[fast_out_pos<M, E>(gq)] = Z[gq];

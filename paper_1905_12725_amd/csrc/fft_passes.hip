@@ -46,6 +46,10 @@ void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const 
     launch_strided_fast<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop);
     return;
   }
+  if (mixed_strided_supported(sg.nline)) {
+    launch_strided_mixed<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop);
+    return;
+  }
   const int eb = (int)sizeof(cpx<T>);
   const int TZ = strided_tile(sg.nline, eb, mode != SP_PLAIN);
   const int ntiles = (sg.ncols + TZ - 1) / TZ;
@@ -121,6 +125,12 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
     launch_line_fast<T>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
     return;
   }
+  const bool iso = kin == KIN_SMALL && (tan.kind == TAN_ISO_PHASE || tan.kind == TAN_ISO_FIELD);
+  if (mode == LP_FUSED && macro_add == nullptr && mixed_line_supported(g.n3, (int)sizeof(cpx<T>), iso)) {
+    if (nblocks_out) *nblocks_out = mixed_line_blocks(g);
+    launch_line_mixed<T>(kin, iso, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
+    return;
+  }
   const int eb = (int)sizeof(cpx<T>);
   const int L = line_lines_per_block(g, ncomp, eb);
   const long long nlines = (long long)g.n1 * g.n2;
@@ -164,6 +174,7 @@ template void launch_line<float>(int, int, const void*, void*, const Geom&, cons
 int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes, int tan_kind) {
   const bool iso = (ncomp == 6) && (tan_kind == TAN_ISO_PHASE || tan_kind == TAN_ISO_FIELD);
   if (fast_line_supported(g.n3) && (elem_bytes == 8 || iso)) return fast_line_blocks(g, elem_bytes);
+  if (mixed_line_supported(g.n3, elem_bytes, iso)) return mixed_line_blocks(g);
   const int L = line_lines_per_block(g, ncomp, elem_bytes);
   return (int)(((long long)g.n1 * g.n2 + L - 1) / L);
 }
