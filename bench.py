@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 is recorded here and are reported as null once those change.
 TRAFFIC_SOURCES = ("paper_1905_12725_amd/csrc/fft_fast.hip", "paper_1905_12725_amd/csrc/fft_common.h",
                    "paper_1905_12725_amd/csrc/pcg_core.h", "paper_1905_12725_amd/csrc/pcg.hip")
-TRAFFIC_SHA256 = "87c7fdffbb156342d6dbd2da53e8a088afc73de157e849f110f8553e44163de7"
-TRAFFIC_128_FP64 = {"x_inverse_grad": 149477691, "x_forward_div": 149431211, "z_fused_tangent": 206523845,
-                    "y_inverse": 203751860, "y_forward": 203751860, "cg_update": 319600632,
-                    "cg_direction": 148063831}
+TRAFFIC_SHA256 = "14c150c9eb364377e4b04e36c9cc96f7a2243f6d059a49b014451ab66ba3639a"
+TRAFFIC_128_FP64 = {"x_inverse_grad": 149478896, "y_inverse": 201895042, "y_forward": 201895042,
+                    "z_fused_tangent": 206329805, "x_forward_div": 221383903, "cg_beta": 27436,
+                    "cg_direction": 247967861}
 
 
 def measured_traffic(n, kind):
@@ -159,7 +159,7 @@ def cpu_baseline(n, phase, E, nu, loads, seconds):
     }
 
 
-def batched_leg(log, ncell=32, ninc=10, seed=4):
+def batched_leg(log, ncell=32, ninc=10, seed=4, only_batched=False):
     """Uneven batch: `ncell` cubic cells with sizes drawn from the even
     2-3-5-smooth sizes in [32, 96], each a neo-Hookean two-phase sphere
     composite (centred sphere at 20 %, mu 1 / 10, kappa = 3 mu), stretched to
@@ -167,7 +167,8 @@ def batched_leg(log, ncell=32, ninc=10, seed=4):
     FP32-mixed solve (one launch per pass over all cells, graph-replayed PCG
     chunks, autotuned tiles) against the same cells solved one after the
     other in plain FP64; both at PCG tol 1e-6 and Newton tol 1e-7, errors
-    against a batched FP64 solve at 1e-10."""
+    against a batched FP64 solve at 1e-10.  `only_batched` runs the batched
+    FP32-mixed solve alone (no reference, no sequential leg), for profiling."""
     import torch
     from paper_1905_12725_amd import microstructure as ms
     from paper_1905_12725_amd.api import Cell, Batch
@@ -188,6 +189,17 @@ def batched_leg(log, ncell=32, ninc=10, seed=4):
         out = fn()
         torch.cuda.synchronize()
         return time.perf_counter() - t, out
+
+    if only_batched:
+        c32 = make("fp32_mixed")
+        with Batch(c32) as b32:
+            tb, ib = timed(lambda: b32.solve([Fbar] * ncell, None, n_increments=ninc, **opts))
+        for c in c32:
+            c.close()
+        log(f"[bench] batch workload: batched FP32-mixed {tb:.3f} s")
+        return {"sizes": sizes, "batched_fp32_mixed": {"time_s": tb,
+                                                       "pcg_iters": int(sum(i["pcg_iters"] for i in ib)),
+                                                       "newton_iters": int(sum(i["newton_iters"] for i in ib))}}
 
     c64 = make("fp64")
     with Batch(c64) as b:
@@ -225,6 +237,44 @@ def batched_leg(log, ncell=32, ninc=10, seed=4):
     }
 
 
+def contrast_sweep(log, grids=((63, 63, 63), (64, 64, 64))):
+    """Iterations against phase contrast (Sec. 3.1 strain control, Sec. 3.2
+    stress control): centred sphere inclusion at 20 %, matrix E = 70,
+    inclusion E = k * 70 for k = 1e-5 ... 1e4, nu = 0.3; uniaxial strain
+    1e-3, or uniaxial stress with the other five components zero; FP64 PCG
+    to 1e-8 equilibrium and 1e-10 loading residual, at most 1e4 iterations.
+    The odd 63^3 grid is the paper's; 64^3 is its power-of-two neighbour."""
+    import torch
+    from paper_1905_12725_amd import microstructure as ms
+    from paper_1905_12725_amd.api import Cell
+
+    ks = [10.0 ** e for e in range(-5, 5)]
+    out = {"workload": "centred sphere inclusion at 20 %, E_m = 70, E_i = k E_m, nu = 0.3, FP64, "
+                       "tol 1e-8 (equilibrium) / 1e-10 (loading)", "k": ks}
+    for n in grids:
+        phase = ms.centred_sphere(n, 0.2)
+        for control in ("strain", "stress"):
+            load = np.zeros((3, 3))
+            mask = np.zeros((3, 3), bool)
+            if control == "strain":
+                load[0, 0] = 1e-3
+            else:
+                load[0, 0] = 0.07
+                mask[:] = True
+            iters, times = [], []
+            for k in ks:
+                with Cell(n, "iso_phase", torch.from_numpy(phase), [70.0, 0.3, 70.0 * k, 0.3]) as cell:
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    info = cell.solve(load, mask, tol=1e-8, tol_load=1e-10, max_iter=10000)
+                    times.append(time.perf_counter() - t)
+                iters.append(int(info["pcg_iters"]))
+            key = f"{n[0]}x{n[1]}x{n[2]}_{control}"
+            out[key] = {"pcg_iters": iters, "solve_s": times}
+            log(f"[bench] contrast sweep {key}: iterations {iters}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +285,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the phase-contrast sweep")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched FP32-mixed solve of the uneven neo-Hookean batch (for profiling)")
     ap.add_argument("--unfused", action="store_true", help="separate CG vector kernels (fused_cg = 0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (reference kernel for HBM byte counters)")
@@ -251,6 +304,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.batch_only:
+        print(json.dumps({"batched": batched_leg(lambda m: print(m, file=sys.stderr, flush=True),
+                                                 only_batched=True)}), flush=True)
+        return
     if args.copy_calibration:
         nbytes = 1 << 30
         a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -391,6 +448,8 @@ def main():
 
     if not args.no_batch:
         out["batched"] = batched_leg(log)
+    if not args.no_sweep:
+        out["contrast_sweep"] = contrast_sweep(log)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")

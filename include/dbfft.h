@@ -15,8 +15,8 @@
  * Conventions of this library:
  *   - unit cell (all L_a = 1); fields sampled at voxel centres; even grids
  *     give the Nyquist frequency a zero wavenumber;
- *   - n3 must be even (real-to-complex transforms along the last axis);
- *     every grid size must factor into 2, 3 and 5;
+ *   - every grid size must factor into 2, 3, 5 and 7; odd sizes are
+ *     allowed on every axis (the paper's grids are 63^3);
  *   - real fields are device arrays of doubles, component-major
  *     [c][x][y][z] with z fastest; symmetric tensors have 6 components in
  *     the order 11 22 33 23 13 12 (plain tensor components, no factors),
@@ -96,6 +96,10 @@ typedef struct {
                           from 8 to 256, n2 even): the divergence pass updates the residual, no
                           separate update kernel; 0: separate vector kernels.  Same arithmetic,
                           other summation order; 1 */
+  int32_t graph;       /* 1: a single-cell solve that runs past its first chunk of check_every
+                          iterations captures one chunk as a HIP graph (on a private stream) and
+                          replays it on the context's stream; 0: every chunk launched eagerly.
+                          Same launches, same results; 1 */
 } dbfft_opts;
 
 typedef struct {
@@ -120,8 +124,8 @@ void dbfft_default_opts(dbfft_opts* opts);
  * DBFFT_FP32_MIXED (FP32 transforms and pointwise work, FP64 dot products,
  * residuals and outer corrections); hip_stream: hipStream_t the context
  * enqueues on (NULL = default stream).  The material field is copied.
- * EINVAL on null pointers, non-positive or odd n3, sizes with prime factors
- * other than 2, 3, 5, unknown or mismatched material kind. */
+ * EINVAL on null pointers, non-positive sizes, sizes with prime factors
+ * other than 2, 3, 5, 7, unknown or mismatched material kind. */
 dbfft_status dbfft_setup(dbfft_ctx** out, const int64_t n[3], int32_t kinematics, int32_t precision,
                          int32_t material, const void* field_dev, const double* params, int32_t nparams,
                          void* hip_stream);

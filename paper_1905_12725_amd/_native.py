@@ -46,6 +46,7 @@ class Opts(ct.Structure):
         ("max_refine", ct.c_int32),
         ("check_every", ct.c_int32),
         ("fused_cg", ct.c_int32),
+        ("graph", ct.c_int32),
     ]
 
 

@@ -159,6 +159,17 @@ void launch_line_fast(int kin, const void* in, void* out, const Geom& g, const v
                       const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
                       const int* stop);
 int line_lines_per_block(const Geom& g, int ncomp, int elem_bytes);
+// Length of the complex transform of one z line in the generic z pass: n3/2
+// on packed pairs of real samples when n3 is even, n3 on the real samples
+// (zero imaginary part) when it is odd.
+__host__ __device__ constexpr inline int z_length(int n3) { return (n3 % 2 == 0) ? n3 / 2 : n3; }
+// LDS bytes of a generic z-pass block of L lines: twiddles (z_length),
+// split twiddles (n3/2 + 1), two transform buffers, the half-spectrum
+// staging lines and the real samples of every component.
+inline size_t line_smem_bytes(const Geom& g, int L, int ncomp, int elem_bytes) {
+  const size_t Z = (size_t)z_length(g.n3), M = (size_t)(g.n3 / 2), l = (size_t)L, eb = (size_t)elem_bytes;
+  return (Z + M + 1) * eb + 2 * Z * l * eb + (M + 1) * l * eb + (size_t)ncomp * l * g.n3 * (eb / 2);
+}
 
 // PCG vector kernels (3 half-spectrum components).
 template <typename T>

@@ -54,7 +54,7 @@ static bool make_plan(int n, FftPlan& p) {
   std::memset(&p, 0, sizeof(p));
   p.n = n;
   int m = n, ns = 1;
-  const int radices[5] = {8, 4, 2, 3, 5};
+  const int radices[6] = {8, 4, 2, 3, 5, 7};
   for (int r : radices) {
     while (m % r == 0) {
       if (p.nstages >= kMaxStages) return false;
@@ -190,6 +190,14 @@ struct Ctx {
   double prof_ms[16] = {0};
   long long prof_n[16] = {0};
 
+  // HIP graph of one chunk of PCG iterations, captured on a private stream
+  // and replayed on `st`; `chunk_key` holds the launch arguments it was
+  // captured with (a solve with other arguments captures again)
+  hipStream_t cap_st = nullptr;
+  hipGraph_t chunk_graph = nullptr;
+  hipGraphExec_t chunk_exec = nullptr;
+  std::vector<unsigned char> chunk_key;
+
   // solution state
   bool solved = false;
   int last_mask[9] = {0};
@@ -197,6 +205,7 @@ struct Ctx {
   double e_st[9] = {0};    // macro unknown as a tensor (stored order)
   double sig_rm[9] = {0}, eps_rm[9] = {0};
   bool use_fused = true;  // opts.fused_cg of the current call
+  bool use_graph = true;  // opts.graph of the current call
   bool linear_material() const { return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE; }
 };
 
@@ -613,7 +622,33 @@ static bool fused_cg(const Ctx& c) {
   return c.use_fused && c.kin == KIN_SMALL && fast_strided_supported(c.n[0]) && c.n[1] % 2 == 0;
 }
 
+// Launch arguments of one PCG chunk, byte for byte: a chunk graph captured
+// with an equal key replays exactly the launches the eager loop would make.
+template <typename T>
+static std::vector<unsigned char> chunk_key(const Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa,
+                                            const PcgConst& pc, const void* x, const void* r, const void* p,
+                                            const void* q, int check_every) {
+  std::vector<unsigned char> k;
+  auto put = [&](const void* v, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(v);
+    k.insert(k.end(), b, b + n);
+  };
+  const int head[3] = {(int)sizeof(T), check_every, fused_cg(c) ? 1 : 0};
+  const void* vec[4] = {x, r, p, q};
+  put(head, sizeof(head));
+  put(vec, sizeof(vec));
+  put(&tan, sizeof(tan));
+  put(&pa, sizeof(pa));
+  put(&pc, sizeof(pc));
+  return k;
+}
+
 // Solves K x = b with b in r (precision T); x is overwritten (starts at 0).
+// The iterations are enqueued in chunks of `check_every`, each followed by
+// a read of the device scalars.  The first chunk is launched eagerly; a
+// solve that needs more captures one chunk in a HIP graph (unless kernel
+// timing is on) and replays it, which takes the per-launch host cost out of
+// every later chunk.
 template <typename T>
 static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r,
                       void* p, void* q, const double sig0[9], const double re0[kMaxMacro], int check_every) {
@@ -624,8 +659,10 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
   const int* stop = reinterpret_cast<const int*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, converged));
   if (check_every < 1) check_every = 1;
   const bool fused = fused_cg(c);
-  while (!c.sc_host->converged) {
-    const int iter0 = c.sc_host->iter;
+  // one chunk of iterations on stream s (c.st itself, or the capture stream)
+  auto enqueue_chunk = [&](hipStream_t s) {
+    const hipStream_t st_saved = c.st;
+    c.st = s;
     for (int k = 0; k < check_every; ++k) {
       c.prof_tag = k;
       if (fused) {
@@ -670,6 +707,32 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
     }
     prof_mark(c, PK_END);
     c.prof_tag = -1;
+    c.st = st_saved;
+  };
+  bool first = true;
+  while (!c.sc_host->converged) {
+    const int iter0 = c.sc_host->iter;
+    if (!first && !c.prof_on && c.use_graph) {
+      std::vector<unsigned char> key = chunk_key<T>(c, tan, pa, pc, x, r, p, q, check_every);
+      if (c.chunk_exec == nullptr || key != c.chunk_key) {
+        if (c.chunk_exec) HIPCK(hipGraphExecDestroy(c.chunk_exec));
+        if (c.chunk_graph) HIPCK(hipGraphDestroy(c.chunk_graph));
+        c.chunk_exec = nullptr;
+        c.chunk_graph = nullptr;
+        c.chunk_key.clear();
+        if (c.cap_st == nullptr) HIPCK(hipStreamCreateWithFlags(&c.cap_st, hipStreamNonBlocking));
+        HIPCK(hipStreamBeginCapture(c.cap_st, hipStreamCaptureModeThreadLocal));
+        enqueue_chunk(c.cap_st);
+        HIPCK(hipStreamEndCapture(c.cap_st, &c.chunk_graph));
+        HIPCK(hipGraphInstantiate(&c.chunk_exec, c.chunk_graph, nullptr, nullptr, 0));
+        c.chunk_key.swap(key);
+        if (g_verbose) std::fprintf(stderr, "[dbfft] pcg: captured a graph of %d iterations\n", check_every);
+      }
+      HIPCK(hipGraphLaunch(c.chunk_exec, c.st));
+    } else {
+      enqueue_chunk(c.st);
+    }
+    first = false;
     HIPCK(hipGetLastError());
     HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
     HIPCK(hipStreamSynchronize(c.st));
@@ -699,8 +762,8 @@ static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const
   LinOut out;
   double C4[81];
   mean_tangent(c, C4);
-  PrecondArgs pa;
-  PcgConst pc;
+  PrecondArgs pa{};
+  PcgConst pc{};
   std::memset(&pc, 0, sizeof(pc));
   build_precond(c, C4, ms, pa, pc);
   pc.tol = o.tol;
@@ -1059,7 +1122,7 @@ static int newton_solve(Ctx& c, const double load_rm[9], const int mask[9], int 
 // ------------------------------------------------------------------ setup
 static bool smooth(long long n) {
   if (n < 1) return false;
-  for (int p : {2, 3, 5})
+  for (int p : {2, 3, 5, 7})
     while (n % p == 0) n /= p;
   return n == 1;
 }
@@ -1075,14 +1138,16 @@ static void release(Ctx* c) {
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->red_host) (void)hipHostFree(c->red_host);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
+  if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
+  if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
 }
 
 static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const void* field, const double* params,
                   int nparams, void* stream) {
   if (!n) DB_THROW(DBFFT_EINVAL, "null grid size");
   for (int a = 0; a < 3; ++a)
-    if (n[a] < 1 || n[a] > 4096 || !smooth(n[a])) DB_THROW(DBFFT_EINVAL, "grid sizes must be 2^a 3^b 5^c");
-  if (n[2] % 2 != 0) DB_THROW(DBFFT_EINVAL, "n3 must be even");
+    if (n[a] < 1 || n[a] > 4096 || !smooth(n[a])) DB_THROW(DBFFT_EINVAL, "grid sizes must be 2^a 3^b 5^c 7^d");
   {
     // the x/y passes keep one line (plus twiddles) of every tile column in
     // LDS, the z pass one z line of every component: both within 64 KiB
@@ -1116,7 +1181,7 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
     g.nh = (long long)g.n1 * g.n2 * g.nh3;
     g.nvox = (long long)g.n1 * g.n2 * g.n3;
     g.inv_nvox = 1.0 / (double)g.nvox;
-    if (!make_plan(g.n1, c->p1) || !make_plan(g.n2, c->p2) || !make_plan(g.n3 / 2, c->p3))
+    if (!make_plan(g.n1, c->p1) || !make_plan(g.n2, c->p2) || !make_plan(z_length(g.n3), c->p3))
       DB_THROW(DBFFT_EINVAL, "cannot plan the transform lengths");
     std::vector<double> re, im;
     twiddles(g.n1, g.n1, g.n1, re, im);
@@ -1125,8 +1190,8 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
     twiddles(g.n2, g.n2, g.n2, re, im);
     c->td.tw2 = upload_table<double>(re, im);
     c->tf.tw2 = upload_table<float>(re, im);
-    const int M = g.n3 / 2;
-    twiddles(M, M, std::max(M, 1), re, im);
+    const int M = g.n3 / 2, Z = z_length(g.n3);
+    twiddles(Z, Z, std::max(Z, 1), re, im);
     c->td.tw3 = upload_table<double>(re, im);
     c->tf.tw3 = upload_table<float>(re, im);
     twiddles(g.n3, g.n3, M + 1, re, im);
@@ -1445,8 +1510,7 @@ static void batch_build(Batch& B) {
       lz = std::max(lz, (size_t)(2 * M + 1 + (size_t)(kLineThreads / 64) * lb * (M + tl + 1)) * eb);
     } else {
       bz[r + 1] = bz[r] + (int)((nlines + B.L[r] - 1) / B.L[r]);
-      lz = std::max(lz, (size_t)(2 * M + 1) * eb + (size_t)2 * M * B.L[r] * eb + (size_t)(M + 1) * B.L[r] * eb +
-                            (size_t)c.ncomp * B.L[r] * c.g.n3 * sizeof(T));
+      lz = std::max(lz, line_smem_bytes(c.g, B.L[r], c.ncomp, (int)eb));
     }
     bv[r + 1] = bv[r] + pcg_block_count(c.g);
   }
@@ -1817,6 +1881,7 @@ void dbfft_default_opts(dbfft_opts* o) {
   o->max_refine = 30;
   o->check_every = 8;
   o->fused_cg = 1;
+  o->graph = 1;
 }
 
 const char* dbfft_last_error(void) { return g_err.c_str(); }
@@ -1946,6 +2011,7 @@ dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t str
   if (opts) o = *opts;
   else dbfft_default_opts(&o);
   c.use_fused = o.fused_cg != 0;
+  c.use_graph = o.graph != 0;
   int mask[9];
   for (int i = 0; i < 9; ++i) mask[i] = stress_mask[i] ? 1 : 0;
   if (c.kin == KIN_SMALL) {

@@ -96,6 +96,37 @@ __device__ __forceinline__ void dft5(cpx<T>* v, T d) {
   v[3] = sub(m2, t2);
 }
 
+// 7 points: the six non-zero inputs in conjugate pairs (1,6), (2,5), (3,4);
+// output m gathers sum_k s_k cos(2 pi k m/7) and d i sum_k d_k sin(2 pi k m/7)
+template <typename T>
+__device__ __forceinline__ void dft7(cpx<T>* v, T d) {
+  const T c[3] = {(T)0.62348980185873359439, (T)-0.22252093395631433737, (T)-0.90096886790241903498};
+  const T sn[3] = {(T)0.78183148246802980363, (T)0.97492791218182361934, (T)0.43388373911755823142};
+  const cpx<T> a = v[0];
+  cpx<T> sp[3], dm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    sp[k] = add(v[k + 1], v[6 - k]);
+    dm[k] = sub(v[k + 1], v[6 - k]);
+  }
+  v[0] = add(a, add(sp[0], add(sp[1], sp[2])));
+#pragma unroll
+  for (int m = 1; m <= 3; ++m) {
+    cpx<T> re = a, im = mk<T>(0, 0);
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+      const int j = (k * m) % 7;  // cos and sin of 2 pi j / 7 through the pair index
+      const int q = (j <= 3) ? j : 7 - j;
+      const T sg = (j <= 3) ? (T)1 : (T)-1;
+      re = add(re, scl(sp[k - 1], c[q - 1]));
+      im = add(im, scl(dm[k - 1], sg * sn[q - 1]));
+    }
+    const cpx<T> t = muli(im, d);
+    v[m] = add(re, t);
+    v[7 - m] = sub(re, t);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void dft8(cpx<T>* v, T d) {
   const T r = (T)0.70710678118654752440;
@@ -123,6 +154,7 @@ __device__ __forceinline__ void dftR(cpx<T>* v, T d) {
   else if constexpr (R == 3) dft3(v, d);
   else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3], d);
   else if constexpr (R == 5) dft5(v, d);
+  else if constexpr (R == 7) dft7(v, d);
   else if constexpr (R == 8) dft8(v, d);
 }
 
@@ -170,6 +202,7 @@ __device__ cpx<T>* fft_lds(cpx<T>* A, cpx<T>* B, const cpx<T>* tw, const FftPlan
       case 3: stockham_stage<T, 3>(src, dst, tw, n, S, Ns, d, tid, nthr); break;
       case 4: stockham_stage<T, 4>(src, dst, tw, n, S, Ns, d, tid, nthr); break;
       case 5: stockham_stage<T, 5>(src, dst, tw, n, S, Ns, d, tid, nthr); break;
+      case 7: stockham_stage<T, 7>(src, dst, tw, n, S, Ns, d, tid, nthr); break;
       default: stockham_stage<T, 8>(src, dst, tw, n, S, Ns, d, tid, nthr); break;
     }
     __syncthreads();

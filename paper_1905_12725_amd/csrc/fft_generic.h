@@ -301,12 +301,15 @@ __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const G
                                           int L, int ncomp, long long lineblock, unsigned char* smem_raw) {
   constexpr int NT = kLineThreads;
   const int tid = threadIdx.x;
-  const int n3 = g.n3, M = n3 / 2, nh3 = g.nh3;
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // M
-  cpx<T>* rtw = tw + M;                               // M + 1
-  cpx<T>* FA = rtw + (M + 1);                         // M * L
-  cpx<T>* FB = FA + M * L;                            // M * L
-  cpx<T>* XB = FB + M * L;                            // (M + 1) * L
+  // even n3: complex transforms of length Z = n3/2 on packed sample pairs;
+  // odd n3: complex transforms of length Z = n3 on the samples themselves
+  const int n3 = g.n3, M = n3 / 2, nh3 = g.nh3, Z = z_length(n3);
+  const bool odd = (n3 & 1) != 0;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);  // Z
+  cpx<T>* rtw = tw + Z;                               // M + 1
+  cpx<T>* FA = rtw + (M + 1);                         // Z * L
+  cpx<T>* FB = FA + Z * L;                            // Z * L
+  cpx<T>* XB = FB + Z * L;                            // (M + 1) * L
   T* RB = reinterpret_cast<T*>(XB + (M + 1) * L);     // ncomp * L * n3
   __shared__ double red[NT / 64];
 
@@ -314,7 +317,7 @@ __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const G
   const long long line0 = lineblock * L;
   const int nl = (int)min((long long)L, nlines - line0);
 
-  for (int t = tid; t < M; t += NT) tw[t] = twg[t];
+  for (int t = tid; t < Z; t += NT) tw[t] = twg[t];
   for (int t = tid; t <= M; t += NT) rtw[t] = rtwg[t];
   __syncthreads();
 
@@ -332,22 +335,37 @@ __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const G
         XB[k * L + s] = (s < nl) ? src[(long long)s * nh3 + k] : mk<T>(0, 0);
       }
       __syncthreads();
-      for (int e = tid; e < M * L; e += NT) {
-        const int k = e / L, s = e - k * L;
-        const cpx<T> Xk = XB[k * L + s];
-        const cpx<T> Xm = conj(XB[(M - k) * L + s]);
-        const cpx<T> E = add(Xk, Xm);
-        const cpx<T> O = mul(sub(Xk, Xm), conj(rtw[k]));
-        FA[k * L + s] = add(E, muli(O, (T)1));
+      if (odd) {
+        // full spectrum from the half spectrum: X(n3 - k) = conj X(k)
+        for (int e = tid; e < Z * L; e += NT) {
+          const int k = e / L, s = e - k * L;
+          FA[k * L + s] = (k < nh3) ? XB[k * L + s] : conj(XB[(n3 - k) * L + s]);
+        }
+      } else {
+        for (int e = tid; e < M * L; e += NT) {
+          const int k = e / L, s = e - k * L;
+          const cpx<T> Xk = XB[k * L + s];
+          const cpx<T> Xm = conj(XB[(M - k) * L + s]);
+          const cpx<T> E = add(Xk, Xm);
+          const cpx<T> O = mul(sub(Xk, Xm), conj(rtw[k]));
+          FA[k * L + s] = add(E, muli(O, (T)1));
+        }
       }
       __syncthreads();
       cpx<T>* res = fft_lds<T>(FA, FB, tw, plan, L, (T)1, tid, NT);
       T* rb = RB + (long long)c * L * n3;
-      for (int e = tid; e < M * L; e += NT) {
-        const int nn = e / L, s = e - nn * L;
-        const cpx<T> z = res[nn * L + s];
-        rb[s * n3 + 2 * nn] = z.x;
-        rb[s * n3 + 2 * nn + 1] = z.y;
+      if (odd) {
+        for (int e = tid; e < Z * L; e += NT) {
+          const int nn = e / L, s = e - nn * L;
+          rb[s * n3 + nn] = res[nn * L + s].x;
+        }
+      } else {
+        for (int e = tid; e < M * L; e += NT) {
+          const int nn = e / L, s = e - nn * L;
+          const cpx<T> z = res[nn * L + s];
+          rb[s * n3 + 2 * nn] = z.x;
+          rb[s * n3 + 2 * nn + 1] = z.y;
+        }
       }
       __syncthreads();
     }
@@ -422,13 +440,28 @@ __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const G
     const T scale = (T)g.inv_nvox;
     for (int c = 0; c < ncomp; ++c) {
       const T* rb = RB + (long long)c * L * n3;
-      for (int e = tid; e < M * L; e += NT) {
-        const int nn = e / L, s = e - nn * L;
-        FA[nn * L + s] = mk<T>(rb[s * n3 + 2 * nn], rb[s * n3 + 2 * nn + 1]);
+      if (odd) {
+        for (int e = tid; e < Z * L; e += NT) {
+          const int nn = e / L, s = e - nn * L;
+          FA[nn * L + s] = mk<T>(rb[s * n3 + nn], (T)0);
+        }
+      } else {
+        for (int e = tid; e < M * L; e += NT) {
+          const int nn = e / L, s = e - nn * L;
+          FA[nn * L + s] = mk<T>(rb[s * n3 + 2 * nn], rb[s * n3 + 2 * nn + 1]);
+        }
       }
       __syncthreads();
       cpx<T>* res = fft_lds<T>(FA, FB, tw, plan, L, (T)-1, tid, NT);
       cpx<T>* dst = outc + c * g.nh + line0 * nh3;
+      if (odd) {
+        for (int e = tid; e < nh3 * L; e += NT) {
+          const int s = e / nh3, k = e - s * nh3;
+          if (s < nl) dst[(long long)s * nh3 + k] = scl(res[k * L + s], scale);
+        }
+        __syncthreads();
+        continue;
+      }
       for (int e = tid; e < nh3 * L; e += NT) {
         const int s = e / nh3, k = e - s * nh3;
         if (s >= nl) continue;

@@ -84,9 +84,10 @@ template void launch_strided<float>(int, const void*, void*, int, const StridedG
                                     const void*, int, double*, hipStream_t, const int*);
 
 // ------------------------------------------------------------------ z pass
-// Block = L consecutive (x, y) lines.  A real transform of length n3 is done
-// as a complex transform of length n3/2 on z[n] = f[2n] + i f[2n+1] with the
-// standard even/odd split before (C2R) or after (R2C).
+// Block = L consecutive (x, y) lines.  A real transform of even length n3 is
+// done as a complex transform of length n3/2 on z[n] = f[2n] + i f[2n+1] with
+// the standard even/odd split before (C2R) or after (R2C); an odd n3 takes
+// the full-length complex transform of the real samples.
 template <typename T, int MODE, int KIN>
 __global__ __launch_bounds__(kLineThreads) void k_line(const void* in_v, void* out_v, Geom g, FftPlan plan,
                                                        const cpx<T>* __restrict__ twg,
@@ -106,12 +107,7 @@ int line_lines_per_block(const Geom& g, int ncomp, int elem_bytes) {
   int L = 512 / g.n3;
   if (L < 1) L = 1;
   if (L > 16) L = 16;
-  const int M = g.n3 / 2;
-  auto bytes = [&](int l) {
-    return (size_t)(2 * M + 1) * elem_bytes + (size_t)2 * M * l * elem_bytes + (size_t)(M + 1) * l * elem_bytes +
-           (size_t)ncomp * l * g.n3 * (elem_bytes / 2);
-  };
-  while (L > 1 && bytes(L) > 64 * 1024) --L;
+  while (L > 1 && line_smem_bytes(g, L, ncomp, elem_bytes) > 64 * 1024) --L;
   return L;
 }
 
@@ -136,9 +132,7 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
   const long long nlines = (long long)g.n1 * g.n2;
   const int nblk = (int)((nlines + L - 1) / L);
   if (nblocks_out) *nblocks_out = nblk;
-  const int M = g.n3 / 2;
-  const size_t shm = (size_t)(2 * M + 1) * eb + (size_t)2 * M * L * eb + (size_t)(M + 1) * L * eb +
-                     (size_t)ncomp * L * g.n3 * sizeof(T);
+  const size_t shm = line_smem_bytes(g, L, ncomp, eb);
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
 #define DBFFT_LINE(MD, KN)                                                                                       \

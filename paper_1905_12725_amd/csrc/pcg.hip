@@ -86,9 +86,9 @@ template void launch_pcg_xp<float>(void*, void*, const void*, const PcgScalars*,
                                    hipStream_t);
 
 int fused_cg_partials(const Geom& g) {
-  // divergence tiles (at least 8 columns each): all (k2, k3) pairs, padding,
+  // divergence tiles (at least 2 columns each): all (k2, k3) pairs, padding,
   // then the two plane columns again; two sums each
-  return 2 * (int)(((long long)g.n2 * (g.nh3 + 2) + 7) / 8 + 2);
+  return 2 * (int)(((long long)g.n2 * (g.nh3 + 2) + 1) / 2 + 2);
 }
 
 template <typename T>

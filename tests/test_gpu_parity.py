@@ -292,3 +292,32 @@ def test_fused_cg_matches_separate_kernels(gpu, n, prec):
     assert rel(out[1][1], out[0][1]) < (1e-9 if prec == "fp64" else 1e-5)
     if prec == "fp64":
         assert abs(out[1][0]["pcg_iters"] - out[0][0]["pcg_iters"]) <= 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("n", [(32, 32, 32), (24, 20, 30)])
+def test_chunk_graph_matches_eager(gpu, n, prec):
+    """Single-cell solves whose later chunks of iterations replay a captured
+    HIP graph (default) against every chunk launched eagerly: the same
+    launches, so bit-identical solutions and equal iteration counts; two
+    solves in a row with different loads reuse or recapture the graph."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case chunk graph vs eager n={n} {prec}", flush=True)
+    phase, _, _ = ms.random_spheres(n, 11, 2.0, 5.0, 0.25)
+    E = [1.0, 50.0]
+    mask = np.zeros((3, 3), bool)
+    mask[2, 2] = True
+    loads = [np.diag([1e-3, 0.0, 0.0]), np.array([[0, 2e-3, 0], [2e-3, 0, 0], [0, 0, 1e-2]])]
+    out = {}
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3), precision=prec) as cell:
+        for graph in (1, 0):
+            res = []
+            for L in loads:
+                info = cell.solve(L, mask, tol=1e-10, tol_load=1e-10, graph=graph, check_every=4)
+                res.append((info["pcg_iters"], info["refine_steps"], cell.solution()[0].cpu().numpy()))
+            out[graph] = res
+    for (i1, r1, a1), (i0, r0, a0) in zip(out[1], out[0]):
+        assert i1 == i0 and r1 == r0
+        assert np.array_equal(a1, a0)
+        assert i1 > 8
