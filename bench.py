@@ -11,13 +11,15 @@ the final residual check), inputs resident in HBM.
 
 Prints one JSON line.  `value` is operator applications per second over
 the timed steps in FP64 (every CG iteration applies the operator once).
-Also reported: voxel-DOFs per second, per-kernel HIP-event durations and
+Also reported: voxel-DOFs per second, per-kernel durations from HIP events
+the launches record at each kernel's start and end over the timed region,
 the roofline of the dominant kernel, the FP32-mixed (FP32 transforms and
 pointwise work, FP64 dots and outer corrections) solve time against FP64
 at equal homogenized-stress accuracy, and the CPU oracle timed on a
 bounded sample of the same workload.  A second workload (32 neo-Hookean
 cells of uneven grid sizes, 10 load increments) compares the batched
-FP32-mixed solve with sequential FP64 solves.
+FP32-mixed solve with sequential FP64 solves; a third sweeps the phase
+contrast of a sphere inclusion at 63^3 and 64^3 (iterations per case).
 """
 from __future__ import annotations
 
@@ -40,10 +42,10 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 is recorded here and are reported as null once those change.
 TRAFFIC_SOURCES = ("paper_1905_12725_amd/csrc/fft_fast.hip", "paper_1905_12725_amd/csrc/fft_common.h",
                    "paper_1905_12725_amd/csrc/pcg_core.h", "paper_1905_12725_amd/csrc/pcg.hip")
-TRAFFIC_SHA256 = "14c150c9eb364377e4b04e36c9cc96f7a2243f6d059a49b014451ab66ba3639a"
-TRAFFIC_128_FP64 = {"x_inverse_grad": 149478896, "y_inverse": 201895042, "y_forward": 201895042,
-                    "z_fused_tangent": 206329805, "x_forward_div": 221383903, "cg_beta": 27436,
-                    "cg_direction": 247967861}
+TRAFFIC_SHA256 = "7d2712ced1090aaf46ec885d5c128bc730b65fd062ed4aecccd4a00a08de7b65"
+TRAFFIC_128_FP64 = {"x_inverse_grad": 149478871, "y_inverse": 201644988, "y_forward": 201644988,
+                    "z_fused_tangent": 207370239, "x_forward_div": 221393702, "cg_beta": 27436,
+                    "cg_direction": 247967856}
 
 
 def measured_traffic(n, kind):
@@ -389,11 +391,12 @@ def main():
         "gvoxel_dof_per_s": 3.0 * N * applies_per_s / 1e9,
         "hbm_model": {
             "apply_bytes": apply_bytes,
-            "apply_us_events": apply_us,
+            "apply_us_kernels": apply_us,
             "apply_frac_of_peak": apply_bytes / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
             "iteration_bytes": iter_bytes,
-            "iteration_us_events": iter_us,
+            "iteration_us_kernels": iter_us,
             "iteration_frac_of_peak": iter_bytes / (iter_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "iteration_us_wall": 1e6 / applies_per_s,
             "whole_job_frac_of_peak": iter_bytes * applies_per_s / 1e9 / HBM_PEAK_GBS,
         },
         "kernels": per_kernel,

@@ -183,9 +183,13 @@ dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]);
  * J_out (host, may be NULL) receives J. */
 dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out);
 
-/* Per-kernel timing of PCG iterations with HIP events recorded on the
- * context's stream around every kernel of every iteration (only iterations
- * that ran to completion are counted).  Slot k of ms_total / launches
+/* Per-kernel timing of PCG iterations with HIP events (only iterations
+ * that ran to completion are counted).  A step that is one kernel launch
+ * is timed by events the launch itself records at the kernel's start and
+ * end (its execution time, as a kernel trace reports it); a step of several
+ * launches by events recorded on the context's stream around it.  One
+ * iteration per chunk of check_every is timed (the middle one).  Timing
+ * launches eagerly (no chunk graph).  Slot k of ms_total / launches
  * (host arrays of 16, either may be NULL) receives the accumulated
  * milliseconds and launch count of kernel kind k:
  *   0 x pass inverse + gradient      1 y pass inverse

@@ -8,9 +8,35 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 
 namespace dbfft {
+
+// Per-kernel timing: when the engine times a PCG kernel it leaves a pair of
+// events here before the launch; DB_LAUNCH then launches through
+// hipExtLaunchKernelGGL, which records them at the kernel's own start and
+// end (the kernel's execution time, without the gap to the previous
+// kernel), and counts the launches so the engine knows whether the pair
+// covered the only kernel of the timed step.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int consumed = 0;
+  long long launches = 0;
+};
+extern thread_local LaunchTiming g_launch_timing;
+#define DB_LAUNCH(K, GRID, BLOCK, SHM, ST, ...)                                                            \
+  do {                                                                                                    \
+    ::dbfft::LaunchTiming& lt_ = ::dbfft::g_launch_timing;                                                \
+    if (lt_.start != nullptr) {                                                                           \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, SHM, ST, lt_.start, lt_.stop, 0u, __VA_ARGS__);               \
+      lt_.start = lt_.stop = nullptr;                                                                     \
+      lt_.consumed = 1;                                                                                   \
+    } else {                                                                                              \
+      hipLaunchKernelGGL(K, GRID, BLOCK, SHM, ST, __VA_ARGS__);                                           \
+    }                                                                                                     \
+    ++lt_.launches;                                                                                       \
+  } while (0)
 
 constexpr int kMaxStages = 12;
 constexpr int kMaxPhases = 8;

@@ -185,8 +185,8 @@ struct Ctx {
   // optional per-kernel timing of PCG iterations with HIP events
   int prof_on = 0;
   int prof_tag = -1;  // iteration index within the enqueued chunk, -1 = not timed
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_kind, ev_iter;
+  std::vector<hipEvent_t> ev_pool, ext_pool;
+  std::vector<int> ev_kind, ev_iter, ev_ext;
   double prof_ms[16] = {0};
   long long prof_n[16] = {0};
 
@@ -213,18 +213,36 @@ enum ProfKind {
   PK_XINV = 0, PK_YINV, PK_ZFUSED, PK_YFWD, PK_XFWD, PK_ALPHA, PK_UPDATE, PK_BETA, PK_PUPDATE, PK_END
 };
 
-// records an event that marks the start of a kernel of `kind` (PK_END closes)
-static void prof_mark(Ctx& c, int kind) {
-  if (!c.prof_on || c.prof_tag < 0) return;
-  const size_t i = c.ev_kind.size();
-  if (i >= c.ev_pool.size()) {
+thread_local LaunchTiming g_launch_timing;
+
+static hipEvent_t pool_event(std::vector<hipEvent_t>& pool, size_t i) {
+  while (pool.size() <= i) {
     hipEvent_t e;
     HIPCK(hipEventCreate(&e));
-    c.ev_pool.push_back(e);
+    pool.push_back(e);
   }
-  HIPCK(hipEventRecord(c.ev_pool[i], c.st));
+  return pool[i];
+}
+
+// Marks the start of the kernel of `kind` (PK_END closes the last one): an
+// event recorded on the stream brackets the step, and a second pair is left
+// for DB_LAUNCH, which records it at the kernel's own start and end.  The
+// pair is used when it covered the step's only launch; otherwise the
+// bracket (which also holds the gap to the previous kernel) is.
+static void prof_mark(Ctx& c, int kind) {
+  if (!c.prof_on || c.prof_tag < 0) return;
+  LaunchTiming& lt = g_launch_timing;
+  if (!c.ev_kind.empty()) c.ev_ext.back() = (lt.consumed && lt.launches == 1) ? 1 : 0;
+  lt = LaunchTiming{};
+  const size_t i = c.ev_kind.size();
+  HIPCK(hipEventRecord(pool_event(c.ev_pool, i), c.st));
   c.ev_kind.push_back(kind);
   c.ev_iter.push_back(c.prof_tag);
+  c.ev_ext.push_back(0);
+  if (kind < PK_END) {
+    lt.start = pool_event(c.ext_pool, 2 * i);
+    lt.stop = pool_event(c.ext_pool, 2 * i + 1);
+  }
 }
 
 // after a stream sync: attribute elapsed times of the first `executed`
@@ -235,12 +253,15 @@ static void prof_collect(Ctx& c, int executed) {
     const int k = c.ev_kind[i];
     if (k < 0 || k >= PK_END || c.ev_iter[i] >= executed) continue;
     float ms = 0.f;
-    HIPCK(hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));
+    if (c.ev_ext[i]) HIPCK(hipEventElapsedTime(&ms, c.ext_pool[2 * i], c.ext_pool[2 * i + 1]));
+    else HIPCK(hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));
     c.prof_ms[k] += ms;
     c.prof_n[k] += 1;
   }
   c.ev_kind.clear();
   c.ev_iter.clear();
+  c.ev_ext.clear();
+  g_launch_timing = LaunchTiming{};
 }
 
 static void* dalloc(size_t bytes) {
@@ -660,11 +681,19 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
   if (check_every < 1) check_every = 1;
   const bool fused = fused_cg(c);
   // one chunk of iterations on stream s (c.st itself, or the capture stream)
+  // Kernel timing samples the middle iteration of every chunk (the events
+  // a launch records cost the stream a few microseconds each; the kernels of
+  // every iteration are the same work).
+  const int sample = check_every / 2;
   auto enqueue_chunk = [&](hipStream_t s) {
     const hipStream_t st_saved = c.st;
     c.st = s;
     for (int k = 0; k < check_every; ++k) {
-      c.prof_tag = k;
+      if (k == sample + 1) {
+        c.prof_tag = sample;
+        prof_mark(c, PK_END);
+      }
+      c.prof_tag = (k == sample) ? k : -1;
       if (fused) {
         // gradient | y | z (+ <p, K p> partials) | y (its first block: alpha)
         // | divergence with r -= alpha q and the Hermitian planes | beta (+
@@ -705,7 +734,10 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
       prof_mark(c, PK_PUPDATE);
       launch_pcg_pupdate<T>(p, r, c.sc_dev, pa, c.g, nb, c.st);
     }
-    prof_mark(c, PK_END);
+    if (sample == check_every - 1) {
+      c.prof_tag = sample;
+      prof_mark(c, PK_END);
+    }
     c.prof_tag = -1;
     c.st = st_saved;
   };
@@ -1138,6 +1170,7 @@ static void release(Ctx* c) {
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   if (c->red_host) (void)hipHostFree(c->red_host);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ext_pool) (void)hipEventDestroy(e);
   if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
   if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
   if (c->cap_st) (void)hipStreamDestroy(c->cap_st);

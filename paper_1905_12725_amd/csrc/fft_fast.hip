@@ -488,6 +488,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
   for (int q = 0; q < E; ++q) a0[q] = a1[q] = a2[q] = mk<T>(0, 0);
   cpx<T> nx[E];
   loadv(in, nx);
+  const long long cs = sg.cstride_out;
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
     cpx<T> v[E];
@@ -518,15 +519,16 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
   }
   const double alpha = sc->alpha;
   // r -= alpha q with q = -i a, rounded to the storage precision
-  const long long cs = sg.cstride_out;
   cpx<T> rn[3][E];
 #pragma unroll
   for (int gq = 0; gq < E; ++gq) {
     const long long off = base + (long long)(t + TL * fast_out_pos<N, E>(gq)) * ls;
     const cpx<T> qv[3] = {muli(a0[gq], (T)-1), muli(a1[gq], (T)-1), muli(a2[gq], (T)-1)};
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      rn[c][gq] = valid ? down<T>(sub(up(r[off + c * cs]), scl(up(qv[c]), alpha))) : mk<T>(0, 0);
+    for (int c = 0; c < 3; ++c) {
+      const cpx<T> rv0 = valid ? r[off + c * cs] : mk<T>(0, 0);
+      rn[c][gq] = valid ? down<T>(sub(up(rv0), scl(up(qv[c]), alpha))) : mk<T>(0, 0);
+    }
   }
   if (plane_tile) {
     // Hermitian projection: element (k1, line) pairs with (-k1, partner line)
@@ -583,7 +585,7 @@ static int launch_div_update_n(const void* W, void* r, const StridedGeom& sg, co
   using S = StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>;
   const long long npair = div_plane_pad<S::TZ>(sg.nother) + (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
-  hipLaunchKernelGGL((k_div_update_fast<T, N>), dim3(ntiles), dim3(S::NT), 0, st, static_cast<const cpx<T>*>(W),
+  DB_LAUNCH((k_div_update_fast<T, N>), dim3(ntiles), dim3(S::NT), 0, st, static_cast<const cpx<T>*>(W),
                      static_cast<cpx<T>*>(r), sg, g, static_cast<const cpx<T>*>(tw), sc, pa, dc_out, partials);
   return ntiles;
 }
@@ -616,7 +618,7 @@ static void launch_fast_nm(const void* in, void* out, int ncomp_plain, const Str
   const long long npair = (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
   dim3 grid(ntiles, 1, MODE == SP_PLAIN ? ncomp_plain : 1);
-  hipLaunchKernelGGL((k_strided_fast<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
+  DB_LAUNCH((k_strided_fast<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
                      static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop, alpha_sc,
                      eparts, neparts);
 }
@@ -679,6 +681,38 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
   return mk<T>(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
+// Value of lane (TL - t) mod TL of the same line (lines of TL = 8 or 16
+// lanes sit in DPP rows): row mirror (half-row mirror for 8) then row shift
+// right by one; lane t = 0 of a line gets a value it does not use.
+template <int TL>
+__device__ __forceinline__ int partner_b32(int v, int partner) {
+  if constexpr (TL == 16) {
+    const int m = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, m, 0x111, 0xF, 0xF, false);
+  } else if constexpr (TL == 8) {
+    const int m = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, m, 0x111, 0xF, 0xF, false);
+  } else {
+    return __shfl(v, partner, 64);
+  }
+}
+template <int TL>
+__device__ __forceinline__ double partner_f64(double x, int partner) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = partner_b32<TL>((int)b, partner);
+  const int hi = partner_b32<TL>((int)(b >> 32), partner);
+  return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int TL, typename T>
+__device__ __forceinline__ cpx<T> shfl_partner(cpx<T> v, int partner) {
+  if constexpr (sizeof(T) == 8) {
+    return mk<T>(partner_f64<TL>(v.x, partner), partner_f64<TL>(v.y, partner));
+  } else {
+    return mk<T>(__builtin_bit_cast(float, partner_b32<TL>(__builtin_bit_cast(int, v.x), partner)),
+                 __builtin_bit_cast(float, partner_b32<TL>(__builtin_bit_cast(int, v.y), partner)));
+  }
+}
+
 // Exchange padding of the z pass: one slot per 256 bytes of a line.
 template <typename T>
 constexpr int line_pad() {
@@ -715,7 +749,7 @@ __device__ __forceinline__ void line_inverse(const cpx<T>* src, bool valid, int 
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     // X[M - k] for k = t + TL r: lane (TL - t), register 7 - r; for t = 0 own register 8 - r (XN when r = 0)
-    const cpx<T> sh = shfl_c(X[E - 1 - r], partner);
+    const cpx<T> sh = shfl_partner<M / E>(X[E - 1 - r], partner);
     const cpx<T> own = (r == 0) ? XN : X[(E - r) & (E - 1)];
     const cpx<T> Xm = conj((t == 0) ? own : sh);
     const cpx<T> Ev = add(X[r], Xm);
@@ -742,7 +776,7 @@ __device__ __forceinline__ void line_forward(cpx<T>* dst, bool valid, int t, int
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + TL * m;
-    const cpx<T> sh = shfl_c(Zp[E - 1 - m], partner);
+    const cpx<T> sh = shfl_partner<M / E>(Zp[E - 1 - m], partner);
     const cpx<T> own = Zp[(E - m) & (E - 1)];
     const cpx<T> Zm = conj((t == 0) ? own : sh);
     const cpx<T> Ev = scl(add(Zp[m], Zm), (T)0.5);
@@ -970,13 +1004,13 @@ static void launch_line_fast_m(int kin, const void* in, void* out, const Geom& g
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
   if (kin == KIN_SMALL && (tan.kind == TAN_ISO_PHASE || tan.kind == TAN_ISO_FIELD))
-    hipLaunchKernelGGL((k_line_fast<T, M, KIN_SMALL, 1>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_fast<T, M, KIN_SMALL, 1>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else if (kin == KIN_SMALL)
-    hipLaunchKernelGGL((k_line_fast<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_fast<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else
-    hipLaunchKernelGGL((k_line_fast<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_fast<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
 }
 

@@ -35,7 +35,7 @@ static void launch_mixed_nm(const void* in, void* out, int ncomp_plain, const St
   const long long npair = (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
   dim3 grid(ntiles, 1, MODE == SP_PLAIN ? ncomp_plain : 1);
-  hipLaunchKernelGGL((k_strided_mixed<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
+  DB_LAUNCH((k_strided_mixed<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
                      static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop);
 }
 
@@ -112,14 +112,14 @@ static void launch_line_mixed_m(int kin, bool iso, const void* in, void* out, co
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
   if (iso)
-    hipLaunchKernelGGL((k_line_mixed<T, M, KIN_SMALL, 1>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 1>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else if constexpr (sizeof(T) == 4) {
     if (kin == KIN_SMALL)
-      hipLaunchKernelGGL((k_line_mixed<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+      DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                          partials, stop);
     else
-      hipLaunchKernelGGL((k_line_mixed<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan,
+      DB_LAUNCH((k_line_mixed<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan,
                          macro_dev, partials, stop);
   }
 }

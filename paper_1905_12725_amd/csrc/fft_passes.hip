@@ -61,19 +61,19 @@ void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const 
   auto t = static_cast<const cpx<T>*>(tw);
   switch (mode) {
     case SP_PLAIN:
-      hipLaunchKernelGGL((k_strided<T, SP_PLAIN>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_PLAIN>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
       break;
     case SP_GRAD_SMALL:
-      hipLaunchKernelGGL((k_strided<T, SP_GRAD_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_GRAD_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
       break;
     case SP_GRAD_FINITE:
-      hipLaunchKernelGGL((k_strided<T, SP_GRAD_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_GRAD_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
       break;
     case SP_DIV_SMALL:
-      hipLaunchKernelGGL((k_strided<T, SP_DIV_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_DIV_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
       break;
     default:
-      hipLaunchKernelGGL((k_strided<T, SP_DIV_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_DIV_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
       break;
   }
 }
@@ -136,7 +136,7 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
 #define DBFFT_LINE(MD, KN)                                                                                       \
-  hipLaunchKernelGGL((k_line<T, MD, KN>), dim3(nblk), dim3(kLineThreads), shm, st, in, out, g, plan, t, r, tan, \
+  DB_LAUNCH((k_line<T, MD, KN>), dim3(nblk), dim3(kLineThreads), shm, st, in, out, g, plan, t, r, tan, \
                      macro_dev, macro_add, partials, L, ncomp, stop)
   if (kin == KIN_SMALL) {
     switch (mode) {

@@ -68,16 +68,16 @@ __global__ __launch_bounds__(kVecThreads) void k_xp(cpx<T>* __restrict__ x, cpx<
 }
 
 void launch_pcg_alpha_only(PcgScalars* sc, const double* partials, int nparts, hipStream_t st) {
-  hipLaunchKernelGGL(k_alpha_only, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts);
+  DB_LAUNCH(k_alpha_only, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts);
 }
 void launch_pcg_beta_step(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_beta_step, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
+  DB_LAUNCH(k_beta_step, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
 }
 template <typename T>
 void launch_pcg_xp(void* x, void* p, const void* r, const PcgScalars* sc, const PrecondArgs& pa, const Geom& g,
                    int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_xp<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(x),
+  DB_LAUNCH((k_xp<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(x),
                      static_cast<cpx<T>*>(p), static_cast<const cpx<T>*>(r), sc, pa, g);
 }
 template void launch_pcg_xp<double>(void*, void*, const void*, const PcgScalars*, const PrecondArgs&, const Geom&, int,
@@ -94,29 +94,29 @@ int fused_cg_partials(const Geom& g) {
 template <typename T>
 void launch_pcg_update(void* x, void* r, const void* p, const void* q, const PcgScalars* sc, const PrecondArgs& pa,
                        const Geom& g, double* partials, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_update<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(x),
+  DB_LAUNCH((k_update<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(x),
                      static_cast<cpx<T>*>(r), static_cast<const cpx<T>*>(p), static_cast<const cpx<T>*>(q), sc, pa, g,
                      partials);
 }
 template <typename T>
 void launch_pcg_pupdate(void* p, const void* r, const PcgScalars* sc, const PrecondArgs& pa, const Geom& g,
                         int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_pupdate<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(p),
+  DB_LAUNCH((k_pupdate<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(p),
                      static_cast<const cpx<T>*>(r), sc, pa, g);
 }
 template <typename T>
 void launch_precond_init(void* p, void* r, const PrecondArgs& pa, const Geom& g, double* partials, int nblocks,
                          hipStream_t st) {
-  hipLaunchKernelGGL((k_pinit<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(p),
+  DB_LAUNCH((k_pinit<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(p),
                      static_cast<cpx<T>*>(r), pa, g, partials);
 }
 void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
+  DB_LAUNCH(k_alpha, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
 }
 void launch_pcg_beta(PcgScalars* sc, const double* partials, int nparts, const PcgConst& pc, int first,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_beta, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, pc, first);
+  DB_LAUNCH(k_beta, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, pc, first);
 }
 
 template void launch_pcg_update<double>(void*, void*, const void*, const void*, const PcgScalars*,
@@ -143,7 +143,7 @@ void launch_axpby(void* y, const void* x, double a, double b, long long n, hipSt
   long long nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_axpby<T>), dim3((int)nb), dim3(256), 0, st, static_cast<T*>(y), static_cast<const T*>(x), a, b, n);
+  DB_LAUNCH((k_axpby<T>), dim3((int)nb), dim3(256), 0, st, static_cast<T*>(y), static_cast<const T*>(x), a, b, n);
 }
 template void launch_axpby<double>(void*, const void*, double, double, long long, hipStream_t);
 template void launch_axpby<float>(void*, const void*, double, double, long long, hipStream_t);
@@ -158,7 +158,7 @@ void launch_convert(void* out, const void* in, long long n, hipStream_t st) {
   long long nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3((int)nb), dim3(256), 0, st, static_cast<Tout*>(out),
+  DB_LAUNCH((k_convert<Tin, Tout>), dim3((int)nb), dim3(256), 0, st, static_cast<Tout*>(out),
                      static_cast<const Tin*>(in), n);
 }
 template void launch_convert<double, float>(void*, const void*, long long, hipStream_t);
@@ -189,10 +189,10 @@ __global__ __launch_bounds__(kVecThreads) void k_dotw(const cpx<T>* __restrict__
 void launch_dot_w(const void* u, const void* v, int isf32, const Geom& g, double* partials, int nblocks,
                   hipStream_t st) {
   if (isf32)
-    hipLaunchKernelGGL((k_dotw<float>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<const cpx<float>*>(u),
+    DB_LAUNCH((k_dotw<float>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<const cpx<float>*>(u),
                        static_cast<const cpx<float>*>(v), g, partials);
   else
-    hipLaunchKernelGGL((k_dotw<double>), dim3(nblocks), dim3(kVecThreads), 0, st,
+    DB_LAUNCH((k_dotw<double>), dim3(nblocks), dim3(kVecThreads), 0, st,
                        static_cast<const cpx<double>*>(u), static_cast<const cpx<double>*>(v), g, partials);
 }
 
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kVecThreads) void k_reduce(const double* __restrict
   }
 }
 void launch_reduce(const double* partials, int nparts, int nvals, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kVecThreads), 0, st, partials, nparts, nvals, out);
+  DB_LAUNCH(k_reduce, dim3(1), dim3(kVecThreads), 0, st, partials, nparts, nvals, out);
 }
 
 }  // namespace dbfft
