@@ -19,7 +19,9 @@ at equal homogenized-stress accuracy, and the CPU oracle timed on a
 bounded sample of the same workload.  A second workload (32 neo-Hookean
 cells of uneven grid sizes, 10 load increments) compares the batched
 FP32-mixed solve with sequential FP64 solves; a third sweeps the phase
-contrast of a sphere inclusion at 63^3 and 64^3 (iterations per case).
+contrast of a sphere inclusion at 63^3 and 64^3 (iterations per case); a
+fourth stretches a porous Saint Venant-Kirchhoff cell to twice its length
+(63^3, 5 increments) under both preconditioner-refresh policies.
 """
 from __future__ import annotations
 
@@ -239,6 +241,48 @@ def batched_leg(log, ncell=32, ninc=10, seed=4, only_batched=False):
     }
 
 
+def svk_porous_leg(log, n=(63, 63, 63), seed=6, ninc=5):
+    """Sec. 3.3 workload: Saint Venant-Kirchhoff matrix (E = 70, nu = 0.3)
+    with 5 random non-overlapping spherical pores at 20 % porosity (equal
+    radii, seeded), the pores modelled as SVK inclusions 100 times softer;
+    uniaxial elongation F = diag(2, 1, 1) (the other directions held) in 5
+    increments, Newton tolerance 1e-6, PCG 1e-8 / 1e-10, FP64.  Both
+    preconditioner policies: the mean tangent refreshed at every increment,
+    and the initial tangent only (the paper's choice).  Per-increment
+    counts come from solves to the first k increments (k = 1..5), which
+    repeat the same increments."""
+    import torch
+    from paper_1905_12725_amd import microstructure as ms
+    from paper_1905_12725_amd.api import Cell
+
+    r = n[0] * (0.2 * 3.0 / (4.0 * np.pi * 5.0)) ** (1.0 / 3.0)
+    phase, _, radii = ms.random_spheres(n, seed, r, r, 0.2)
+    Fbar = np.diag([2.0, 1.0, 1.0])
+    out = {"workload": f"{n[0]}^3 SVK matrix E = 70, nu = 0.3, {len(radii)} spherical pores (radius {r:.2f} "
+                       f"voxels, seed {seed}) 100x softer, porosity {float(phase.mean()):.4f}; F = diag(2, 1, 1) "
+                       f"in {ninc} increments; Newton tol 1e-6, PCG tol 1e-8 / 1e-10, FP64"}
+    for name, refresh in (("refresh_every_increment", 0), ("initial_tangent", 1)):
+        cum_pcg, cum_newton, times = [], [], []
+        with Cell(n, "svk", torch.from_numpy(phase), [70.0, 0.3, 0.7, 0.3], kinematics="finite") as cell:
+            for k in range(1, ninc + 1):
+                Fk = np.eye(3) + (Fbar - np.eye(3)) * k / ninc
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                info = cell.solve(Fk, None, n_increments=k, tol=1e-8, tol_load=1e-10, newton_tol=1e-6,
+                                  refresh=refresh)
+                times.append(time.perf_counter() - t)
+                cum_pcg.append(int(info["pcg_iters"]))
+                cum_newton.append(int(info["newton_iters"]))
+        res = {"pcg_iters_per_increment": [cum_pcg[0]] + [b - a for a, b in zip(cum_pcg, cum_pcg[1:])],
+               "newton_iters_per_increment": [cum_newton[0]] + [b - a for a, b in zip(cum_newton, cum_newton[1:])],
+               "pcg_iters_total": cum_pcg[-1], "newton_iters_total": cum_newton[-1], "solve_s": times[-1],
+               "P11_final": float(info["sigma_bar"][0, 0])}
+        out[name] = res
+        log(f"[bench] SVK porous {name}: PCG per increment {res['pcg_iters_per_increment']}, "
+            f"Newton {res['newton_iters_per_increment']}, {times[-1]:.2f} s")
+    return out
+
+
 def contrast_sweep(log, grids=((63, 63, 63), (64, 64, 64))):
     """Iterations against phase contrast (Sec. 3.1 strain control, Sec. 3.2
     stress control): centred sphere inclusion at 20 %, matrix E = 70,
@@ -288,6 +332,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the phase-contrast sweep")
+    ap.add_argument("--no-svk", action="store_true", help="skip the porous SVK finite-strain workload")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched FP32-mixed solve of the uneven neo-Hookean batch (for profiling)")
     ap.add_argument("--unfused", action="store_true", help="separate CG vector kernels (fused_cg = 0)")
@@ -453,6 +498,8 @@ def main():
         out["batched"] = batched_leg(log)
     if not args.no_sweep:
         out["contrast_sweep"] = contrast_sweep(log)
+    if not args.no_svk:
+        out["svk_porous"] = svk_porous_leg(log)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")

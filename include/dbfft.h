@@ -73,13 +73,18 @@ enum { DBFFT_FP64 = 0, DBFFT_FP32_MIXED = 1 };       /* precision */
  *              backward Euler; small strains; Newton outer loop (Sec. 2.4).
  *  NEOHOOKE    field uint8 phase id; params (mu, kappa) per phase.
  *              W = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2 with
- *              lambda = kappa - 2 mu / 3; finite strains (Sec. 2.4). */
+ *              lambda = kappa - 2 mu / 3; finite strains (Sec. 2.4).
+ *  SVK         field uint8 phase id; params (E, nu) per phase.  Saint
+ *              Venant-Kirchhoff hyperelasticity of Sec. 3.3: S = lambda
+ *              tr(E) I + 2 mu E with E = (F^T F - I)/2, P = F S; finite
+ *              strains (Sec. 2.4). */
 enum {
   DBFFT_MAT_ISO_PHASE = 0,
   DBFFT_MAT_ISO_FIELD = 1,
   DBFFT_MAT_ANISO_GRAIN = 2,
   DBFFT_MAT_J2VP_CUBIC = 3,
-  DBFFT_MAT_NEOHOOKE = 4
+  DBFFT_MAT_NEOHOOKE = 4,
+  DBFFT_MAT_SVK = 5
 };
 
 typedef struct {
@@ -120,7 +125,7 @@ void dbfft_default_opts(dbfft_opts* opts);
 
 /* Creates a context for one cell (Sec. 2.1 discretization + material).
  * n: grid size (host, 3 values); kinematics DBFFT_SMALL / DBFFT_FINITE
- * (NEOHOOKE needs FINITE, every other kind SMALL); precision DBFFT_FP64 or
+ * (NEOHOOKE and SVK need FINITE, every other kind SMALL); precision DBFFT_FP64 or
  * DBFFT_FP32_MIXED (FP32 transforms and pointwise work, FP64 dot products,
  * residuals and outer corrections); hip_stream: hipStream_t the context
  * enqueues on (NULL = default stream).  The material field is copied.
@@ -148,8 +153,8 @@ dbfft_status dbfft_apply_fourier(dbfft_ctx* ctx, const void* a_dev, const double
                                  double* sigma_bar_out);
 
 /* Solves the cell problem (Sec. 2.2-2.5): PCG with the preconditioner
- * [xi.Cbar.xi]^-1 (eqs. pred2/pred3); Newton over increments for J2VP_CUBIC
- * and NEOHOOKE.  load: 9 host doubles, row-major; on components whose
+ * [xi.Cbar.xi]^-1 (eqs. pred2/pred3); Newton over increments for J2VP_CUBIC,
+ * NEOHOOKE and SVK.  load: 9 host doubles, row-major; on components whose
  * stress_mask entry is 0 the prescribed strain (small) or deformation
  * gradient F (finite), elsewhere the prescribed stress (Sec. 2.3).  Small
  * strains need a symmetric mask and symmetric load.  The load is reached by
@@ -220,8 +225,8 @@ typedef struct dbfft_batch dbfft_batch;
 
 /* Creates a batch over ncell existing contexts (host array of handles).
  * All contexts need the same precision, kinematics and material class
- * (linear: ISO_PHASE / ISO_FIELD / ANISO_GRAIN; non-linear: J2VP_CUBIC or
- * NEOHOOKE).  The contexts stay owned by the caller and must outlive the
+ * (linear: ISO_PHASE / ISO_FIELD / ANISO_GRAIN; non-linear: J2VP_CUBIC,
+ * NEOHOOKE or SVK).  The contexts stay owned by the caller and must outlive the
  * batch; a context may belong to several batches but only one call may use
  * it at a time.  use_graph = 0 launches the chunks eagerly instead of
  * replaying a captured graph.  Autotunes the column tile of the x and y

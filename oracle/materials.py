@@ -7,8 +7,9 @@ workloads here use:
   * cubic elasticity rotated per grain, with a rate-dependent J2 flow rule
     integrated by backward Euler (a stand-in for the paper's crystal
     plasticity of Sec. 3.4, whose parameters live in a cited work);
-  * compressible neo-Hookean hyperelasticity (a stand-in for the
-    Saint Venant-Kirchhoff law of Sec. 3.3).
+  * the Saint Venant-Kirchhoff hyperelastic law of Sec. 3.3 (matrix and
+    compliant pores, E and nu per phase);
+  * compressible neo-Hookean hyperelasticity (a second finite-strain law).
 The J2 and neo-Hookean laws are not in the paper: their parity is pinned by
 closed forms and finite differences in tests/, not by the paper.
 """
@@ -211,3 +212,37 @@ def neohooke_tangent(F, mu, lam):
     return (mu[..., None, None, None, None] * t1
             + c2[..., None, None, None, None] * t2
             + lam[..., None, None, None, None] * t3)
+
+
+# ---------------------------------------------------------------------------
+# Saint Venant-Kirchhoff (Sec. 3.3):  S = lam tr(E) I + 2 mu E with the
+# Green-Lagrange strain E = (F^T F - I)/2, and P = F S.
+#   dP = dF S + F dS,  dS = lam tr(dE) I + 2 mu dE,  dE = sym(F^T dF)
+#   K_iJkL = d_ik S_LJ + lam F_iJ F_kL + mu (F_iL F_kJ + (F F^T)_ik d_JL)
+# ---------------------------------------------------------------------------
+
+def svk_second_pk(F, mu, lam):
+    """Second Piola-Kirchhoff stress S of F (..., 3, 3)."""
+    E = 0.5 * (np.swapaxes(F, -1, -2) @ F - I3)
+    trE = np.trace(E, axis1=-2, axis2=-1)
+    mu = np.asarray(mu)[..., None, None]
+    lam = np.asarray(lam)[..., None, None]
+    return lam * trE[..., None, None] * I3 + 2.0 * mu * E
+
+
+def svk_stress(F, mu, lam):
+    """First Piola-Kirchhoff stress P = F S."""
+    return F @ svk_second_pk(F, mu, lam)
+
+
+def svk_tangent(F, mu, lam):
+    """dP/dF as a (..., 3, 3, 3, 3) array indexed [i, J, k, L]."""
+    S = svk_second_pk(F, mu, lam)
+    mu = np.asarray(mu, dtype=np.float64)[..., None, None, None, None]
+    lam = np.asarray(lam, dtype=np.float64)[..., None, None, None, None]
+    FFt = F @ np.swapaxes(F, -1, -2)
+    t1 = np.einsum("ik,...LJ->...iJkL", I3, S)
+    t2 = np.einsum("...iJ,...kL->...iJkL", F, F)
+    t3 = np.einsum("...iL,...kJ->...iJkL", F, F)
+    t4 = np.einsum("...ik,JL->...iJkL", FFt, I3)
+    return t1 + lam * t2 + mu * (t3 + t4)

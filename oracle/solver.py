@@ -366,6 +366,22 @@ class J2Law:
         return sig_t, GeneralTangent(Ct), ep.reshape(self.shape + (6,))
 
 
+class SVKLaw:
+    """Saint Venant-Kirchhoff law object for newton() (Sec. 3.3): field is
+    H = F - I."""
+
+    def __init__(self, mu, lam):
+        self.mu = np.asarray(mu, dtype=np.float64)
+        self.lam = np.asarray(lam, dtype=np.float64)
+
+    def update(self, H, state):
+        from .materials import svk_stress, svk_tangent
+        F = np.moveaxis(H, (0, 1), (-2, -1)) + np.eye(3)
+        P = svk_stress(F, self.mu, self.lam)
+        K = svk_tangent(F, self.mu, self.lam)
+        return np.moveaxis(P, (-2, -1), (0, 1)), GeneralTangent(K), state
+
+
 class NeoHookeLaw:
     """Finite-strain law object for newton(): field is H = F - I."""
 

@@ -22,7 +22,7 @@ DBFFT_EMATERIAL = 7
 
 SMALL, FINITE = 0, 1
 FP64, FP32_MIXED = 0, 1
-MAT_ISO_PHASE, MAT_ISO_FIELD, MAT_ANISO_GRAIN, MAT_J2VP_CUBIC, MAT_NEOHOOKE = 0, 1, 2, 3, 4
+MAT_ISO_PHASE, MAT_ISO_FIELD, MAT_ANISO_GRAIN, MAT_J2VP_CUBIC, MAT_NEOHOOKE, MAT_SVK = 0, 1, 2, 3, 4, 5
 
 EXPORTED = (
     "dbfft_default_opts", "dbfft_setup", "dbfft_apply", "dbfft_apply_fourier", "dbfft_solve",

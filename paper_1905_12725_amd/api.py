@@ -21,6 +21,7 @@ _MAT = {
     "aniso_grain": (nat.MAT_ANISO_GRAIN, torch.int32),
     "j2vp_cubic": (nat.MAT_J2VP_CUBIC, torch.int32),
     "neohooke": (nat.MAT_NEOHOOKE, torch.uint8),
+    "svk": (nat.MAT_SVK, torch.uint8),
 }
 
 

@@ -67,6 +67,7 @@ enum TanKind : int {
   TAN_ANISO_GRAIN = 2, // int32 grain id -> 21 Mandel coefficients (table)
   TAN_ANISO_FIELD = 3, // 21 Mandel coefficients per voxel, [21][nvox]
   TAN_NEO_FIELD = 4,   // finite strain: per-voxel F^-1 (9) and ln J, [10][nvox]; phase -> (mu, lambda)
+  TAN_SVK_FIELD = 5,   // finite strain: per-voxel F (9) and S (11 22 33 23 13 12), [15][nvox]; phase -> (mu, lambda)
 };
 
 template <typename T>
@@ -263,6 +264,10 @@ void launch_j2_update(const double* eps, const double* epsp_n, const int32_t* gr
                       const double* grain_S, double s0, double m, double edot0, double dt, long long nvox,
                       double* sig, double* tangent21, double* epsp_new, int* fail, hipStream_t st);
 void launch_neo_update(const double* H, const uint8_t* phase, const NeoParams& np, long long nvox, double* P,
+                       double* data, int* fail, hipStream_t st);
+// Saint Venant-Kirchhoff: P = F S, S = lam tr(E) I + 2 mu E, E = (F^T F - I)/2;
+// data = (F row-major, S in stored order) [15][nvox]
+void launch_svk_update(const double* H, const uint8_t* phase, const NeoParams& np, long long nvox, double* P,
                        double* data, int* fail, hipStream_t st);
 void launch_max_abs_diff(const double* a, const double* b, long long n, double* partials, int nblocks,
                          hipStream_t st);

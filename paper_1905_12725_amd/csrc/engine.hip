@@ -166,7 +166,7 @@ struct Ctx {
   double* sol2 = nullptr;  // adjoint solution
   double *fa = nullptr, *fb = nullptr, *fc = nullptr;  // real FP64 fields ncomp x N
   double *state = nullptr, *state_new = nullptr;        // J2 plastic strain (Mandel) 6 x N
-  double* tanf = nullptr;                               // J2: 21 x N; neo: 10 x N  (FP64)
+  double* tanf = nullptr;                               // J2: 21 x N; neo: 10 x N; SVK: 15 x N (FP64)
   float* tanf32 = nullptr;
   double* partA = nullptr;  // energy partials / general
   double* partB = nullptr;  // update partials
@@ -206,7 +206,9 @@ struct Ctx {
   double sig_rm[9] = {0}, eps_rm[9] = {0};
   bool use_fused = true;  // opts.fused_cg of the current call
   bool use_graph = true;  // opts.graph of the current call
-  bool linear_material() const { return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE; }
+  bool linear_material() const {
+    return mat != DBFFT_MAT_J2VP_CUBIC && mat != DBFFT_MAT_NEOHOOKE && mat != DBFFT_MAT_SVK;
+  }
 };
 
 enum ProfKind {
@@ -319,6 +321,7 @@ TangentArgs<double> elastic_tangent<double>(Ctx& c) {
     case DBFFT_MAT_ISO_PHASE: t.kind = TAN_ISO_PHASE; break;
     case DBFFT_MAT_ISO_FIELD: t.kind = TAN_ISO_FIELD; t.field = c.E64; break;
     case DBFFT_MAT_NEOHOOKE: t.kind = TAN_NEO_FIELD; t.field = c.tanf; break;
+    case DBFFT_MAT_SVK: t.kind = TAN_SVK_FIELD; t.field = c.tanf; break;
     case DBFFT_MAT_J2VP_CUBIC:
       if (c.tangent_from_field) {
         t.kind = TAN_ANISO_FIELD;
@@ -349,7 +352,7 @@ TangentArgs<float> elastic_tangent<float>(Ctx& c) {
   t.grain = d.grain;
   t.grain_table = d.grain_table;
   if (d.kind == TAN_ISO_FIELD) t.field = c.E32;
-  else if (d.kind == TAN_ANISO_FIELD || d.kind == TAN_NEO_FIELD) t.field = c.tanf32;
+  else if (d.kind == TAN_ANISO_FIELD || d.kind == TAN_NEO_FIELD || d.kind == TAN_SVK_FIELD) t.field = c.tanf32;
   return t;
 }
 
@@ -918,7 +921,8 @@ static void material_update(Ctx& c, const double* fld, double* sig_out, double d
       np.mu[i] = c.mu[i];
       np.lam[i] = c.lam[i];
     }
-    launch_neo_update(fld, c.phase, np, c.g.nvox, sig_out, c.tanf, c.fail_dev, c.st);
+    if (c.mat == DBFFT_MAT_SVK) launch_svk_update(fld, c.phase, np, c.g.nvox, sig_out, c.tanf, c.fail_dev, c.st);
+    else launch_neo_update(fld, c.phase, np, c.g.nvox, sig_out, c.tanf, c.fail_dev, c.st);
   }
   int fail = 0;
   HIPCK(hipMemcpyAsync(&fail, c.fail_dev, sizeof(int), hipMemcpyDeviceToHost, c.st));
@@ -926,7 +930,7 @@ static void material_update(Ctx& c, const double* fld, double* sig_out, double d
   if (fail) DB_THROW(DBFFT_EMATERIAL, "constitutive update failed (local Newton or J <= 0)");
   c.tangent_from_field = 1;
   if (c.prec == DBFFT_FP32_MIXED) {
-    const int nt = (c.mat == DBFFT_MAT_J2VP_CUBIC) ? 21 : 10;
+    const int nt = (c.mat == DBFFT_MAT_J2VP_CUBIC) ? 21 : (c.mat == DBFFT_MAT_SVK ? 15 : 10);
     launch_convert<double, float>(c.tanf32, c.tanf, (long long)nt * c.g.nvox, c.st);
   }
 }
@@ -1193,9 +1197,9 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
   }
   if (kin != DBFFT_SMALL && kin != DBFFT_FINITE) DB_THROW(DBFFT_EINVAL, "unknown kinematics");
   if (prec != DBFFT_FP64 && prec != DBFFT_FP32_MIXED) DB_THROW(DBFFT_EINVAL, "unknown precision");
-  if (mat < 0 || mat > DBFFT_MAT_NEOHOOKE) DB_THROW(DBFFT_EINVAL, "unknown material kind");
-  if ((mat == DBFFT_MAT_NEOHOOKE) != (kin == DBFFT_FINITE))
-    DB_THROW(DBFFT_EINVAL, "NEOHOOKE needs FINITE kinematics and every other material SMALL");
+  if (mat < 0 || mat > DBFFT_MAT_SVK) DB_THROW(DBFFT_EINVAL, "unknown material kind");
+  if ((mat == DBFFT_MAT_NEOHOOKE || mat == DBFFT_MAT_SVK) != (kin == DBFFT_FINITE))
+    DB_THROW(DBFFT_EINVAL, "NEOHOOKE and SVK need FINITE kinematics and every other material SMALL");
   if (!field) DB_THROW(DBFFT_EINVAL, "null material field");
   if (!params || nparams < 1) DB_THROW(DBFFT_EINVAL, "null material parameters");
 
@@ -1233,12 +1237,12 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
 
     const long long N = g.nvox;
     // material
-    if (mat == DBFFT_MAT_ISO_PHASE || mat == DBFFT_MAT_NEOHOOKE) {
+    if (mat == DBFFT_MAT_ISO_PHASE || mat == DBFFT_MAT_NEOHOOKE || mat == DBFFT_MAT_SVK) {
       if (nparams % 2 != 0 || nparams / 2 > kMaxPhases) DB_THROW(DBFFT_EINVAL, "phase parameters: pairs, at most 8 phases");
       c->nphase = nparams / 2;
       for (int p = 0; p < c->nphase; ++p) {
         const double a = params[2 * p], b = params[2 * p + 1];
-        if (mat == DBFFT_MAT_ISO_PHASE) {
+        if (mat == DBFFT_MAT_ISO_PHASE || mat == DBFFT_MAT_SVK) {
           c->lam[p] = a * b / ((1.0 + b) * (1.0 - 2.0 * b));
           c->mu[p] = a / (2.0 * (1.0 + b));
         } else {
@@ -1363,6 +1367,14 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
       HIPCK(hipMemset(c->state, 0, 6 * N * sizeof(double)));
       c->tanf = static_cast<double*>(dalloc(21 * N * sizeof(double)));
       c->tanf32 = static_cast<float*>(dalloc(21 * N * sizeof(float)));
+    } else if (mat == DBFFT_MAT_SVK) {
+      c->tanf = static_cast<double*>(dalloc(15 * N * sizeof(double)));
+      c->tanf32 = static_cast<float*>(dalloc(15 * N * sizeof(float)));
+      // reference configuration: F = I, S = 0
+      std::vector<double> h(15 * N, 0.0);
+      for (long long v = 0; v < N; ++v) h[0 * N + v] = h[4 * N + v] = h[8 * N + v] = 1.0;
+      HIPCK(hipMemcpy(c->tanf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      launch_convert<double, float>(c->tanf32, c->tanf, 15 * N, c->st);
     } else if (mat == DBFFT_MAT_NEOHOOKE) {
       c->tanf = static_cast<double*>(dalloc(10 * N * sizeof(double)));
       c->tanf32 = static_cast<float*>(dalloc(10 * N * sizeof(float)));

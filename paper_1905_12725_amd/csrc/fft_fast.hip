@@ -11,6 +11,7 @@
 // transform's input distribution after a register renaming, so the z pass
 // applies the pointwise tangent with no data movement at all.
 #include "fft_common.h"
+#include "fft_generic.h"
 #include "pcg_core.h"
 
 namespace dbfft {
@@ -931,37 +932,7 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
             energy += (double)(ev[0] * sv[0] + ev[1] * sv[1] + ev[2] * sv[2]) +
                       2.0 * (double)(ev[3] * sv[3] + ev[4] * sv[4] + ev[5] * sv[5]);
           } else {
-            T Fi[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Fi[i] = tn.field[(long long)i * g.nvox + vox];
-            const T lnJ = tn.field[9LL * g.nvox + vox];
-            const int p = tn.phase[vox];
-            const T mu = (T)tn.mu[p], lam = (T)tn.lam[p];
-            T tr = 0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int J = 0; J < 3; ++J) tr += Fi[J * 3 + i] * ev[i * 3 + J];
-            T T1[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-              for (int J = 0; J < 3; ++J) {
-                T acc = 0;
-#pragma unroll
-                for (int b = 0; b < 3; ++b) acc += ev[b * 3 + a] * Fi[J * 3 + b];
-                T1[a * 3 + J] = acc;
-              }
-            const T c2 = mu - lam * lnJ;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int J = 0; J < 3; ++J) {
-                T acc = 0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) acc += Fi[a * 3 + i] * T1[a * 3 + J];
-                sv[i * 3 + J] = mu * ev[i * 3 + J] + c2 * acc + lam * tr * Fi[J * 3 + i];
-              }
+            tangent_finite<T>(tn, vox, g.nvox, ev, sv);
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < 9; ++c) acc += (double)(ev[c] * sv[c]);

@@ -293,6 +293,55 @@ __device__ __forceinline__ void tangent_neo(const TangentArgs<T>& tn, long long 
     }
 }
 
+// finite strain Saint Venant-Kirchhoff tangent applied to H (row-major 3x3),
+// from the per-voxel F and S: with C = F^T H,
+// dP = H S + F (lam tr(C) I + mu (C + C^T))
+template <typename T>
+__device__ __forceinline__ void tangent_svk(const TangentArgs<T>& tn, long long vox, long long nvox, const T* H,
+                                            T* P) {
+  T F[9], S6[6];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) F[i] = tn.field[(long long)i * nvox + vox];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) S6[a] = tn.field[(long long)(9 + a) * nvox + vox];
+  const T S[9] = {S6[0], S6[5], S6[4], S6[5], S6[1], S6[3], S6[4], S6[3], S6[2]};
+  const int p = tn.phase[vox];
+  const T mu = (T)tn.mu[p], lam = (T)tn.lam[p];
+  T C[9];
+#pragma unroll
+  for (int K = 0; K < 3; ++K)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      T acc = 0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) acc += F[m * 3 + K] * H[m * 3 + J];
+      C[K * 3 + J] = acc;
+    }
+  const T tr = C[0] + C[4] + C[8];
+  T dS[9];
+#pragma unroll
+  for (int K = 0; K < 3; ++K)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) dS[K * 3 + J] = mu * (C[K * 3 + J] + C[J * 3 + K]) + ((K == J) ? lam * tr : (T)0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      T acc = 0;
+#pragma unroll
+      for (int K = 0; K < 3; ++K) acc += H[i * 3 + K] * S[K * 3 + J] + F[i * 3 + K] * dS[K * 3 + J];
+      P[i * 3 + J] = acc;
+    }
+}
+
+// finite-strain tangent of the context's law applied to H
+template <typename T>
+__device__ __forceinline__ void tangent_finite(const TangentArgs<T>& tn, long long vox, long long nvox, const T* H,
+                                               T* P) {
+  if (tn.kind == TAN_SVK_FIELD) tangent_svk<T>(tn, vox, nvox, H, P);
+  else tangent_neo<T>(tn, vox, nvox, H, P);
+}
+
 template <typename T, int MODE, int KIN>
 __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const Geom& g, const FftPlan& plan,
                                           const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ rtwg,
@@ -412,7 +461,7 @@ __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const G
           energy += (double)(e[0] * sg[0] + e[1] * sg[1] + e[2] * sg[2]) +
                     2.0 * (double)(e[3] * sg[3] + e[4] * sg[4] + e[5] * sg[5]);
         } else {
-          tangent_neo<T>(tn, vox, g.nvox, e, sg);
+          tangent_finite<T>(tn, vox, g.nvox, e, sg);
           double acc = 0.0;
 #pragma unroll
           for (int c = 0; c < 9; ++c) acc += (double)(e[c] * sg[c]);

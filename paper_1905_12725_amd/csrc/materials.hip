@@ -8,6 +8,8 @@
 //    consistent tangent is [S + dp dn/dsigma + dp (m / s_eq) n n^T]^-1;
 //  * compressible neo-Hookean first Piola-Kirchhoff stress, plus the
 //    per-voxel data (F^-1, ln J) the fused operator needs for K:H;
+//  * Saint Venant-Kirchhoff first Piola-Kirchhoff stress (Sec. 3.3), plus
+//    the per-voxel data (F, S) the fused operator needs for K:H;
 //  * voxel averages of the tangent (the preconditioner's mean stiffness,
 //    Sec. 2.5), max-norm of a field difference (Newton stop, Sec. 2.4),
 //    adjoint gradient density.
@@ -261,6 +263,47 @@ void launch_neo_update(const double* H, const uint8_t* phase, const NeoParams& n
   hipLaunchKernelGGL(k_neo_update, dim3(nb), dim3(kMatThreads), 0, st, H, phase, np, nvox, P, data, fail);
 }
 
+// Saint Venant-Kirchhoff: E = (F^T F - I)/2, S = lam tr(E) I + 2 mu E,
+// P = F S; data = (F row-major, S stored order 11 22 33 23 13 12).  No
+// failure condition: the law is defined for every F.
+__global__ __launch_bounds__(kMatThreads) void k_svk_update(const double* __restrict__ H,
+                                                           const uint8_t* __restrict__ phase, NeoParams np,
+                                                           long long nvox, double* __restrict__ P,
+                                                           double* __restrict__ data) {
+  const long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x;
+  if (v >= nvox) return;
+  double F[9];
+  for (int i = 0; i < 9; ++i) F[i] = H[(long long)i * nvox + v] + ((i % 4 == 0) ? 1.0 : 0.0);
+  double E[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double c = 0.0;
+      for (int k = 0; k < 3; ++k) c += F[k * 3 + a] * F[k * 3 + b];
+      E[a * 3 + b] = 0.5 * (c - (a == b ? 1.0 : 0.0));
+    }
+  const int p = phase[v];
+  const double mu = np.mu[p], lam = np.lam[p];
+  const double tr = E[0] + E[4] + E[8];
+  double S[9];
+  for (int a = 0; a < 9; ++a) S[a] = 2.0 * mu * E[a] + ((a % 4 == 0) ? lam * tr : 0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int J = 0; J < 3; ++J) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += F[i * 3 + k] * S[k * 3 + J];
+      P[(long long)(i * 3 + J) * nvox + v] = acc;
+    }
+  for (int i = 0; i < 9; ++i) data[(long long)i * nvox + v] = F[i];
+  const int sidx[6] = {0, 4, 8, 5, 2, 1};
+  for (int a = 0; a < 6; ++a) data[(long long)(9 + a) * nvox + v] = S[sidx[a]];
+}
+
+void launch_svk_update(const double* H, const uint8_t* phase, const NeoParams& np, long long nvox, double* P,
+                       double* data, int* fail, hipStream_t st) {
+  (void)fail;
+  const int nb = (int)((nvox + kMatThreads - 1) / kMatThreads);
+  hipLaunchKernelGGL(k_svk_update, dim3(nb), dim3(kMatThreads), 0, st, H, phase, np, nvox, P, data);
+}
+
 // ------------------------------------------------------------ tangent mean
 constexpr int kMeanBlocks = 512;
 int tangent_mean_block_count(const Geom&) { return kMeanBlocks; }
@@ -303,6 +346,17 @@ __global__ __launch_bounds__(kMatThreads) void k_tangent_mean(TangentArgs<T> tn,
         } else {
           val = (double)tn.field[(long long)c * g.nvox + v];
         }
+      } else if (tn.kind == TAN_SVK_FIELD) {
+        // K_iJkL = d_ik S_LJ + lam F_iJ F_kL + mu (F_iL F_kJ + (F F^T)_ik d_JL)
+        const int L = c % 3, k = (c / 3) % 3, J = (c / 9) % 3, i = c / 27;
+        auto Fv = [&](int r, int q) { return (double)tn.field[(long long)(r * 3 + q) * g.nvox + v]; };
+        const int smap[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};  // (a, b) -> stored index
+        const int p = tn.phase[v];
+        const double mu = tn.mu[p], lam = tn.lam[p];
+        double FFt = 0.0;
+        for (int q = 0; q < 3; ++q) FFt += Fv(i, q) * Fv(k, q);
+        val = ((i == k) ? (double)tn.field[(long long)(9 + smap[L * 3 + J]) * g.nvox + v] : 0.0) +
+              lam * Fv(i, J) * Fv(k, L) + mu * (Fv(i, L) * Fv(k, J) + ((J == L) ? FFt : 0.0));
       } else {
         // K_iJkL, c = ((i*3+J)*3+k)*3+L
         const int L = c % 3, k = (c / 3) % 3, J = (c / 9) % 3, i = c / 27;

@@ -256,3 +256,88 @@ def test_adjoint_finite_differences(objective):
         Em = E.copy(); Em[idx] -= h
         fd = (J_of(Ep) - J_of(Em)) / (2 * h)
         assert np.isclose(g[idx], fd, rtol=1e-6, atol=1e-9 * abs(J))
+
+
+# --------------------------------------------------------------------------
+# Saint Venant-Kirchhoff (Sec. 3.3)
+# --------------------------------------------------------------------------
+
+def test_svk_reference_tangent_is_isotropic_elasticity():
+    mu, lam = 1.3, 2.1
+    K = mt.svk_tangent(np.eye(3), np.float64(mu), np.float64(lam))
+    assert np.allclose(K, mt.isotropic_tensor(lam, mu), atol=1e-14)
+    assert np.allclose(mt.svk_stress(np.eye(3), mu, lam), 0.0, atol=1e-15)
+
+
+def test_svk_uniaxial_stretch_closed_form():
+    """F = diag(a, 1, 1): E11 = (a^2 - 1)/2, S11 = (lam + 2 mu) E11,
+    S22 = S33 = lam E11, P = F S (worked by hand)."""
+    mu, lam, a = 26.9, 40.4, 2.0
+    e11 = 0.5 * (a * a - 1.0)
+    expect = np.diag([a * (lam + 2 * mu) * e11, lam * e11, lam * e11])
+    assert np.allclose(mt.svk_stress(np.diag([a, 1.0, 1.0]), mu, lam), expect, rtol=1e-15, atol=0)
+
+
+def test_svk_tangent_finite_difference_symmetry_and_objectivity():
+    rng = np.random.default_rng(17)
+    F = np.eye(3) + 0.3 * rng.standard_normal((3, 3))
+    mu, lam = 1.0, 1.5
+    K = mt.svk_tangent(F, np.float64(mu), np.float64(lam))
+    h = 1e-6
+    for k in range(3):
+        for L in range(3):
+            Fp = F.copy(); Fp[k, L] += h
+            Fm = F.copy(); Fm[k, L] -= h
+            fd = (mt.svk_stress(Fp, mu, lam) - mt.svk_stress(Fm, mu, lam)) / (2 * h)
+            assert np.allclose(K[:, :, k, L], fd, atol=1e-8)
+    # hyperelastic: major symmetry of dP/dF
+    assert np.allclose(K, np.transpose(K, (2, 3, 0, 1)), atol=1e-13)
+    Q = ms.random_rotations(1, 8)[0]
+    assert np.allclose(mt.svk_stress(Q @ F, mu, lam), Q @ mt.svk_stress(F, mu, lam), atol=1e-13)
+
+
+def _finite_laminate_law(stress, tangent, mus, lams, fractions, normal, Fbar):
+    """Two-phase finite-strain laminate for any law: F_p = Fbar + a_p (x) n,
+    traction continuity P_0 n = P_1 n, f_0 a_0 + f_1 a_1 = 0; Newton in a_0."""
+    n = np.zeros(3); n[normal] = 1.0
+    f0, f1 = fractions
+    a0 = np.zeros(3)
+    for _ in range(50):
+        a1 = -f0 * a0 / f1
+        F0 = Fbar + np.outer(a0, n)
+        F1 = Fbar + np.outer(a1, n)
+        g = stress(F0, mus[0], lams[0]) @ n - stress(F1, mus[1], lams[1]) @ n
+        A0 = np.einsum("iJkL,J,L->ik", tangent(F0, np.float64(mus[0]), np.float64(lams[0])), n, n)
+        A1 = np.einsum("iJkL,J,L->ik", tangent(F1, np.float64(mus[1]), np.float64(lams[1])), n, n)
+        d = np.linalg.solve(A0 + A1 * f0 / f1, -g)
+        a0 = a0 + d
+        if np.max(np.abs(d)) < 1e-15:
+            break
+    a1 = -f0 * a0 / f1
+    return f0 * stress(Fbar + np.outer(a0, n), mus[0], lams[0]) + f1 * stress(Fbar + np.outer(a1, n), mus[1], lams[1])
+
+
+def test_newton_svk_laminate():
+    shape = (8, 4, 4)
+    phase = ms.laminate(shape, 0, [4, 4])
+    lam0, mu0 = mt.lame(np.array([70.0, 0.7]), 0.3)
+    law = so.SVKLaw(mu0[phase], lam0[phase])
+    Fbar = np.array([[1.2, 0.05, 0.0], [0.02, 0.97, 0.01], [0.0, -0.03, 1.02]])
+    loads = [(np.eye(3) + (k + 1) / 4 * (Fbar - np.eye(3))) - np.eye(3) for k in range(4)]
+    a, e, st, info = so.newton(shape, law, loads, None, kin=so.FINITE, tol=1e-12, tol_load=1e-12,
+                               newton_tol=1e-12)
+    assert info.converged
+    expect = _finite_laminate_law(mt.svk_stress, mt.svk_tangent, mu0, lam0, [0.5, 0.5], 0, Fbar)
+    assert np.allclose(info.sigma_bar[-1], expect, rtol=0, atol=1e-10 * np.abs(expect).max())
+
+
+def test_newton_svk_homogeneous_closed_form():
+    shape = (4, 5, 3)
+    lam, mu = mt.lame(70.0, 0.3)
+    law = so.SVKLaw(np.full(shape, mu), np.full(shape, lam))
+    Fbar = np.diag([1.4, 1.0, 1.0])
+    a, e, st, info = so.newton(shape, law, [Fbar - np.eye(3)], None, kin=so.FINITE)
+    assert info.pcg_iters[0] == 0
+    e11 = 0.5 * (1.4 ** 2 - 1.0)
+    expect = np.diag([1.4 * (lam + 2 * mu) * e11, lam * e11, lam * e11])
+    assert np.allclose(info.sigma_bar[-1], expect, rtol=1e-14, atol=0)
