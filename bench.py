@@ -21,7 +21,10 @@ cells of uneven grid sizes, 10 load increments) compares the batched
 FP32-mixed solve with sequential FP64 solves; a third sweeps the phase
 contrast of a sphere inclusion at 63^3 and 64^3 (iterations per case); a
 fourth stretches a porous Saint Venant-Kirchhoff cell to twice its length
-(63^3, 5 increments) under both preconditioner-refresh policies.
+(63^3, 5 increments) under both preconditioner-refresh policies; a fifth
+solves the six load cases as one batch against one after the other; the
+64^3 J2 polycrystal (40 increments) and the 96^3 adjoint gradient are
+timed last.
 """
 from __future__ import annotations
 
@@ -241,6 +244,131 @@ def batched_leg(log, ncell=32, ninc=10, seed=4, only_batched=False):
     }
 
 
+def j2_polycrystal_leg(log, n=(64, 64, 64)):
+    """The 64^3 polycrystal: 200 seeded Voronoi grains with uniformly random
+    orientations, cubic elasticity C11 = 168, C12 = 121, C44 = 75 GPa, rate-
+    dependent J2 (sigma0 = 100 MPa, m = 20, edot0 = 1e-3/s); uniaxial strain
+    rate 1e-3/s to 2 % in 40 increments of 0.5 s, the other macroscopic
+    stresses zero; Newton + PCG, FP64 (parity is tested at small sizes)."""
+    import torch
+    from paper_1905_12725_amd import microstructure as ms
+    from paper_1905_12725_amd.api import Cell
+
+    grain, _ = ms.voronoi_grains(n, 200, 3)
+    R = ms.random_rotations(200, 3)
+    params = [168e3, 121e3, 75e3, 100.0, 20.0, 1e-3] + list(np.asarray(R).reshape(-1))
+    mask = np.ones((3, 3), bool)
+    mask[0, 0] = False
+    final = np.zeros((3, 3))
+    final[0, 0] = 0.02
+    with Cell(n, "j2vp_cubic", torch.from_numpy(grain), params) as cell:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = cell.solve(final, mask, n_increments=40, dt=0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+    log(f"[bench] J2 polycrystal 64^3: {el:.2f} s, {info['pcg_iters']} PCG, {info['newton_iters']} Newton, "
+        f"sigma11 {info['sigma_bar'][0, 0]:.2f} MPa")
+    return {"workload": "64^3, 200 Voronoi grains (seed 3), cubic elasticity (MPa), J2 s0 = 100 MPa, m = 20, "
+                        "edot0 = 1e-3/s; eps11 to 2 % at 1e-3/s in 40 increments, other stresses zero; FP64",
+            "solve_s": el, "pcg_iters": int(info["pcg_iters"]), "newton_iters": int(info["newton_iters"]),
+            "sigma11_MPa": float(info["sigma_bar"][0, 0]), "status": int(info["status"])}
+
+
+def adjoint_leg(log, n=(96, 96, 96), nfd=5):
+    """The 96^3 log-normal modulus field (correlation length 8 voxels,
+    sigma_log 1, nu 0.3): C1111 by a strain-controlled solve and its
+    gradient with respect to every voxel modulus by the adjoint solve, FP64
+    and FP32-mixed (tol 1e-10), with a central finite-difference check of
+    the FP64 gradient on `nfd` random voxels (the GPU tests use 50)."""
+    import torch
+    from paper_1905_12725_amd import microstructure as ms
+    from paper_1905_12725_amd.api import Cell
+
+    E = ms.lognormal_modulus(n, 5, corr_len=8.0, sigma_log=1.0)
+    load = np.zeros((3, 3)); load[0, 0] = 1.0
+    G = np.zeros((3, 3)); G[0, 0] = 1.0
+    out = {"workload": f"{n[0]}^3 log-normal E (seed 5, corr 8, sigma_log 1), nu 0.3; C1111 and dC1111/dE(x)"}
+    grads = {}
+    for prec in ("fp64", "fp32_mixed"):
+        with Cell(n, "iso_field", torch.from_numpy(E), [0.3], precision=prec) as cell:
+            cell.solve(load, tol=1e-10, tol_load=1e-10)  # warm
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = cell.solve(load, tol=1e-10, tol_load=1e-10)
+            torch.cuda.synchronize()
+            t_fwd = time.perf_counter() - t
+            t = time.perf_counter()
+            g, J = cell.adjoint(G)
+            torch.cuda.synchronize()
+            t_adj = time.perf_counter() - t
+            grads[prec] = g.cpu().numpy()
+        out[prec] = {"C1111": J, "forward_s": t_fwd, "adjoint_s": t_adj, "pcg_iters_forward": int(info["pcg_iters"])}
+        log(f"[bench] adjoint 96^3 {prec}: forward {t_fwd:.3f} s, adjoint {t_adj:.3f} s, C1111 {J:.6f}")
+    g64 = grads["fp64"]
+    out["fp32_mixed_vs_fp64_grad_rel"] = float(np.max(np.abs(grads["fp32_mixed"] - g64)) / np.max(np.abs(g64)))
+    rng = np.random.default_rng(55)
+    worst = 0.0
+    for _ in range(nfd):
+        idx = tuple(int(rng.integers(0, v)) for v in n)
+        h = 1e-2 * E[idx]
+        vals = []
+        for s in (1.0, -1.0):
+            Ef = E.copy()
+            Ef[idx] += s * h
+            with Cell(n, "iso_field", torch.from_numpy(Ef), [0.3]) as c2:
+                vals.append(float(c2.solve(load, tol=1e-12, tol_load=1e-12)["sigma_bar"][0, 0]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        worst = max(worst, abs(g64[idx] - fd) / abs(fd))
+    out["fd_voxels"] = nfd
+    out["fd_max_rel_err"] = worst
+    log(f"[bench] adjoint 96^3: FD check on {nfd} voxels, max rel err {worst:.2e}")
+    return out
+
+
+def multi_rhs_leg(log, sizes=((64, 64, 64), (96, 96, 96), (128, 128, 128))):
+    """The six Mandel load cases of the headline workload solved together:
+    six contexts on the same microstructure in one batch (one launch per
+    pass for all six right-hand sides) against the six solves one after
+    the other, FP64 and FP32-mixed, PCG tol 1e-8.  Timed after one warm
+    run of each."""
+    import torch
+    from paper_1905_12725_amd import microstructure as ms
+    from paper_1905_12725_amd.api import Cell, Batch
+
+    out = {"workload": "random spheres (radius 6-10 voxels scaled with n/128, 30 %, seed 2), contrast 100, "
+                       "six Mandel strain load cases, PCG tol 1e-8"}
+    loads = mandel_loads()
+    params = [1.0, 0.3, 100.0, 0.3]
+    for n in sizes:
+        phase, _, _ = ms.random_spheres(n, 2, 6.0 * n[0] / 128, 10.0 * n[0] / 128, 0.30)
+        for prec in ("fp64", "fp32_mixed"):
+            cell = Cell(n, "iso_phase", torch.from_numpy(phase), params, precision=prec)
+            run_cases(cell, loads[:2], tol=1e-8)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, it_seq, _ = run_cases(cell, loads, tol=1e-8)
+            torch.cuda.synchronize()
+            t_seq = time.perf_counter() - t
+            cell.close()
+            cells = [Cell(n, "iso_phase", torch.from_numpy(phase), params, precision=prec) for _ in loads]
+            with Batch(cells) as b:
+                b.solve(loads, None, tol=1e-8)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                infos = b.solve(loads, None, tol=1e-8)
+                torch.cuda.synchronize()
+                t_b = time.perf_counter() - t
+            for c in cells:
+                c.close()
+            key = f"{n[0]}x{n[1]}x{n[2]}_{prec}"
+            out[key] = {"sequential_s": t_seq, "batched_s": t_b, "speedup": t_seq / t_b,
+                        "pcg_iters_sequential": int(it_seq),
+                        "pcg_iters_batched": int(sum(i["pcg_iters"] for i in infos))}
+            log(f"[bench] six cases {key}: sequential {t_seq * 1e3:.1f} ms, one batch {t_b * 1e3:.1f} ms")
+    return out
+
+
 def svk_porous_leg(log, n=(63, 63, 63), seed=6, ninc=5):
     """Sec. 3.3 workload: Saint Venant-Kirchhoff matrix (E = 70, nu = 0.3)
     with 5 random non-overlapping spherical pores at 20 % porosity (equal
@@ -333,6 +461,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the phase-contrast sweep")
     ap.add_argument("--no-svk", action="store_true", help="skip the porous SVK finite-strain workload")
+    ap.add_argument("--no-multi", action="store_true", help="skip the six-cases-in-one-batch comparison")
+    ap.add_argument("--no-configs", action="store_true", help="skip the J2 polycrystal and adjoint workloads")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched FP32-mixed solve of the uneven neo-Hookean batch (for profiling)")
     ap.add_argument("--unfused", action="store_true", help="separate CG vector kernels (fused_cg = 0)")
@@ -500,6 +630,11 @@ def main():
         out["contrast_sweep"] = contrast_sweep(log)
     if not args.no_svk:
         out["svk_porous"] = svk_porous_leg(log)
+    if not args.no_multi:
+        out["multi_rhs"] = multi_rhs_leg(log)
+    if not args.no_configs:
+        out["j2_polycrystal"] = j2_polycrystal_leg(log)
+        out["adjoint"] = adjoint_leg(log)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")

@@ -1,0 +1,113 @@
+"""Full-size workloads through the C ABI, checked by the oracle on what it
+can evaluate at that size, or by properties that hold at any size.
+
+  * 128^3 random spheres (contrast 100), FP64 and FP32-mixed: the oracle's
+    own operator evaluates the GPU solution's equilibrium residual.
+  * 96^3 log-normal modulus field (correlation length 8, sigma_log 1): the
+    adjoint gradients of C1111 (strain control) and of the compliance
+    energy (stress control) against central finite differences of GPU
+    solves on random voxels, and the FP32-mixed gradient against FP64.
+
+Bars: oracle residual of the GPU solution at most 1.05 x the tolerance;
+gradient vs finite differences within 1e-3 relative (the voxel gradient
+is about 1e-6 of J, so a 1e-12 solve leaves about 1e-4 of noise in the
+difference quotient); FP32-mixed vs FP64 gradient within 1e-6 of the
+gradient's max norm.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_12725_amd import microstructure as ms
+from oracle import solver as so, materials as mt
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_residuals(n, tan, load, mask, a, eps_bar):
+    space = so.Space(n, so.SMALL, mask)
+    eps = space.field_of(a, np.zeros(len(space.S)), eps_bar)
+    r, dc = space.divergence_residual(tan.stress(eps))
+    _, sbar = so.split_load(space, load)
+    return so.residual_norms(space, (r, sbar - space.macro_row(dc)), dc)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_config2_128_oracle_residual(gpu, prec):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (128, 128, 128)
+    print(f"case config2 128^3 {prec}", flush=True)
+    phase, _, _ = ms.random_spheres(n, 2, 6.0, 10.0, 0.30)
+    E = np.array([1.0, 100.0])
+    load = np.zeros((3, 3))
+    load[1, 2] = load[2, 1] = 1e-3 / np.sqrt(2.0)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 100.0, 0.3], precision=prec) as cell:
+        info = cell.solve(load, tol=1e-8)
+        h = cell.homogenize()
+        a, _ = cell.solution()
+        a = a.cpu().numpy()
+    assert info["status"] == 0
+    lam, mu = mt.lame(E[phase], 0.3)
+    eq, ld = oracle_residuals(n, so.IsoTangent(lam, mu), load, np.zeros((3, 3), bool), a, h["eps_bar"])
+    assert eq < 1.05e-8, eq
+
+
+def _config5(objective):
+    n = (96, 96, 96)
+    E = ms.lognormal_modulus(n, 5, corr_len=8.0, sigma_log=1.0)
+    G = np.zeros((3, 3)); H = np.zeros((3, 3)); mask = np.zeros((3, 3), bool); load = np.zeros((3, 3))
+    if objective == "c1111":
+        load[0, 0] = 1.0
+        G[0, 0] = 1.0
+    else:
+        mask[:] = True
+        load[0, 0] = 1.0
+        H[0, 0] = 1.0
+    return n, E, G, H, mask, load
+
+
+@pytest.mark.parametrize("objective,nfd", [("c1111", 50), ("compliance", 10)])
+def test_config5_96_adjoint_vs_finite_differences(gpu, objective, nfd):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n, E, G, H, mask, load = _config5(objective)
+    print(f"case config5 96^3 adjoint {objective}, {nfd} voxels", flush=True)
+    nu, tol = 0.3, 1e-12
+    with Cell(n, "iso_field", torch.from_numpy(E), [nu]) as cell:
+        info = cell.solve(load, mask, tol=tol, tol_load=tol)
+        assert info["status"] == 0
+        g, J = cell.adjoint(G, H)
+        g = g.cpu().numpy()
+        rng = np.random.default_rng(55)
+        worst = 0.0
+        for k in range(nfd):
+            idx = tuple(int(rng.integers(0, v)) for v in n)
+            h = 1e-2 * E[idx]
+            vals = []
+            for s in (1.0, -1.0):
+                Ef = E.copy()
+                Ef[idx] += s * h
+                with Cell(n, "iso_field", torch.from_numpy(Ef), [nu]) as c2:
+                    i2 = c2.solve(load, mask, tol=tol, tol_load=tol)
+                vals.append(float(np.sum(G * i2["sigma_bar"]) + np.sum(H * i2["eps_bar"])))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            worst = max(worst, abs(g[idx] - fd) / abs(fd))
+        print(f"config5 {objective}: J = {J:.6e}, worst FD rel error {worst:.2e}", flush=True)
+        assert worst < 1e-3
+
+
+def test_config5_96_fp32_mixed_gradient(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n, E, G, H, mask, load = _config5("c1111")
+    print("case config5 96^3 fp32-mixed gradient", flush=True)
+    grads = {}
+    for prec in ("fp64", "fp32_mixed"):
+        with Cell(n, "iso_field", torch.from_numpy(E), [0.3], precision=prec) as cell:
+            cell.solve(load, mask, tol=1e-10, tol_load=1e-10)
+            g, J = cell.adjoint(G, H)
+            grads[prec] = (g.cpu().numpy(), J)
+    g64, J64 = grads["fp64"]
+    g32, J32 = grads["fp32_mixed"]
+    assert abs(J32 - J64) < 1e-8 * abs(J64)
+    assert np.max(np.abs(g32 - g64)) < 1e-6 * np.max(np.abs(g64))
