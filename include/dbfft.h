@@ -225,8 +225,8 @@ typedef struct dbfft_batch dbfft_batch;
 
 /* Creates a batch over ncell existing contexts (host array of handles).
  * All contexts need the same precision, kinematics and material class
- * (linear: ISO_PHASE / ISO_FIELD / ANISO_GRAIN; non-linear: J2VP_CUBIC,
- * NEOHOOKE or SVK).  The contexts stay owned by the caller and must outlive the
+ * (linear: ISO_PHASE / ISO_FIELD / ANISO_GRAIN, mixed freely; non-linear:
+ * one of J2VP_CUBIC, NEOHOOKE or SVK for every cell).  The contexts stay owned by the caller and must outlive the
  * batch; a context may belong to several batches but only one call may use
  * it at a time.  use_graph = 0 launches the chunks eagerly instead of
  * replaying a captured graph.  Autotunes the column tile of the x and y
@@ -240,8 +240,12 @@ dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int3
  * infos (ncell entries) receives each cell's dbfft_info.  n_increments and
  * dt are shared by all cells.  Afterwards dbfft_homogenize and
  * dbfft_get_solution read each context's result as after dbfft_solve.
- * Returns OK when every cell converged, else the status of the last cell
- * that did not (each info.status holds its own). */
+ * Each pass runs as one launch over all cells, except when every cell has
+ * at least 128^3 voxels and takes the fused single-cell iteration (small
+ * strains, n1 a power of two from 8 to 256, n2 even, opts.fused_cg): such
+ * cells are solved one after another by dbfft_solve, whose passes already
+ * fill the GPU.  Returns OK when every cell converged, else the status of
+ * the last cell that did not (each info.status holds its own). */
 dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_t* stress_masks,
                                int32_t n_increments, double dt, const dbfft_opts* opts, dbfft_info* infos);
 

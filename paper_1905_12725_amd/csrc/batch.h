@@ -37,6 +37,7 @@ struct CellDesc {
 // device arrays of ncell + 1 entries)
 struct BatchLaunch {
   int ncell, kin, ncomp;
+  int law;  // finite strains: 2 Saint Venant-Kirchhoff, 0 neo-Hookean
   int nbx_f, nby, nbz, nbv;
   const int* boff_xf;
   const int* boff_y;

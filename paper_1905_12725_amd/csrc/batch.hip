@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>*
 }
 
 // two-step z pass of a cell: four waves per block, one energy partial per block
-template <typename T, int M, int KIN>
+template <typename T, int M, int KIN, int LAW>
 __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, unsigned char* smem_raw) {
   using L = MixedLine<M>;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -132,7 +132,7 @@ __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, u
     else if constexpr (sizeof(T) == 4)
       e = mixed_line_fused<T, M, KIN_SMALL, 0>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
   } else if constexpr (sizeof(T) == 4) {
-    e = mixed_line_fused<T, M, KIN_FINITE, 0>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
+    e = mixed_line_fused<T, M, KIN_FINITE, LAW>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
   }
   if (lane == 0) ew[w] = e;
   __syncthreads();
@@ -143,7 +143,7 @@ __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, u
   }
 }
 
-template <typename T, int KIN>
+template <typename T, int KIN, int LAW>
 __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __restrict__ D, const int* __restrict__ boff,
                                                         int ncell, int ncomp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __res
   if (R.mz) {
     switch (R.g.n3 / 2) {
 #define DBFFT_BZ(MM) \
-  case MM: batch_mixed_line<T, MM, KIN>(R, lb, smem_raw); return;
+  case MM: batch_mixed_line<T, MM, KIN, LAW>(R, lb, smem_raw); return;
       DBFFT_BZ(12) DBFFT_BZ(16) DBFFT_BZ(18) DBFFT_BZ(20) DBFFT_BZ(24) DBFFT_BZ(25) DBFFT_BZ(27) DBFFT_BZ(30)
       DBFFT_BZ(32) DBFFT_BZ(36) DBFFT_BZ(40) DBFFT_BZ(45) DBFFT_BZ(48) DBFFT_BZ(50) DBFFT_BZ(54) DBFFT_BZ(60)
       DBFFT_BZ(64)
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __res
       default: return;
     }
   }
-  line_core<T, LP_FUSED, KIN>(R.W, R.W, R.g, R.p3, R.tw3, R.rtw, R.tan, R.sc->pmac, nullptr, R.partA, R.L, ncomp,
+  line_core<T, LP_FUSED, KIN, LAW>(R.W, R.W, R.g, R.p3, R.tw3, R.rtw, R.tan, R.sc->pmac, nullptr, R.partA, R.L, ncomp,
                               (long long)lb, smem_raw);
 }
 
@@ -222,9 +222,11 @@ void launch_batch_iteration(const BatchLaunch& bl, const void* desc, hipStream_t
                      bl.ncomp, (T)1);
   // z: C2R, tangent, R2C
   if (bl.kin == KIN_SMALL)
-    hipLaunchKernelGGL((kb_line<T, KIN_SMALL>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+    hipLaunchKernelGGL((kb_line<T, KIN_SMALL, 0>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+  else if (bl.law == 2)
+    hipLaunchKernelGGL((kb_line<T, KIN_FINITE, 2>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
   else
-    hipLaunchKernelGGL((kb_line<T, KIN_FINITE>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+    hipLaunchKernelGGL((kb_line<T, KIN_FINITE, 0>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
   // y forward
   hipLaunchKernelGGL((kb_strided<T, SP_PLAIN>), dim3(bl.nby), ts, bl.lds_y, st, D, bl.boff_y, bl.ncell, 1, BUF_W, BUF_W,
                      bl.ncomp, (T)-1);

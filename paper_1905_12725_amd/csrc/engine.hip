@@ -1409,6 +1409,7 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
 // chunk of iterations is captured once in a HIP graph and replayed.
 struct Batch {
   std::vector<Ctx*> cells;
+  std::vector<dbfft_ctx*> handles;  // the callers' handles of `cells`
   int prec = 0, kin = 0, ncomp = 6;
   hipStream_t st = nullptr;  // own stream (graph capture needs a non-null stream)
   void* desc_dev = nullptr;
@@ -1568,6 +1569,7 @@ static void batch_build(Batch& B) {
   HIPCK(hipMemcpy(B.boff_dev, boff.data(), boff.size() * sizeof(int), hipMemcpyHostToDevice));
   B.bl.ncell = n;
   B.bl.kin = B.kin;
+  B.bl.law = (B.cells[0]->mat == DBFFT_MAT_SVK) ? 2 : 0;
   B.bl.ncomp = B.ncomp;
   B.bl.nbx_f = bx[n];
   B.bl.nby = by[n];
@@ -2165,13 +2167,17 @@ dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int3
   Ctx& c0 = *C(cells[0]);
   for (int r = 1; r < ncell; ++r) {
     Ctx& c = *C(cells[r]);
-    if (c.prec != c0.prec || c.kin != c0.kin || c.linear_material() != c0.linear_material())
+    if (c.prec != c0.prec || c.kin != c0.kin || c.linear_material() != c0.linear_material() ||
+        (!c0.linear_material() && c.mat != c0.mat))
       DB_THROW(DBFFT_EINVAL, "batched contexts need one precision, one kinematics and one material class");
   }
   dbfft_batch* h = new dbfft_batch();
   try {
     Batch& B = h->impl;
-    for (int r = 0; r < ncell; ++r) B.cells.push_back(C(cells[r]));
+    for (int r = 0; r < ncell; ++r) {
+      B.cells.push_back(C(cells[r]));
+      B.handles.push_back(cells[r]);
+    }
     B.prec = c0.prec;
     B.kin = c0.kin;
     B.ncomp = c0.ncomp;
@@ -2188,6 +2194,18 @@ dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int3
   *out = h;
   return DBFFT_OK;
   API_END
+}
+
+// A batch whose every cell takes the fused single-cell iteration with at
+// least 128^3 voxels solves the cells one after another with it: each pass
+// then already has a thousand or more blocks, and the batched passes (LDS
+// Stockham transforms, separate CG vector kernels) are slower there.
+static bool solve_cellwise(const Batch& B, const dbfft_opts& o) {
+  for (const Ctx* c : B.cells)
+    if (!(o.fused_cg && c->kin == KIN_SMALL && fast_strided_supported(c->n[0]) && c->n[1] % 2 == 0 &&
+          c->g.nvox >= (1LL << 21)))
+      return false;
+  return true;
 }
 
 dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_t* stress_masks, int32_t n_increments,
@@ -2213,6 +2231,19 @@ dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_
   if (!B.cells[0]->linear_material()) {
     if (n_increments < 1) DB_THROW(DBFFT_EINVAL, "n_increments must be >= 1");
     if (B.cells[0]->mat == DBFFT_MAT_J2VP_CUBIC && !(dt > 0.0)) DB_THROW(DBFFT_EINVAL, "dt must be > 0");
+  }
+  if (solve_cellwise(B, o)) {
+    // cells that each fill the GPU with the fused single-cell iteration
+    int worst = DBFFT_OK;
+    for (int r = 0; r < n; ++r) {
+      const dbfft_status s = dbfft_solve(B.handles[r], loads + 9 * r, stress_masks + 9 * r, n_increments, dt, &o,
+                                         &infos[r]);
+      if (s != DBFFT_OK) {
+        if (s != DBFFT_ENOTCONV && s != DBFFT_EBREAKDOWN) return s;
+        worst = s;
+      }
+    }
+    return (dbfft_status)worst;
   }
   std::vector<int> st = (B.prec == DBFFT_FP64) ? batch_solve_t<double>(B, loads, stress_masks, n_increments, dt, o, infos)
                                                : batch_solve_t<float>(B, loads, stress_masks, n_increments, dt, o, infos);

@@ -932,7 +932,7 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
             energy += (double)(ev[0] * sv[0] + ev[1] * sv[1] + ev[2] * sv[2]) +
                       2.0 * (double)(ev[3] * sv[3] + ev[4] * sv[4] + ev[5] * sv[5]);
           } else {
-            tangent_finite<T>(tn, vox, g.nvox, ev, sv);
+            tangent_finite<T, ISO>(tn, vox, g.nvox, ev, sv);
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < 9; ++c) acc += (double)(ev[c] * sv[c]);
@@ -981,8 +981,12 @@ static void launch_line_fast_m(int kin, const void* in, void* out, const Geom& g
     DB_LAUNCH((k_line_fast<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else
-    DB_LAUNCH((k_line_fast<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
-                       partials, stop);
+    if (finite_law(tan.kind) == 2)
+      DB_LAUNCH((k_line_fast<T, M, KIN_FINITE, 2>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+                         partials, stop);
+    else
+      DB_LAUNCH((k_line_fast<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+                         partials, stop);
 }
 
 template <typename T>

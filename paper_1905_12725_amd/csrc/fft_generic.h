@@ -334,15 +334,20 @@ __device__ __forceinline__ void tangent_svk(const TangentArgs<T>& tn, long long 
     }
 }
 
-// finite-strain tangent of the context's law applied to H
-template <typename T>
+// finite-strain tangent applied to H; LAW (a template parameter, so each
+// kernel holds the registers of one law only): 2 Saint Venant-Kirchhoff,
+// otherwise neo-Hookean
+template <typename T, int LAW>
 __device__ __forceinline__ void tangent_finite(const TangentArgs<T>& tn, long long vox, long long nvox, const T* H,
                                                T* P) {
-  if (tn.kind == TAN_SVK_FIELD) tangent_svk<T>(tn, vox, nvox, H, P);
+  if constexpr (LAW == 2) tangent_svk<T>(tn, vox, nvox, H, P);
   else tangent_neo<T>(tn, vox, nvox, H, P);
 }
 
-template <typename T, int MODE, int KIN>
+// law selector of the finite-strain kernels for a tangent kind
+inline int finite_law(int tan_kind) { return tan_kind == TAN_SVK_FIELD ? 2 : 0; }
+
+template <typename T, int MODE, int KIN, int LAW = 0>
 __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const Geom& g, const FftPlan& plan,
                                           const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ rtwg,
                                           const TangentArgs<T>& tn, const double* __restrict__ macro_dev,
@@ -461,7 +466,7 @@ __device__ __forceinline__ void line_core(const void* in_v, void* out_v, const G
           energy += (double)(e[0] * sg[0] + e[1] * sg[1] + e[2] * sg[2]) +
                     2.0 * (double)(e[3] * sg[3] + e[4] * sg[4] + e[5] * sg[5]);
         } else {
-          tangent_finite<T>(tn, vox, g.nvox, e, sg);
+          tangent_finite<T, LAW>(tn, vox, g.nvox, e, sg);
           double acc = 0.0;
 #pragma unroll
           for (int c = 0; c < 9; ++c) acc += (double)(e[c] * sg[c]);

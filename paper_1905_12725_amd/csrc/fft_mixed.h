@@ -400,7 +400,7 @@ __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out
             energy += (double)(ev[0] * sv[0] + ev[1] * sv[1] + ev[2] * sv[2]) +
                       2.0 * (double)(ev[3] * sv[3] + ev[4] * sv[4] + ev[5] * sv[5]);
           } else {
-            tangent_finite<T>(tn, vox, g.nvox, ev, sv);
+            tangent_finite<T, ISO>(tn, vox, g.nvox, ev, sv);
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < 9; ++c) acc += (double)(ev[c] * sv[c]);

@@ -118,9 +118,12 @@ static void launch_line_mixed_m(int kin, bool iso, const void* in, void* out, co
     if (kin == KIN_SMALL)
       DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                          partials, stop);
+    else if (finite_law(tan.kind) == 2)
+      DB_LAUNCH((k_line_mixed<T, M, KIN_FINITE, 2>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+                partials, stop);
     else
-      DB_LAUNCH((k_line_mixed<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan,
-                         macro_dev, partials, stop);
+      DB_LAUNCH((k_line_mixed<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+                partials, stop);
   }
 }
 

@@ -88,7 +88,7 @@ template void launch_strided<float>(int, const void*, void*, int, const StridedG
 // done as a complex transform of length n3/2 on z[n] = f[2n] + i f[2n+1] with
 // the standard even/odd split before (C2R) or after (R2C); an odd n3 takes
 // the full-length complex transform of the real samples.
-template <typename T, int MODE, int KIN>
+template <typename T, int MODE, int KIN, int LAW>
 __global__ __launch_bounds__(kLineThreads) void k_line(const void* in_v, void* out_v, Geom g, FftPlan plan,
                                                        const cpx<T>* __restrict__ twg,
                                                        const cpx<T>* __restrict__ rtwg, TangentArgs<T> tn,
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line(const void* in_v, void* o
                                                        const int* __restrict__ stop) {
   if (stop != nullptr && *stop) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  line_core<T, MODE, KIN>(in_v, out_v, g, plan, twg, rtwg, tn, macro_dev, macro_add, partials, L, ncomp,
+  line_core<T, MODE, KIN, LAW>(in_v, out_v, g, plan, twg, rtwg, tn, macro_dev, macro_add, partials, L, ncomp,
                           (long long)blockIdx.x, smem_raw);
 }
 
@@ -135,24 +135,32 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
   const size_t shm = line_smem_bytes(g, L, ncomp, eb);
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
-#define DBFFT_LINE(MD, KN)                                                                                       \
-  DB_LAUNCH((k_line<T, MD, KN>), dim3(nblk), dim3(kLineThreads), shm, st, in, out, g, plan, t, r, tan, \
-                     macro_dev, macro_add, partials, L, ncomp, stop)
+#define DBFFT_LINE(MD, KN, LW)                                                                                   \
+  DB_LAUNCH((k_line<T, MD, KN, LW>), dim3(nblk), dim3(kLineThreads), shm, st, in, out, g, plan, t, r, tan,      \
+            macro_dev, macro_add, partials, L, ncomp, stop)
   if (kin == KIN_SMALL) {
     switch (mode) {
-      case LP_FUSED: DBFFT_LINE(LP_FUSED, KIN_SMALL); break;
-      case LP_C2R: DBFFT_LINE(LP_C2R, KIN_SMALL); break;
-      case LP_R2C: DBFFT_LINE(LP_R2C, KIN_SMALL); break;
-      case LP_STRESS: DBFFT_LINE(LP_STRESS, KIN_SMALL); break;
-      default: DBFFT_LINE(LP_CONST, KIN_SMALL); break;
+      case LP_FUSED: DBFFT_LINE(LP_FUSED, KIN_SMALL, 0); break;
+      case LP_C2R: DBFFT_LINE(LP_C2R, KIN_SMALL, 0); break;
+      case LP_R2C: DBFFT_LINE(LP_R2C, KIN_SMALL, 0); break;
+      case LP_STRESS: DBFFT_LINE(LP_STRESS, KIN_SMALL, 0); break;
+      default: DBFFT_LINE(LP_CONST, KIN_SMALL, 0); break;
+    }
+  } else if (finite_law(tan.kind) == 2) {
+    switch (mode) {
+      case LP_FUSED: DBFFT_LINE(LP_FUSED, KIN_FINITE, 2); break;
+      case LP_C2R: DBFFT_LINE(LP_C2R, KIN_FINITE, 2); break;
+      case LP_R2C: DBFFT_LINE(LP_R2C, KIN_FINITE, 2); break;
+      case LP_STRESS: DBFFT_LINE(LP_STRESS, KIN_FINITE, 2); break;
+      default: DBFFT_LINE(LP_CONST, KIN_FINITE, 2); break;
     }
   } else {
     switch (mode) {
-      case LP_FUSED: DBFFT_LINE(LP_FUSED, KIN_FINITE); break;
-      case LP_C2R: DBFFT_LINE(LP_C2R, KIN_FINITE); break;
-      case LP_R2C: DBFFT_LINE(LP_R2C, KIN_FINITE); break;
-      case LP_STRESS: DBFFT_LINE(LP_STRESS, KIN_FINITE); break;
-      default: DBFFT_LINE(LP_CONST, KIN_FINITE); break;
+      case LP_FUSED: DBFFT_LINE(LP_FUSED, KIN_FINITE, 0); break;
+      case LP_C2R: DBFFT_LINE(LP_C2R, KIN_FINITE, 0); break;
+      case LP_R2C: DBFFT_LINE(LP_R2C, KIN_FINITE, 0); break;
+      case LP_STRESS: DBFFT_LINE(LP_STRESS, KIN_FINITE, 0); break;
+      default: DBFFT_LINE(LP_CONST, KIN_FINITE, 0); break;
     }
   }
 #undef DBFFT_LINE

@@ -283,3 +283,25 @@ def test_batch_neohooke_smooth_sizes_fp32_vs_fp64_single(gpu):
         assert rel(infos[i]["sigma_bar"], refs[i]) < 1e-6, s
     for c in cells:
         c.close()
+
+
+def test_batch_of_large_cells_solves_cell_by_cell(gpu):
+    """Two 128^3 cells that take the fused single-cell iteration: the batch
+    solves them one after another with it, so each result equals the
+    cell's own solve bit for bit."""
+    import torch
+    from paper_1905_12725_amd.api import Batch, Cell
+    n = (128, 128, 128)
+    print("case batch of two 128^3 cells", flush=True)
+    phase, _, _ = ms.random_spheres(n, 2, 6.0, 10.0, 0.3)
+    params = [1.0, 0.3, 100.0, 0.3]
+    loads = [np.diag([1e-3, 0.0, 0.0]), np.array([[0.0, 1e-3, 0.0], [1e-3, 0.0, 0.0], [0.0, 0.0, 0.0]])]
+    cells = [Cell(n, "iso_phase", torch.from_numpy(phase), params) for _ in loads]
+    with Batch(cells) as b:
+        infos = b.solve(loads, None, tol=1e-8)
+        sols = [c.solution()[0].cpu().numpy() for c in cells]
+    for c, L, info, a in zip(cells, loads, infos, sols):
+        one = c.solve(L, tol=1e-8)
+        assert info["pcg_iters"] == one["pcg_iters"]
+        assert np.array_equal(a, c.solution()[0].cpu().numpy())
+        c.close()
