@@ -45,3 +45,50 @@ def test_default_opts_and_error_string_without_gpu():
     assert o.newton_tol == 1e-6
     lib = _native.lib()
     assert isinstance(lib.dbfft_last_error(), bytes)
+
+
+# -- argument validation: every case below is rejected before any HIP call,
+#    so it runs without a GPU (the header's stated error behaviour)
+
+def _setup(n, kin=0, prec=0, mat=0, field=1, params=(1.0, 0.3), out=True):
+    from paper_1905_12725_amd import _native
+    lib = _native.lib()
+    h = ctypes.c_void_p()
+    nn = (ctypes.c_int64 * 3)(*n)
+    pp = (ctypes.c_double * max(len(params), 1))(*params)
+    st = lib.dbfft_setup(ctypes.byref(h) if out else None, nn, kin, prec, mat,
+                         ctypes.c_void_p(field) if field else None, pp if params else None, len(params), None)
+    return st, lib.dbfft_last_error().decode()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdbfft.so not built")
+@pytest.mark.parametrize("kwargs,needle", [
+    (dict(n=(11, 8, 8)), "2^a 3^b 5^c 7^d"),
+    (dict(n=(8, 0, 8)), "2^a 3^b 5^c 7^d"),
+    (dict(n=(8, 8, 8), kin=1, mat=0), "FINITE"),
+    (dict(n=(8, 8, 8), kin=0, mat=5), "FINITE"),
+    (dict(n=(8, 8, 8), kin=0, mat=4), "FINITE"),
+    (dict(n=(8, 8, 8), mat=9), "unknown material"),
+    (dict(n=(8, 8, 8), kin=2), "kinematics"),
+    (dict(n=(8, 8, 8), prec=7), "precision"),
+    (dict(n=(8, 8, 8), field=0), "null material field"),
+    (dict(n=(8, 8, 8), params=()), "parameters"),
+    (dict(n=(8, 8, 8), out=False), "null output"),
+])
+def test_setup_rejects_invalid_arguments(kwargs, needle):
+    st, msg = _setup(**kwargs)
+    assert st == 1, (st, msg)  # DBFFT_EINVAL
+    assert needle in msg, msg
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdbfft.so not built")
+def test_null_handles_are_rejected():
+    from paper_1905_12725_amd import _native
+    lib = _native.lib()
+    load = (ctypes.c_double * 9)()
+    mask = (ctypes.c_uint8 * 9)()
+    info = _native.Info()
+    assert lib.dbfft_solve(None, load, mask, 1, 1.0, None, ctypes.byref(info)) == 1
+    assert lib.dbfft_batch_create(None, None, 0, 1) == 1
+    assert lib.dbfft_batch_solve(None, load, mask, 1, 1.0, None, ctypes.byref(info)) == 1
+    lib.dbfft_destroy(None)
