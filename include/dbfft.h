@@ -62,7 +62,7 @@ enum { DBFFT_FP64 = 0, DBFFT_FP32_MIXED = 1 };       /* precision */
  *  ISO_PHASE   field uint8 phase id; params (E, nu) per phase (<= 8 phases).
  *              Linear isotropic elasticity (Sec. 2.2, Sec. 3.1 material).
  *  ISO_FIELD   field double E(x); params (nu).  Linear isotropic with a
- *              per-voxel Young's modulus; the only kind dbfft_adjoint handles.
+ *              per-voxel Young's modulus; the linear kind dbfft_adjoint handles.
  *  ANISO_GRAIN field int32 grain id; params 36 doubles per grain: the 6x6
  *              stiffness in the orthonormal Mandel basis (11 22 33 √2·23
  *              √2·13 √2·12), row-major.  Linear anisotropic elasticity.
@@ -179,12 +179,21 @@ dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_ba
  * components (host 3x3 row-major); either may be NULL. */
 dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]);
 
-/* Adjoint gradient of J = G:<sigma> + H:<eps> at the last linear solve with
- * respect to the per-voxel Young's modulus (DBFFT_MAT_ISO_FIELD, small
- * strains).  A second PCG solve with the same operator and stress mask and
- * load (G on the strain-controlled, -H on the stress-controlled components)
- * gives eta; grad(x) = eta(x) : C1 : eps(x) / N with C1 the unit-modulus
- * stiffness.  G, H: host row-major 3x3.  grad_dev: device doubles [N].
+/* Adjoint gradient of J = G:<sigma> + H:<eps> at the end of the last solve.
+ *  ISO_FIELD (small strains, linear): with respect to the per-voxel Young's
+ *    modulus.  A second PCG solve with the same operator and stress mask and
+ *    load (G on the strain-controlled, -H on the stress-controlled
+ *    components) gives eta; grad(x) = eta(x) : C1 : eps(x) / N with C1 the
+ *    unit-modulus stiffness.
+ *  NEOHOOKE, SVK (finite strains, hyperelastic): J = G:<P> + H:<F> with
+ *    respect to a per-voxel factor theta(x) scaling the law's moduli, at
+ *    theta = 1.  The response at the end of the path depends on the final
+ *    state only, so the checkpoint is the final Newton state: its tangent K
+ *    is recomputed, eta solves the linearized cell problem K eta with the
+ *    same mask and load as above, and grad(x) = (G + grad eta)(x) : P(x) / N
+ *    (P is linear in the moduli).  G, H need not be symmetric.
+ * Other kinds (J2VP_CUBIC, path-dependent; ANISO_GRAIN; ISO_PHASE) return
+ * EUNSUPPORTED.  G, H: host row-major 3x3.  grad_dev: device doubles [N].
  * J_out (host, may be NULL) receives J. */
 dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out);
 

@@ -242,12 +242,14 @@ class LinearResult:
 
 
 def solve_linear(shape, tangent, load, stress_mask=None, tol=1e-8, tol_load=1e-10,
-                 max_iter=10000, x0=None, keep_history=False):
-    """Small-strain linear elastic DBFFT solve (Sec. 2.2 strain control,
-    Sec. 2.3 stress/mixed control).  `load` holds the prescribed strain on
-    strain-controlled components and the prescribed stress on the components
-    where stress_mask is true."""
-    space = Space(shape, SMALL, stress_mask)
+                 max_iter=10000, x0=None, keep_history=False, kin=SMALL):
+    """Linear DBFFT solve (Sec. 2.2 strain control, Sec. 2.3 stress/mixed
+    control): small-strain elasticity, or (kin=FINITE) the linearized
+    finite-strain problem with a fixed tangent K (the system of one Newton
+    step, Sec. 2.4).  `load` holds the prescribed strain (displacement
+    gradient) on strain-controlled components and the prescribed stress on
+    the components where stress_mask is true."""
+    space = Space(shape, kin, stress_mask)
     E_U, sbar = split_load(space, load)
     (ka, _), dc0 = space.apply(space.zeros(), tangent, E_U)
     b = (-ka, sbar - space.macro_row(dc0))
@@ -404,6 +406,33 @@ class NeoHookeLaw:
 # where eta solves the same DBFFT system with prescribed strain G on the
 # strain-controlled set and prescribed stress -H on S.
 # ---------------------------------------------------------------------------
+
+def adjoint_gradient_hyperelastic(shape, law, loads, stress_mask, G, H, tol=1e-12, newton_tol=1e-12):
+    """Hyperelastic finite-strain counterpart (not in the paper): J = G:<P> +
+    H:<F> at the end of the load path `loads` (as for newton()), and its
+    gradient with respect to a per-voxel factor theta(x) on the law's moduli
+    at theta = 1.  The end state does not depend on the path, so with the
+    tangent K of the final state the Lagrangian gives: eta solves the
+    linearized cell problem with prescribed gradient G on the controlled
+    components and stress -H on S, and dJ/dtheta(x) = (G + grad eta):dP/dtheta
+    / N with dP/dtheta = P (P linear in the moduli).
+    Returns (J, gradient field, newton info)."""
+    a, e, state, info = newton(shape, law, loads, stress_mask, kin=FINITE, tol=tol, tol_load=tol,
+                               newton_tol=newton_tol)
+    space = Space(shape, FINITE, stress_mask)
+    E_U, _ = split_load(space, loads[-1])
+    Hf = space.field_of(a, e, E_U)
+    P, K, _ = law.update(Hf, state)
+    mask = np.asarray(stress_mask if stress_mask is not None else np.zeros((3, 3)), bool)
+    G = np.asarray(G, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    adj = solve_linear(shape, K, np.where(mask, -H, G), stress_mask, tol, tol, kin=FINITE)
+    Hadj = adj.strain_field()
+    N = float(np.prod(shape))
+    g = np.einsum("ij...,ij...->...", Hadj, P) / N
+    J = float(np.sum(G * info.sigma_bar[-1]) + np.sum(H * (info.eps_bar[-1] + np.eye(3))))
+    return J, g, info
+
 
 def adjoint_gradient(shape, tangent, dtangent, load, stress_mask, G, H, tol=1e-12,
                      max_iter=10000):

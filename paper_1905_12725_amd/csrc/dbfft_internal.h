@@ -273,5 +273,8 @@ void launch_max_abs_diff(const double* a, const double* b, long long n, double* 
                          hipStream_t st);
 void launch_adjoint_density(const double* eps, const double* eta, double lam1, double mu1, long long nvox,
                             double* grad, double scale, hipStream_t st);
+// grad(x) = scale * sum_c A_c(x) B_c(x) (component-major [nc][nvox] fields)
+void launch_contract(const double* A, const double* B, int nc, long long nvox, double* grad, double scale,
+                     hipStream_t st);
 
 }  // namespace dbfft

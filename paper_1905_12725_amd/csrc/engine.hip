@@ -2294,17 +2294,30 @@ dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9],
   API_BEGIN
   if (!ctx || !G || !H || !grad_dev) DB_THROW(DBFFT_EINVAL, "null argument");
   Ctx& c = *C(ctx);
-  if (c.mat != DBFFT_MAT_ISO_FIELD || c.kin != KIN_SMALL)
-    DB_THROW(DBFFT_EUNSUPPORTED, "the adjoint handles ISO_FIELD materials under small strains");
+  const bool hyper = (c.mat == DBFFT_MAT_NEOHOOKE || c.mat == DBFFT_MAT_SVK) && c.kin == KIN_FINITE;
+  if (!hyper && (c.mat != DBFFT_MAT_ISO_FIELD || c.kin != KIN_SMALL))
+    DB_THROW(DBFFT_EUNSUPPORTED,
+             "the adjoint handles ISO_FIELD materials under small strains and NEOHOOKE / SVK under finite strains");
   if (!c.solved) DB_THROW(DBFFT_EINVAL, "no forward solution");
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      if (G[i * 3 + j] != G[j * 3 + i] || H[i * 3 + j] != H[j * 3 + i]) DB_THROW(DBFFT_EINVAL, "G and H must be symmetric");
+  if (!hyper)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (G[i * 3 + j] != G[j * 3 + i] || H[i * 3 + j] != H[j * 3 + i])
+          DB_THROW(DBFFT_EINVAL, "G and H must be symmetric");
   if (!c.sol2) c.sol2 = static_cast<double*>(dalloc(3 * (size_t)c.g.nh * 2 * sizeof(double)));
   dbfft_opts o;
   dbfft_default_opts(&o);
   o.tol = 1e-12;
   o.tol_load = 1e-12;
+  if (hyper) {
+    // the final state's nominal stress and tangent (hyperelastic: the
+    // response at the end of the path depends on that state only)
+    double mt[9];
+    for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+    set_macro(c, mt);
+    strain_field(c, c.sol, c.mac_dev, c.fa);
+    material_update(c, c.fa, c.fc, 1.0);
+  }
   const MacroSet ms = macro_set(c, c.last_mask);
   double Urm[9], Lrm[9];
   for (int i = 0; i < 9; ++i) {
@@ -2322,13 +2335,20 @@ dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9],
   for (int i = 0; i < 9; ++i) mt2[i] = EU2[i];
   for (int a = 0; a < ms.nS; ++a)
     for (int i = 0; i < 9; ++i) mt2[i] += lo.e_coef[a] * ms.bst[a][i];
-  double mt[9];
-  for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
-  set_macro(c, mt);
-  strain_field(c, c.sol, c.mac_dev, c.fa);
-  set_macro(c, mt2);
-  strain_field(c, c.sol2, c.mac_dev, c.fb);
-  launch_adjoint_density(c.fa, c.fb, c.lam1, c.mu1, c.g.nvox, grad_dev, c.g.inv_nvox, c.st);
+  if (hyper) {
+    // P is linear in the law's moduli: dP/dtheta = P at theta = 1
+    set_macro(c, mt2);
+    strain_field(c, c.sol2, c.mac_dev, c.fb);
+    launch_contract(c.fb, c.fc, 9, c.g.nvox, grad_dev, c.g.inv_nvox, c.st);
+  } else {
+    double mt[9];
+    for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+    set_macro(c, mt);
+    strain_field(c, c.sol, c.mac_dev, c.fa);
+    set_macro(c, mt2);
+    strain_field(c, c.sol2, c.mac_dev, c.fb);
+    launch_adjoint_density(c.fa, c.fb, c.lam1, c.mu1, c.g.nvox, grad_dev, c.g.inv_nvox, c.st);
+  }
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(c.st));
   if (J_out) {

@@ -428,4 +428,20 @@ void launch_adjoint_density(const double* eps, const double* eta, double lam1, d
   hipLaunchKernelGGL(k_adjoint_density, dim3(nb), dim3(kMatThreads), 0, st, eps, eta, lam1, mu1, nvox, grad, scale);
 }
 
+// g(x) = scale * sum_c A_c(x) B_c(x) over nc component-major fields
+__global__ __launch_bounds__(kMatThreads) void k_contract(const double* __restrict__ A, const double* __restrict__ B,
+                                                         int nc, long long nvox, double* __restrict__ grad,
+                                                         double scale) {
+  const long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x;
+  if (v >= nvox) return;
+  double acc = 0.0;
+  for (int c = 0; c < nc; ++c) acc += A[(long long)c * nvox + v] * B[(long long)c * nvox + v];
+  grad[v] = scale * acc;
+}
+void launch_contract(const double* A, const double* B, int nc, long long nvox, double* grad, double scale,
+                     hipStream_t st) {
+  const int nb = (int)((nvox + kMatThreads - 1) / kMatThreads);
+  hipLaunchKernelGGL(k_contract, dim3(nb), dim3(kMatThreads), 0, st, A, B, nc, nvox, grad, scale);
+}
+
 }  // namespace dbfft

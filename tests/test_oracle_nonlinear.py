@@ -341,3 +341,68 @@ def test_newton_svk_homogeneous_closed_form():
     e11 = 0.5 * (1.4 ** 2 - 1.0)
     expect = np.diag([1.4 * (lam + 2 * mu) * e11, lam * e11, lam * e11])
     assert np.allclose(info.sigma_bar[-1], expect, rtol=1e-14, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Hyperelastic adjoint (finite strains)
+# --------------------------------------------------------------------------
+
+def _hyper_law(kind, mu, lam):
+    return (so.SVKLaw if kind == "svk" else so.NeoHookeLaw)(mu, lam)
+
+
+@pytest.mark.parametrize("kind", ["svk", "neohooke"])
+def test_hyperelastic_adjoint_homogeneous_closed_form(kind):
+    """A homogeneous cell deforms uniformly, so the adjoint field has no
+    fluctuation and dJ/dtheta(x) = G:P / N at every voxel."""
+    shape = (4, 4, 4)
+    mu = np.full(shape, 1.3)
+    lam = np.full(shape, 2.0)
+    Fm = np.array([[1.2, 0.1, 0.0], [0.0, 0.95, 0.05], [0.02, 0.0, 1.05]])
+    G = np.zeros((3, 3)); G[0, 0] = 1.0; G[0, 1] = 0.5
+    J, g, info = so.adjoint_gradient_hyperelastic(shape, _hyper_law(kind, mu, lam), [Fm - np.eye(3)], None,
+                                                  G, np.zeros((3, 3)))
+    if kind == "svk":
+        P = mt.svk_stress(Fm, np.float64(1.3), np.float64(2.0))
+    else:
+        P = mt.neohooke_stress(Fm, np.float64(1.3), np.float64(2.0))
+    assert np.isclose(J, float(np.sum(G * P)), rtol=1e-12)
+    assert np.allclose(g, np.sum(G * P) / 64, rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("kind,control", [("svk", "strain"), ("neohooke", "strain"), ("svk", "mixed"),
+                                          ("neohooke", "mixed")])
+def test_hyperelastic_adjoint_finite_differences(kind, control):
+    """Gradient with respect to a per-voxel factor on both moduli against
+    central differences of full Newton solves."""
+    shape = (5, 4, 4)
+    rng = np.random.default_rng(21 if kind == "svk" else 22)
+    mu = np.exp(0.7 * rng.standard_normal(shape))
+    lam = 1.5 * mu
+    G = np.zeros((3, 3)); H = np.zeros((3, 3)); mask = None
+    if control == "strain":
+        loads = [np.diag([0.15, 0.0, -0.05]) * (k + 1) / 2 for k in range(2)]
+        loads = [L + np.array([[0, 0.05, 0], [0, 0, 0], [0, 0, 0]]) * (k + 1) / 2 for k, L in enumerate(loads)]
+        G[0, 0] = 1.0; G[0, 1] = 0.3; G[2, 2] = -0.4
+    else:
+        mask = np.array([[0, 0, 0], [1, 1, 0], [1, 1, 1]], dtype=bool)
+        loads = [np.diag([0.2 * (k + 1) / 2, 0.0, 0.0]) for k in range(2)]
+        G[0, 0] = 1.0; G[1, 2] = 0.5; H[1, 1] = 0.7; H[2, 0] = -0.3
+
+    def J_of(th):
+        law = _hyper_law(kind, mu * th, lam * th)
+        _, _, _, inf = so.newton(shape, law, loads, mask, kin=so.FINITE, tol=1e-13, tol_load=1e-13,
+                                 newton_tol=1e-13)
+        assert inf.converged
+        return float(np.sum(G * inf.sigma_bar[-1]) + np.sum(H * (inf.eps_bar[-1] + np.eye(3))))
+
+    J, g, info = so.adjoint_gradient_hyperelastic(shape, _hyper_law(kind, mu, lam), loads, mask, G, H,
+                                                  tol=1e-13, newton_tol=1e-13)
+    assert info.converged
+    assert np.isclose(J, J_of(np.ones(shape)), rtol=1e-11)
+    for idx in [(0, 0, 0), (3, 2, 1)]:
+        h = 1e-4
+        tp = np.ones(shape); tp[idx] += h
+        tm = np.ones(shape); tm[idx] -= h
+        fd = (J_of(tp) - J_of(tm)) / (2 * h)
+        assert np.isclose(g[idx], fd, rtol=1e-6, atol=1e-9 * abs(J)), (idx, g[idx], fd)
