@@ -108,6 +108,7 @@ def j2vp_return_map(eps, eps_p_n, C, s0, m, edot0, dt, elastic_cutoff=1e-12):
 
     eps, eps_p_n : (nv, 6) Mandel strains at t_{n+1} and plastic strain at t_n
     C            : (nv, 6, 6) Mandel elastic stiffness
+    s0           : flow stress, a scalar or one value per voxel (nv,)
     Returns sigma (nv, 6), dp (nv,), eps_p (nv, 6) and the consistent tangent
     (nv, 6, 6): [S + dp dn/dsigma + dp (m/s_eq) n n^T]^-1 with
     dn/dsigma = (3/(2 s_eq)) (P_dev - (2/3) n n^T).
@@ -117,6 +118,7 @@ def j2vp_return_map(eps, eps_p_n, C, s0, m, edot0, dt, elastic_cutoff=1e-12):
     """
     eps = np.asarray(eps, dtype=np.float64)
     nv = eps.shape[0]
+    s0v = np.broadcast_to(np.asarray(s0, dtype=np.float64), (nv,))
     S = np.linalg.inv(C)
     sig_tr = np.einsum("vab,vb->va", C, eps - eps_p_n)
     seq_tr, n_tr = _seq_and_n(sig_tr)
@@ -125,9 +127,10 @@ def j2vp_return_map(eps, eps_p_n, C, s0, m, edot0, dt, elastic_cutoff=1e-12):
     sig = sig_tr.copy()
     dp = np.zeros(nv)
     tangent = C.copy()
-    act = seq_tr > elastic_cutoff * s0
+    act = seq_tr > elastic_cutoff * s0v
     if not np.any(act):
         return sig, dp, eps_p_n.copy(), tangent
+    s0 = s0v[act]
 
     # Scalar starting value: s_eq ~ s_eq_tr - h dp with h = n_tr : C : n_tr,
     # dp = edot0 dt (s_eq/s0)^m, solved in y = ln dp by bracketed Newton.
@@ -168,7 +171,7 @@ def j2vp_return_map(eps, eps_p_n, C, s0, m, edot0, dt, elastic_cutoff=1e-12):
         d = np.linalg.solve(J, -R[..., None])[..., 0]
         sg = sg + d[:, :6]
         y = y + d[:, 6]
-        if np.max(np.abs(d[:, :6])) <= 1e-11 * s0 and np.max(np.abs(d[:, 6])) <= 1e-11:
+        if np.all(np.abs(d[:, :6]) <= 1e-11 * s0[:, None]) and np.max(np.abs(d[:, 6])) <= 1e-11:
             break
     seq, n = _seq_and_n(sg)
     dpa = np.exp(y)

@@ -289,7 +289,7 @@ class NewtonInfo:
 
 def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
            newton_tol=1e-6, max_newton=25, max_iter=10000, refresh="increment",
-           state=None):
+           state=None, checkpoints=None):
     """Incremental Newton-DBFFT driver.
 
     law.update(field, state) -> (stress, tangent_obj, new_state) where field
@@ -298,6 +298,8 @@ def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
     increment (strain / F - I on strain-controlled components, stress on S).
     refresh: 'increment' recomputes the preconditioner's mean tangent at the
     first Newton iteration of every increment (Sec. 2.5), 'initial' only once.
+    checkpoints: a list that receives, per increment, the converged (a, e,
+    E_U) and the law state the increment started from.
     Returns (a, e, state, info)."""
     space = Space(shape, kin, stress_mask)
     a, e = space.zeros()
@@ -331,6 +333,8 @@ def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
             fld = new_fld
             its += 1
         eq, _ = residual_norms(space, r, dc)
+        if checkpoints is not None:
+            checkpoints.append((a.copy(), e.copy(), E_U.copy(), state))
         state = new_state
         info.increments += 1
         info.newton_iters.append(its)
@@ -348,6 +352,7 @@ class J2Law:
     Mandel elastic stiffness C (n1, n2, n3, 6, 6)."""
 
     def __init__(self, C_mandel, s0, m, edot0, dt):
+        """s0 is a scalar or one flow stress per voxel (n1, n2, n3)."""
         self.C = np.asarray(C_mandel, dtype=np.float64)
         self.s0, self.m, self.edot0, self.dt = s0, m, edot0, dt
         self.shape = self.C.shape[:3]
@@ -361,8 +366,9 @@ class J2Law:
             state = self.initial_state()
         nv = int(np.prod(self.shape))
         ev = np.moveaxis(sym_to_mandel(eps), 0, -1).reshape(nv, 6)
+        s0 = np.broadcast_to(np.asarray(self.s0, dtype=np.float64), self.shape).reshape(nv)
         sig, dp, ep, tan = j2vp_return_map(ev, state.reshape(nv, 6), self.C.reshape(nv, 6, 6),
-                                           self.s0, self.m, self.edot0, self.dt)
+                                           s0, self.m, self.edot0, self.dt)
         sig_t = mandel_to_sym(np.moveaxis(sig.reshape(self.shape + (6,)), -1, 0))
         Ct = mandel_to_tensor4(tan.reshape(self.shape + (6, 6)))
         return sig_t, GeneralTangent(Ct), ep.reshape(self.shape + (6,))
@@ -432,6 +438,66 @@ def adjoint_gradient_hyperelastic(shape, law, loads, stress_mask, G, H, tol=1e-1
     g = np.einsum("ij...,ij...->...", Hadj, P) / N
     J = float(np.sum(G * info.sigma_bar[-1]) + np.sum(H * (info.eps_bar[-1] + np.eye(3))))
     return J, g, info
+
+
+def adjoint_gradient_j2(shape, law, loads, stress_mask, G, H, tol=1e-12, newton_tol=1e-12, max_iter=10000):
+    """J2 viscoplastic counterpart (not in the paper): J = G:<sigma> + H:<eps>
+    after the increments `loads` (as for newton(); the response depends on
+    the path), and its gradient with respect to a per-voxel factor theta(x)
+    on the flow stress s0 at theta = 1.
+
+    Per voxel and increment n the return map gives sigma_n from eps_n -
+    p_{n-1} (p the plastic strain, Mandel vectors) with the consistent
+    tangent K_n, and p_n = eps_n - S sigma_n (S the elastic compliance);
+    the flow increment dp_n scales as -m dp_n with theta.  Going back from
+    the last increment with lambda (the multiplier of p_n, zero after the
+    last increment):
+      A_n    = lambda - K_n S lambda                         (prestress)
+      eps*_n = adjoint field of the linearized cell problem with tangent K_n,
+               stress law K_n:eps + A_n, prescribed strain G on the
+               controlled components and stress -H on S at the last
+               increment, zero at the others
+      lambda <- K_n (S lambda - eps*_n)
+      grad  += -(m / N) dp_n . lambda
+    Returns (J, gradient field, newton info)."""
+    ck = []
+    a, e, state, info = newton(shape, law, loads, stress_mask, kin=SMALL, tol=tol, tol_load=tol,
+                               newton_tol=newton_tol, max_iter=max_iter, checkpoints=ck)
+    from .materials import j2vp_return_map
+    space = Space(shape, SMALL, stress_mask)
+    nv = int(np.prod(shape))
+    C = law.C.reshape(nv, 6, 6)
+    Sc = np.linalg.inv(C)
+    s0 = np.broadcast_to(np.asarray(law.s0, dtype=np.float64), shape).reshape(nv)
+    mask = np.asarray(stress_mask if stress_mask is not None else np.zeros((3, 3)), bool)
+    G = np.asarray(G, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    lam = np.zeros((nv, 6))
+    g = np.zeros(nv)
+    for n in reversed(range(len(loads))):
+        an, en, EUn, p_prev = ck[n]
+        p_prev = (law.initial_state() if p_prev is None else p_prev).reshape(nv, 6)
+        eps = space.field_of(an, en, EUn)
+        ev = np.moveaxis(sym_to_mandel(eps), 0, -1).reshape(nv, 6)
+        _, _, p_n, K = j2vp_return_map(ev, p_prev, C, s0, law.m, law.edot0, law.dt)
+        dp = p_n - p_prev
+        KSlam = np.einsum("vab,vb->va", K, np.einsum("vab,vb->va", Sc, lam))
+        A = lam - KSlam
+        load = np.where(mask, -H, G) if n == len(loads) - 1 else np.zeros((3, 3))
+        E_U, sbar = split_load(space, load)
+        tan = GeneralTangent(mandel_to_tensor4(K.reshape(tuple(shape) + (6, 6))))
+        sig0 = tan.stress(np.broadcast_to(E_U[:, :, None, None, None], (3, 3) + tuple(shape)))
+        sig0 = sig0 + mandel_to_sym(np.moveaxis(A.reshape(tuple(shape) + (6,)), -1, 0))
+        r_a, dc = space.divergence_residual(sig0)
+        d, _, pinfo = pcg(space, tan, space.preconditioner(tan.mean()), (r_a, sbar - space.macro_row(dc)), dc,
+                          tol, tol, max_iter)
+        if not pinfo.converged:
+            raise RuntimeError("adjoint solve did not converge")
+        es = np.moveaxis(sym_to_mandel(space.field_of(d[0], d[1], E_U)), 0, -1).reshape(nv, 6)
+        lam = KSlam - np.einsum("vab,vb->va", K, es)
+        g += -(law.m / nv) * np.sum(dp * lam, axis=1)
+    J = float(np.sum(G * info.sigma_bar[-1]) + np.sum(H * info.eps_bar[-1]))
+    return J, g.reshape(shape), info
 
 
 def adjoint_gradient(shape, tangent, dtangent, load, stress_mask, G, H, tol=1e-12,

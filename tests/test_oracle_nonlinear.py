@@ -406,3 +406,87 @@ def test_hyperelastic_adjoint_finite_differences(kind, control):
         tm = np.ones(shape); tm[idx] -= h
         fd = (J_of(tp) - J_of(tm)) / (2 * h)
         assert np.isclose(g[idx], fd, rtol=1e-6, atol=1e-9 * abs(J)), (idx, g[idx], fd)
+
+
+# --------------------------------------------------------------------------
+# J2 adjoint through the load path
+# --------------------------------------------------------------------------
+
+def _j2_case(control, shape=(4, 4, 3), ngrain=3, ninc=5):
+    grain, _ = ms.voronoi_grains(shape, ngrain, 41)
+    R = ms.random_rotations(ngrain, 42)
+    C = mt.tensor4_to_mandel(mt.rotate_tensor4(mt.cubic_tensor(168000.0, 121000.0, 75000.0), R))[grain]
+    dt = 0.5
+    G = np.zeros((3, 3)); H = np.zeros((3, 3))
+    if control == "mixed":
+        mask = np.ones((3, 3), bool); mask[0, 0] = False
+        final = np.zeros((3, 3)); final[0, 0] = 1e-3 * dt * ninc
+        G[0, 0] = 1.0; H[1, 1] = 3e4; H[0, 1] = H[1, 0] = -2e4
+    else:
+        mask = None
+        final = np.zeros((3, 3)); final[0, 0] = 1e-3 * dt * ninc; final[1, 2] = final[2, 1] = 4e-4 * dt * ninc
+        G[0, 0] = 1.0; G[1, 2] = G[2, 1] = 0.5; G[2, 2] = -0.3
+    loads = [final * (k + 1) / ninc for k in range(ninc)]
+    return C, dt, mask, loads, G, H
+
+
+def _j2_J(shape, C, s0, dt, loads, mask, G, H):
+    law = so.J2Law(C, s0, M, EDOT0, dt)
+    _, _, _, inf = so.newton(shape, law, loads, mask, tol=1e-13, tol_load=1e-13, newton_tol=1e-13)
+    assert inf.converged
+    return float(np.sum(G * inf.sigma_bar[-1]) + np.sum(H * inf.eps_bar[-1]))
+
+
+@pytest.mark.parametrize("control", ["mixed", "strain"])
+def test_j2_path_adjoint_finite_differences(control):
+    """Gradient with respect to a per-voxel factor on s0 against central
+    differences of the whole incremental Newton solve (the response depends
+    on the path: plastic strain carries over between increments)."""
+    shape = (4, 4, 3)
+    C, dt, mask, loads, G, H = _j2_case(control, shape)
+    J, g, info = so.adjoint_gradient_j2(shape, so.J2Law(C, S0, M, EDOT0, dt), loads, mask, G, H, tol=1e-13,
+                                        newton_tol=1e-13)
+    assert info.converged
+    assert np.isclose(J, _j2_J(shape, C, S0, dt, loads, mask, G, H), rtol=1e-11)
+    h = 1e-4
+    for idx in [(0, 0, 0), (2, 1, 2), (3, 3, 1)]:
+        tp = np.full(shape, S0); tp[idx] *= 1 + h
+        tm = np.full(shape, S0); tm[idx] *= 1 - h
+        fd = (_j2_J(shape, C, tp, dt, loads, mask, G, H) - _j2_J(shape, C, tm, dt, loads, mask, G, H)) / (2 * h)
+        assert np.isclose(g[idx], fd, rtol=1e-5, atol=1e-7 * abs(J)), (idx, g[idx], fd)
+
+
+def test_j2_path_adjoint_sum_is_uniform_scaling():
+    """Summed over the voxels the gradient is the derivative with respect to
+    one factor on s0 everywhere."""
+    shape = (4, 4, 3)
+    C, dt, mask, loads, G, H = _j2_case("mixed", shape)
+    J, g, _ = so.adjoint_gradient_j2(shape, so.J2Law(C, S0, M, EDOT0, dt), loads, mask, G, H, tol=1e-13,
+                                     newton_tol=1e-13)
+    h = 1e-4
+    fd = (_j2_J(shape, C, S0 * (1 + h), dt, loads, mask, G, H) -
+          _j2_J(shape, C, S0 * (1 - h), dt, loads, mask, G, H)) / (2 * h)
+    assert np.isclose(np.sum(g), fd, rtol=1e-6)
+
+
+def test_j2_path_adjoint_single_increment_single_crystal():
+    """One grain, one increment: the cell deforms uniformly, so the gradient
+    is uniform and equals the 0-D material point's derivative over N."""
+    shape = (3, 3, 3)
+    R = ms.random_rotations(1, 43)
+    C1 = mt.tensor4_to_mandel(mt.rotate_tensor4(mt.cubic_tensor(168000.0, 121000.0, 75000.0), R))[0]
+    C = np.broadcast_to(C1, shape + (6, 6))
+    dt = 2.0
+    ev = np.array([2e-3, -5e-4, 3e-4, 1e-3, 0.0, 7e-4])
+    E = mt.mandel_to_sym(ev)
+    G = np.array([[1.0, 0.2, 0.0], [0.2, 0.0, 0.0], [0.0, 0.0, 0.5]])
+    J, g, _ = so.adjoint_gradient_j2(shape, so.J2Law(C, S0, M, EDOT0, dt), [E], None, G, np.zeros((3, 3)))
+
+    def point(s0):
+        sig, _, _, _ = mt.j2vp_return_map(ev[None], np.zeros((1, 6)), C1[None], s0, M, EDOT0, dt)
+        return float(np.sum(G * mt.mandel_to_sym(sig[0])))
+
+    h = 1e-5
+    d = (point(S0 * (1 + h)) - point(S0 * (1 - h))) / (2 * h)
+    assert np.isclose(J, point(S0), rtol=1e-12)
+    assert np.allclose(g, d / 27, rtol=1e-7)
