@@ -105,6 +105,11 @@ typedef struct {
                           iterations captures one chunk as a HIP graph (on a private stream) and
                           replays it on the context's stream; 0: every chunk launched eagerly.
                           Same launches, same results; 1 */
+  int32_t checkpoint;  /* J2VP_CUBIC: 1 keeps, per increment, the converged solution and the
+                          plastic strain the increment started from (device memory of
+                          24 N + 48 N bytes per increment, held by the context until the next
+                          solve) for dbfft_adjoint; single-cell solves only (a batch keeps
+                          none); 0 */
 } dbfft_opts;
 
 typedef struct {
@@ -192,9 +197,24 @@ dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]);
  *    is recomputed, eta solves the linearized cell problem K eta with the
  *    same mask and load as above, and grad(x) = (G + grad eta)(x) : P(x) / N
  *    (P is linear in the moduli).  G, H need not be symmetric.
- * Other kinds (J2VP_CUBIC, path-dependent; ANISO_GRAIN; ISO_PHASE) return
- * EUNSUPPORTED.  G, H: host row-major 3x3.  grad_dev: device doubles [N].
- * J_out (host, may be NULL) receives J. */
+ *  J2VP_CUBIC (small strains, path-dependent): with respect to a per-voxel
+ *    factor theta(x) on the flow stress s0, at theta = 1, through every
+ *    increment of the last solve, which must have run with
+ *    opts.checkpoint = 1 (EINVAL otherwise).  Backwards over the
+ *    increments n, with the plastic-strain multiplier lambda (zero after the
+ *    last increment): the return map at the checkpointed state gives the
+ *    consistent tangent K_n and the flow increment dp_n; eta_n solves the
+ *    linearized cell problem with stress law K_n : eps + lambda -
+ *    K_n S lambda (S the grain's elastic compliance), load as above at the
+ *    last increment and zero before it; then lambda <- K_n (S lambda -
+ *    eps*_n) with eps*_n the adjoint strain, and grad(x) += -m dp_n(x) .
+ *    lambda(x) / N.  G, H symmetric.  Every component stress-controlled is
+ *    EUNSUPPORTED (the intermediate adjoint problems then have a zero mean
+ *    stress, the scale of the residual test).  The context's state is left
+ *    as the solve left it.
+ * Other kinds (ANISO_GRAIN, ISO_PHASE) return EUNSUPPORTED.  G, H: host
+ * row-major 3x3.  grad_dev: device doubles [N].  J_out (host, may be NULL)
+ * receives J. */
 dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out);
 
 /* Per-kernel timing of PCG iterations with HIP events (only iterations

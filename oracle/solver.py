@@ -161,8 +161,10 @@ class PCGInfo:
     history: list = field(default_factory=list)
 
 
-def residual_norms(space, r, sig):
-    nrm = float(np.linalg.norm(sig))
+def residual_norms(space, r, sig, scale=None):
+    """Equilibrium and loading residuals relative to ||<sigma>|| (Sec. 3),
+    or to a fixed `scale` when one is given."""
+    nrm = float(np.linalg.norm(sig)) if scale is None else float(scale)
     ra = np.sqrt(max(sp.inner(r[0], r[0], space.w), 0.0))
     re = float(np.linalg.norm(r[1]))
     if nrm == 0.0:
@@ -171,14 +173,15 @@ def residual_norms(space, r, sig):
 
 
 def pcg(space, tangent, precond, b, sig0, tol=1e-8, tol_load=1e-10, max_iter=10000,
-        x0=None, keep_history=False):
+        x0=None, keep_history=False, scale=None):
     """Preconditioned conjugate gradient on K{a|e} = b (Sec. 3 intro: CG for
     complex numbers with the preconditioner of eqs. pred2/pred3).
 
     sig0 is <sigma> of the field that produced b; the average stress of the
     current iterate is tracked as sig0 + <sigma>(K x).  Stops when the
     equilibrium residual is below tol and the loading residual below
-    tol_load (checked before the first iteration too)."""
+    tol_load (checked before the first iteration too).  `scale` replaces
+    ||<sigma>|| in both tests when given."""
     info = PCGInfo()
     if x0 is None:
         x = space.zeros()
@@ -193,7 +196,7 @@ def pcg(space, tangent, precond, b, sig0, tol=1e-8, tol_load=1e-10, max_iter=100
     p = (z[0].copy(), z[1].copy())
     rz = space.dot(r, z)
     while True:
-        eq, ld = residual_norms(space, r, sig)
+        eq, ld = residual_norms(space, r, sig, scale)
         info.eq_res, info.load_res = eq, ld
         if keep_history:
             info.history.append(eq)
@@ -456,7 +459,8 @@ def adjoint_gradient_j2(shape, law, loads, stress_mask, G, H, tol=1e-12, newton_
       eps*_n = adjoint field of the linearized cell problem with tangent K_n,
                stress law K_n:eps + A_n, prescribed strain G on the
                controlled components and stress -H on S at the last
-               increment, zero at the others
+               increment, zero at the others (PCG stopped on the residual
+               relative to its initial value)
       lambda <- K_n (S lambda - eps*_n)
       grad  += -(m / N) dp_n . lambda
     Returns (J, gradient field, newton info)."""
@@ -489,10 +493,16 @@ def adjoint_gradient_j2(shape, law, loads, stress_mask, G, H, tol=1e-12, newton_
         sig0 = tan.stress(np.broadcast_to(E_U[:, :, None, None, None], (3, 3) + tuple(shape)))
         sig0 = sig0 + mandel_to_sym(np.moveaxis(A.reshape(tuple(shape) + (6,)), -1, 0))
         r_a, dc = space.divergence_residual(sig0)
-        d, _, pinfo = pcg(space, tan, space.preconditioner(tan.mean()), (r_a, sbar - space.macro_row(dc)), dc,
-                          tol, tol, max_iter)
-        if not pinfo.converged:
-            raise RuntimeError("adjoint solve did not converge")
+        r = (r_a, sbar - space.macro_row(dc))
+        # residual test relative to the initial residual: the mean stress of
+        # these problems changes sign along the path
+        scale = np.sqrt(max(sp.inner(r[0], r[0], space.w), 0.0) + float(np.sum(r[1] ** 2)))
+        if scale > 0.0:
+            d, _, pinfo = pcg(space, tan, space.preconditioner(tan.mean()), r, dc, tol, tol, max_iter, scale=scale)
+            if not pinfo.converged:
+                raise RuntimeError("adjoint solve did not converge")
+        else:
+            d = space.zeros()
         es = np.moveaxis(sym_to_mandel(space.field_of(d[0], d[1], E_U)), 0, -1).reshape(nv, 6)
         lam = KSlam - np.einsum("vab,vb->va", K, es)
         g += -(law.m / nv) * np.sum(dp * lam, axis=1)

@@ -47,6 +47,7 @@ class Opts(ct.Structure):
         ("check_every", ct.c_int32),
         ("fused_cg", ct.c_int32),
         ("graph", ct.c_int32),
+        ("checkpoint", ct.c_int32),
     ]
 
 

@@ -113,6 +113,7 @@ struct PcgConst {
   int ncomp;                          // 6 or 9
   double Me[kMaxMacro][kMaxMacro];    // macro preconditioner
   double basis[kMaxMacro][9];         // B_a as row-major 3x3 (stress-controlled set only)
+  double scale;                       // > 0: fixed scale of the residual test; 0: ||<sigma>||
 };
 
 // ---------------------------------------------------------------- launchers
@@ -273,6 +274,15 @@ void launch_max_abs_diff(const double* a, const double* b, long long n, double* 
                          hipStream_t st);
 void launch_adjoint_density(const double* eps, const double* eta, double lam1, double mu1, long long nvox,
                             double* grad, double scale, hipStream_t st);
+// J2 adjoint, one increment (Mandel vectors; K from the 21-term upper
+// triangle, S the grain's compliance [ngrain][36]):
+//  prestress: sig0 = K : EU + lam - K S lam, written in stored tensor order
+//  back:      lam <- K (S lam - eps*), grad += scale * (p_new - p_old) . lam
+void launch_j2_adj_prestress(const double* lam, const double* tan21, const int32_t* grain, const double* grain_S,
+                             const double EU_st[6], long long nvox, double* sig0, hipStream_t st);
+void launch_j2_adj_back(double* lam, const double* tan21, const int32_t* grain, const double* grain_S,
+                        const double* eps_star, const double* p_new, const double* p_old, double scale, long long nvox,
+                        double* grad, hipStream_t st);
 // grad(x) = scale * sum_c A_c(x) B_c(x) (component-major [nc][nvox] fields)
 void launch_contract(const double* A, const double* B, int nc, long long nvox, double* grad, double scale,
                      hipStream_t st);

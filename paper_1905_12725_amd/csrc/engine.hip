@@ -198,6 +198,16 @@ struct Ctx {
   hipGraphExec_t chunk_exec = nullptr;
   std::vector<unsigned char> chunk_key;
 
+  // J2 checkpoints of the last solve (opts.checkpoint): per increment k,
+  // the converged coefficients (3 x nh complex) followed by the plastic
+  // strain the increment started from (6 x N), and the macro total
+  double* ck_buf = nullptr;
+  int ck_cap = 0;  // increments ck_buf holds
+  int ck_n = 0;    // increments recorded by the last solve
+  double ck_dt = 1.0;
+  std::vector<std::array<double, 9>> ck_mt;
+  double* adj_lam = nullptr;  // J2 adjoint multiplier (Mandel) 6 x N
+
   // solution state
   bool solved = false;
   int last_mask[9] = {0};
@@ -792,8 +802,12 @@ static int pcg_status(int s) {
 
 // Solves the linear problem with prescribed strain EU (stored) and stress
 // row sbar (over the macro set) into sol_out (FP64 coefficients).
-static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const double sbar[kMaxMacro],
-                           const dbfft_opts& o, double* sol_out) {
+// PCG solve of K [x; e] = [c.b; re0] with the current tangent: c.b holds
+// the FP64 right-hand side, dc0 the <sigma> of the field that produced it.
+// FP64 directly; FP32_MIXED as FP32 inner solves with FP64 corrections.
+// scale > 0 replaces ||<sigma>|| in the residual test.
+static LinOut linear_solve_b(Ctx& c, const MacroSet& ms, const double dc0[9], const double re0[kMaxMacro],
+                             const dbfft_opts& o, double* sol_out, double scale = 0.0) {
   LinOut out;
   double C4[81];
   mean_tangent(c, C4);
@@ -804,17 +818,9 @@ static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const
   pc.tol = o.tol;
   pc.tol_load = o.tol_load;
   pc.max_iter = o.max_iter;
+  pc.scale = scale;
   const size_t v64 = 3 * (size_t)c.g.nh * 2 * sizeof(double);
-
-  // right-hand side in FP64: b = -K[0; EU], b_e = sbar - B:<C:EU>
   TangentArgs<double> tan64 = elastic_tangent<double>(c);
-  set_macro(c, EU);
-  apply_const<double>(c, c.b, c.mac_dev, tan64, c.dc_dev);
-  launch_axpby<double>(c.b, c.b, 0.0, -1.0, 6 * c.g.nh, c.st);
-  double dc0[9];
-  read_dc(c, dc0);
-  double re0[kMaxMacro] = {0};
-  for (int a = 0; a < ms.nS; ++a) re0[a] = sbar[a] - bdot(c.kin, ms.bst[a], dc0);
 
   if (c.prec == DBFFT_FP64) {
     HIPCK(hipMemcpyAsync(c.r, c.b, v64, hipMemcpyDeviceToDevice, c.st));
@@ -851,7 +857,7 @@ static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const
       for (int i = 0; i < 9; ++i) sig[i] = dc0[i] + dcx[i];
       for (int a = 0; a < ms.nS; ++a) re[a] = re0[a] - bdot(c.kin, ms.bst[a], dcx);
     }
-    const double nrm = frob_stored(c.kin, sig);
+    const double nrm = scale > 0.0 ? scale : frob_stored(c.kin, sig);
     const double ra = std::sqrt(std::max(dot64(c, r64, r64), 0.0));
     double rl = 0.0;
     for (int a = 0; a < ms.nS; ++a) rl += re[a] * re[a];
@@ -888,6 +894,21 @@ static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const
     for (int a = 0; a < ms.nS; ++a) e[a] += po.xe[a];
   }
   return out;
+}
+
+// linear cell problem with prescribed strain EU and stress sbar on S
+static LinOut linear_solve(Ctx& c, const double EU[9], const MacroSet& ms, const double sbar[kMaxMacro],
+                           const dbfft_opts& o, double* sol_out) {
+  // right-hand side in FP64: b = -K[0; EU], b_e = sbar - B:<C:EU>
+  TangentArgs<double> tan64 = elastic_tangent<double>(c);
+  set_macro(c, EU);
+  apply_const<double>(c, c.b, c.mac_dev, tan64, c.dc_dev);
+  launch_axpby<double>(c.b, c.b, 0.0, -1.0, 6 * c.g.nh, c.st);
+  double dc0[9];
+  read_dc(c, dc0);
+  double re0[kMaxMacro] = {0};
+  for (int a = 0; a < ms.nS; ++a) re0[a] = sbar[a] - bdot(c.kin, ms.bst[a], dc0);
+  return linear_solve_b(c, ms, dc0, re0, o, sol_out);
 }
 
 // true residuals and <sigma> of coefficients sol (FP64) with macro total mt (stored)
@@ -971,6 +992,9 @@ struct NewtonState {
   dbfft_info info;
 };
 
+// doubles per increment in the checkpoint buffer
+static size_t ck_stride(const Ctx& c) { return 6 * (size_t)c.g.nh + 6 * (size_t)c.g.nvox; }
+
 static void macro_total(const Ctx& c, const NewtonState& S, double mt[9]) {
   for (int i = 0; i < 9; ++i) mt[i] = S.EU[i];
   for (int a = 0; a < S.ms.nS; ++a)
@@ -992,6 +1016,19 @@ static void newton_init(Ctx& c, NewtonState& S, const double load_rm[9], const i
   std::memset(&S.info, 0, sizeof(S.info));
   HIPCK(hipMemsetAsync(c.sol, 0, 3 * (size_t)c.g.nh * 2 * sizeof(double), c.st));
   if (c.mat == DBFFT_MAT_J2VP_CUBIC) HIPCK(hipMemsetAsync(c.state, 0, 6 * c.g.nvox * sizeof(double), c.st));
+  c.ck_n = 0;
+  if (c.mat == DBFFT_MAT_J2VP_CUBIC && o.checkpoint) {
+    if (c.ck_cap < ninc) {
+      HIPCK(hipStreamSynchronize(c.st));
+      if (c.ck_buf) HIPCK(hipFree(c.ck_buf));
+      c.ck_buf = nullptr;
+      c.ck_cap = 0;
+      c.ck_buf = static_cast<double*>(dalloc((size_t)ninc * ck_stride(c) * sizeof(double)));
+      c.ck_cap = ninc;
+    }
+    c.ck_mt.assign(ninc, std::array<double, 9>{});
+    c.ck_dt = dt;
+  }
 }
 
 // prescribed parts of increment k, strain field of the current iterate
@@ -1084,6 +1121,14 @@ static void newton_apply_correction(Ctx& c, NewtonState& S, const PcgOut& po) {
 }
 
 static void newton_end_increment(Ctx& c, NewtonState& S) {
+  if (c.mat == DBFFT_MAT_J2VP_CUBIC && S.o.checkpoint) {
+    double* ck = c.ck_buf + (size_t)(S.k - 1) * ck_stride(c);
+    HIPCK(hipMemcpyAsync(ck, c.sol, 6 * (size_t)c.g.nh * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+    HIPCK(hipMemcpyAsync(ck + 6 * (size_t)c.g.nh, c.state, 6 * (size_t)c.g.nvox * sizeof(double),
+                         hipMemcpyDeviceToDevice, c.st));
+    macro_total(c, S, c.ck_mt[S.k - 1].data());
+    c.ck_n = S.k;
+  }
   if (c.mat == DBFFT_MAT_J2VP_CUBIC) std::swap(c.state, c.state_new);
   S.info.increments += 1;
 }
@@ -1168,7 +1213,8 @@ static void release(Ctx* c) {
   void* dev[] = {c->td.tw1, c->td.tw2, c->td.tw3, c->td.rtw, c->tf.tw1, c->tf.tw2, c->tf.tw3, c->tf.rtw,
                  c->phase, c->E64, c->E32, c->grain, c->grain21, c->grainC, c->grainS, c->W, c->x, c->r, c->p,
                  c->q, c->b, c->t64, c->sol, c->sol2, c->fa, c->fb, c->fc, c->state, c->state_new, c->tanf,
-                 c->tanf32, c->partA, c->partB, c->sc_dev, c->dc_dev, c->mac_dev, c->red_dev, c->fail_dev};
+                 c->tanf32, c->partA, c->partB, c->sc_dev, c->dc_dev, c->mac_dev, c->red_dev, c->fail_dev,
+                 c->ck_buf, c->adj_lam};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
@@ -1804,6 +1850,7 @@ static std::vector<int> batch_solve_t(Batch& B, const double* loads, const uint8
       stored_to_rm(c.kin, sig_st, c.sig_rm);
       stored_to_rm(c.kin, mt, c.eps_rm);
       c.solved = true;
+      c.ck_n = 0;
       dbfft_info& inf = infos[r];
       std::memset(&inf, 0, sizeof(inf));
       inf.pcg_iters = iters[r];
@@ -2218,6 +2265,7 @@ dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_
   dbfft_opts o;
   if (opts) o = *opts;
   else dbfft_default_opts(&o);
+  o.checkpoint = 0;  // batches keep no checkpoints
   for (int r = 0; r < n; ++r) {
     const Ctx& c = *B.cells[r];
     if (c.kin == KIN_SMALL)
@@ -2289,15 +2337,87 @@ dbfft_status dbfft_get_solution(dbfft_ctx* ctx, void* a_dev, double e_macro[9]) 
   API_END
 }
 
+// J2 adjoint through the checkpointed increments of the last solve (the
+// recursion is stated with dbfft_adjoint in the header)
+static void j2_adjoint(Ctx& c, const double G[9], const double H[9], double* grad_dev) {
+  bool all_stress = true;
+  for (int i = 0; i < 9; ++i) all_stress = all_stress && c.last_mask[i];
+  if (all_stress) DB_THROW(DBFFT_EUNSUPPORTED, "J2 adjoint with every component stress-controlled");
+  if (c.ck_n <= 0)
+    DB_THROW(DBFFT_EINVAL, "the J2 adjoint needs the checkpoints of the last solve (opts.checkpoint = 1)");
+  const long long N = c.g.nvox;
+  const size_t vs = 6 * (size_t)c.g.nh;
+  if (!c.adj_lam) c.adj_lam = static_cast<double*>(dalloc(6 * (size_t)N * sizeof(double)));
+  HIPCK(hipMemsetAsync(c.adj_lam, 0, 6 * (size_t)N * sizeof(double), c.st));
+  HIPCK(hipMemsetAsync(grad_dev, 0, (size_t)N * sizeof(double), c.st));
+  dbfft_opts o;
+  dbfft_default_opts(&o);
+  o.tol = 1e-12;
+  o.tol_load = 1e-12;
+  const MacroSet ms = macro_set(c, c.last_mask);
+  // converged strain of increment n and the plastic strain it started from;
+  // the return map there gives K_n (tanf), p_n (state_new) and sigma_n (fc)
+  auto restore = [&](int n) {
+    const double* ck = c.ck_buf + (size_t)n * ck_stride(c);
+    set_macro(c, c.ck_mt[n].data());
+    strain_field(c, ck, c.mac_dev, c.fa);
+    HIPCK(hipMemcpyAsync(c.state, ck + vs, 6 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+    material_update(c, c.fa, c.fc, c.ck_dt);
+  };
+  for (int n = c.ck_n - 1; n >= 0; --n) {
+    restore(n);
+    const bool last = n == c.ck_n - 1;
+    double Urm[9] = {0}, Lrm[9] = {0};
+    if (last)
+      for (int i = 0; i < 9; ++i) {
+        Urm[i] = c.last_mask[i] ? 0.0 : G[i];
+        Lrm[i] = c.last_mask[i] ? -H[i] : G[i];
+      }
+    double EU2[9], lst[9];
+    rm_to_stored(c.kin, Urm, EU2);
+    rm_to_stored(c.kin, Lrm, lst);
+    double sbar[kMaxMacro] = {0};
+    for (int a = 0; a < ms.nS; ++a) sbar[a] = bdot(c.kin, ms.bst[a], lst);
+    // residual of the affine stress law K_n : eps + A_n at eps = EU
+    launch_j2_adj_prestress(c.adj_lam, c.tanf, c.grain, c.grainS, EU2, N, c.fc, c.st);
+    stress_residual(c, c.fc, c.b, c.dc_dev);
+    double dc0[9];
+    read_dc(c, dc0);
+    double re0[kMaxMacro] = {0}, r2 = std::max(dot64(c, c.b, c.b), 0.0);
+    for (int a = 0; a < ms.nS; ++a) {
+      re0[a] = sbar[a] - bdot(c.kin, ms.bst[a], dc0);
+      r2 += re0[a] * re0[a];
+    }
+    // the residual test is relative to the initial residual: the mean
+    // stress of these problems changes sign along the path
+    LinOut lo = r2 > 0.0 ? linear_solve_b(c, ms, dc0, re0, o, c.sol2, std::sqrt(r2)) : LinOut{};
+    if (!(r2 > 0.0)) HIPCK(hipMemsetAsync(c.sol2, 0, 6 * (size_t)c.g.nh * sizeof(double), c.st));
+    if (lo.status != DBFFT_OK) DB_THROW(lo.status, "adjoint solve did not converge");
+    double mt2[9];
+    for (int i = 0; i < 9; ++i) mt2[i] = EU2[i];
+    for (int a = 0; a < ms.nS; ++a)
+      for (int i = 0; i < 9; ++i) mt2[i] += lo.e_coef[a] * ms.bst[a][i];
+    set_macro(c, mt2);
+    strain_field(c, c.sol2, c.mac_dev, c.fb);
+    launch_j2_adj_back(c.adj_lam, c.tanf, c.grain, c.grainS, c.fb, c.state_new, c.state, -c.j2_m / (double)N, N,
+                       grad_dev, c.st);
+  }
+  // the state, tangent and fields as the solve left them
+  restore(c.ck_n - 1);
+  std::swap(c.state, c.state_new);
+}
+
 dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9], double* grad_dev, double* J_out) {
   g_err.clear();
   API_BEGIN
   if (!ctx || !G || !H || !grad_dev) DB_THROW(DBFFT_EINVAL, "null argument");
   Ctx& c = *C(ctx);
   const bool hyper = (c.mat == DBFFT_MAT_NEOHOOKE || c.mat == DBFFT_MAT_SVK) && c.kin == KIN_FINITE;
-  if (!hyper && (c.mat != DBFFT_MAT_ISO_FIELD || c.kin != KIN_SMALL))
+  const bool j2 = c.mat == DBFFT_MAT_J2VP_CUBIC && c.kin == KIN_SMALL;
+  if (!hyper && !j2 && (c.mat != DBFFT_MAT_ISO_FIELD || c.kin != KIN_SMALL))
     DB_THROW(DBFFT_EUNSUPPORTED,
-             "the adjoint handles ISO_FIELD materials under small strains and NEOHOOKE / SVK under finite strains");
+             "the adjoint handles ISO_FIELD and J2VP_CUBIC materials under small strains and NEOHOOKE / SVK under "
+             "finite strains");
   if (!c.solved) DB_THROW(DBFFT_EINVAL, "no forward solution");
   if (!hyper)
     for (int i = 0; i < 3; ++i)
@@ -2305,6 +2425,18 @@ dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9],
         if (G[i * 3 + j] != G[j * 3 + i] || H[i * 3 + j] != H[j * 3 + i])
           DB_THROW(DBFFT_EINVAL, "G and H must be symmetric");
   if (!c.sol2) c.sol2 = static_cast<double*>(dalloc(3 * (size_t)c.g.nh * 2 * sizeof(double)));
+  auto objective = [&]() {
+    double J = 0.0;
+    for (int i = 0; i < 9; ++i) J += G[i] * c.sig_rm[i] + H[i] * c.eps_rm[i];
+    return J;
+  };
+  if (j2) {
+    j2_adjoint(c, G, H, grad_dev);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(c.st));
+    if (J_out) *J_out = objective();
+    return DBFFT_OK;
+  }
   dbfft_opts o;
   dbfft_default_opts(&o);
   o.tol = 1e-12;
@@ -2351,11 +2483,7 @@ dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9],
   }
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(c.st));
-  if (J_out) {
-    double J = 0.0;
-    for (int i = 0; i < 9; ++i) J += G[i] * c.sig_rm[i] + H[i] * c.eps_rm[i];
-    *J_out = J;
-  }
+  if (J_out) *J_out = objective();
   return DBFFT_OK;
   API_END
 }

@@ -429,6 +429,102 @@ void launch_adjoint_density(const double* eps, const double* eta, double lam1, d
 }
 
 // g(x) = scale * sum_c A_c(x) B_c(x) over nc component-major fields
+// ------------------------------------------------------------------ J2 adjoint
+__device__ __forceinline__ void load_sym21(const double* __restrict__ t21, long long nvox, long long v,
+                                           double (*K)[6]) {
+  int idx = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b) {
+      const double x = t21[(long long)(idx++) * nvox + v];
+      K[a][b] = x;
+      K[b][a] = x;
+    }
+}
+
+__device__ __forceinline__ void matvec6(const double (*A)[6], const double* x, double* y) {
+  for (int a = 0; a < 6; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < 6; ++b) acc += A[a][b] * x[b];
+    y[a] = acc;
+  }
+}
+
+__device__ __forceinline__ void grain_matvec6(const double* __restrict__ M36, const double* x, double* y) {
+  for (int a = 0; a < 6; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < 6; ++b) acc += M36[a * 6 + b] * x[b];
+    y[a] = acc;
+  }
+}
+
+struct EU6 {
+  double v[6];
+};
+
+__global__ __launch_bounds__(kMatThreads) void k_j2_adj_prestress(const double* __restrict__ lam,
+                                                                 const double* __restrict__ tan21,
+                                                                 const int32_t* __restrict__ grain,
+                                                                 const double* __restrict__ gS, EU6 eu,
+                                                                 long long nvox, double* __restrict__ sig0) {
+  const long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x;
+  if (v >= nvox) return;
+  double K[6][6], l[6], sl[6], u[6], out[6];
+  load_sym21(tan21, nvox, v, K);
+  for (int a = 0; a < 6; ++a) l[a] = lam[(long long)a * nvox + v];
+  grain_matvec6(gS + (long long)grain[v] * 36, l, sl);
+  // u = EU - S lam, so K u + lam = K EU + lam - K S lam
+  for (int a = 0; a < 6; ++a) u[a] = ((a < 3) ? eu.v[a] : kR2 * eu.v[a]) - sl[a];
+  matvec6(K, u, out);
+  for (int a = 0; a < 6; ++a) {
+    const double m = out[a] + l[a];
+    sig0[(long long)a * nvox + v] = (a < 3) ? m : m / kR2;
+  }
+}
+
+void launch_j2_adj_prestress(const double* lam, const double* tan21, const int32_t* grain, const double* grain_S,
+                             const double EU_st[6], long long nvox, double* sig0, hipStream_t st) {
+  EU6 eu;
+  for (int a = 0; a < 6; ++a) eu.v[a] = EU_st[a];
+  const int nb = (int)((nvox + kMatThreads - 1) / kMatThreads);
+  hipLaunchKernelGGL(k_j2_adj_prestress, dim3(nb), dim3(kMatThreads), 0, st, lam, tan21, grain, grain_S, eu, nvox,
+                     sig0);
+}
+
+__global__ __launch_bounds__(kMatThreads) void k_j2_adj_back(double* __restrict__ lam,
+                                                            const double* __restrict__ tan21,
+                                                            const int32_t* __restrict__ grain,
+                                                            const double* __restrict__ gS,
+                                                            const double* __restrict__ eps_star,
+                                                            const double* __restrict__ p_new,
+                                                            const double* __restrict__ p_old, double scale,
+                                                            long long nvox, double* __restrict__ grad) {
+  const long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x;
+  if (v >= nvox) return;
+  double K[6][6], l[6], sl[6], u[6], ln[6];
+  load_sym21(tan21, nvox, v, K);
+  for (int a = 0; a < 6; ++a) l[a] = lam[(long long)a * nvox + v];
+  grain_matvec6(gS + (long long)grain[v] * 36, l, sl);
+  for (int a = 0; a < 6; ++a) {
+    const double e = eps_star[(long long)a * nvox + v];
+    u[a] = sl[a] - ((a < 3) ? e : kR2 * e);
+  }
+  matvec6(K, u, ln);
+  double acc = 0.0;
+  for (int a = 0; a < 6; ++a) {
+    acc += (p_new[(long long)a * nvox + v] - p_old[(long long)a * nvox + v]) * ln[a];
+    lam[(long long)a * nvox + v] = ln[a];
+  }
+  grad[v] += scale * acc;
+}
+
+void launch_j2_adj_back(double* lam, const double* tan21, const int32_t* grain, const double* grain_S,
+                        const double* eps_star, const double* p_new, const double* p_old, double scale, long long nvox,
+                        double* grad, hipStream_t st) {
+  const int nb = (int)((nvox + kMatThreads - 1) / kMatThreads);
+  hipLaunchKernelGGL(k_j2_adj_back, dim3(nb), dim3(kMatThreads), 0, st, lam, tan21, grain, grain_S, eps_star, p_new,
+                     p_old, scale, nvox, grad);
+}
+
 __global__ __launch_bounds__(kMatThreads) void k_contract(const double* __restrict__ A, const double* __restrict__ B,
                                                          int nc, long long nvox, double* __restrict__ grad,
                                                          double scale) {

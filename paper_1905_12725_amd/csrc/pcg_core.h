@@ -326,7 +326,7 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
   sc->rz = rz;
   sc->rr = rr;
   sc->re2 = re2;
-  const double nrm = frob_stored(sc->sig, pc.ncomp);
+  const double nrm = pc.scale > 0.0 ? pc.scale : frob_stored(sc->sig, pc.ncomp);
   const double ra = sqrt(rr > 0.0 ? rr : 0.0), rl = sqrt(re2);
   double eq, ld;
   if (nrm == 0.0) {
