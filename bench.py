@@ -396,7 +396,44 @@ def multi_rhs_leg(log, sizes=((64, 64, 64), (96, 96, 96), (128, 128, 128))):
                         "pcg_iters_sequential": int(it_seq),
                         "pcg_iters_batched": int(sum(i["pcg_iters"] for i in infos))}
             log(f"[bench] six cases {key}: sequential {t_seq * 1e3:.1f} ms, one batch {t_b * 1e3:.1f} ms")
+            if n[0] >= 128:
+                # two contexts on two streams, three cases each, from two
+                # host threads: do independent solves fill each other's gaps?
+                t_c = concurrent_cases(n, phase, params, prec, loads, nstream=2)
+                out[key]["two_streams_s"] = t_c
+                out[key]["two_streams_speedup"] = t_seq / t_c
+                log(f"[bench] six cases {key}: two streams {t_c * 1e3:.1f} ms")
     return out
+
+
+def concurrent_cases(n, phase, params, prec, loads, nstream):
+    """Wall time of the load cases split over `nstream` contexts, each on a
+    stream of its own driven by its own host thread (the library releases
+    the interpreter lock in every call)."""
+    import threading
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    streams = [torch.cuda.Stream() for _ in range(nstream)]
+    cells = [Cell(n, "iso_phase", torch.from_numpy(phase), params, precision=prec, stream=s) for s in streams]
+
+    def work(j):
+        for L in loads[j::nstream]:
+            cells[j].solve(L, tol=1e-8)
+
+    for c, L in zip(cells, loads):
+        c.solve(L, tol=1e-8)
+    torch.cuda.synchronize()
+    th = [threading.Thread(target=work, args=(j,)) for j in range(nstream)]
+    t = time.perf_counter()
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    for c in cells:
+        c.close()
+    return el
 
 
 def svk_porous_leg(log, n=(63, 63, 63), seed=6, ninc=5):

@@ -45,6 +45,21 @@ def test_default_opts_and_error_string_without_gpu():
     assert o.newton_tol == 1e-6
     lib = _native.lib()
     assert isinstance(lib.dbfft_last_error(), bytes)
+    assert o.fused_cg == 1 and o.graph == 1 and o.checkpoint == 0
+
+
+def test_opts_binding_has_the_header_layout():
+    """dbfft_default_opts clears the whole C struct before filling it: the
+    bytes it touches in a poisoned buffer give sizeof(dbfft_opts), which
+    must equal the ctypes mirror's size (a shorter mirror would be
+    overwritten past its end)."""
+    from paper_1905_12725_amd import _native
+    buf = (ctypes.c_ubyte * 512)(*([0xAB] * 512))
+    _native.lib().dbfft_default_opts(ctypes.cast(buf, ctypes.POINTER(_native.Opts)))
+    touched = max(i for i in range(512) if buf[i] != 0xAB) + 1
+    size = ctypes.sizeof(_native.Opts)
+    assert size - 8 < touched <= size
+    assert bytes(buf[size:]) == bytes([0xAB] * (512 - size))
 
 
 # -- argument validation: every case below is rejected before any HIP call,
