@@ -1,6 +1,6 @@
 """Fourier-space building blocks of DBFFT (oracle; test infrastructure only).
 
-Conventions (readings of the paper, listed in the design doc):
+Conventions (readings of the paper where it leaves a choice open):
   * unit cell, L_a = 1; voxel-centre sampling (Sec. 2.1);
   * xi_a = 2 pi m_a with m_a the signed DFT frequency of index k_a; on even
     grids the Nyquist index k_a = n_a/2 gets xi_a = 0 (Sec. 2.1 leaves even
