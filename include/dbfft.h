@@ -31,6 +31,10 @@
  * context's stream before returning).  The context owns its workspaces.
  * Errors: every entry point returns a dbfft_status; dbfft_last_error()
  * gives a message for the calling thread.  No C++ exception crosses the ABI.
+ * Threads: no state is shared between contexts, so calls on different
+ * contexts may run at the same time from different host threads; contexts
+ * created on different streams then overlap on the GPU.  A context (and a
+ * batch) takes one call at a time.
  */
 #ifndef DBFFT_H
 #define DBFFT_H

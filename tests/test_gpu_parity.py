@@ -321,3 +321,44 @@ def test_chunk_graph_matches_eager(gpu, n, prec):
         assert i1 == i0 and r1 == r0
         assert np.array_equal(a1, a0)
         assert i1 > 8
+
+
+def test_concurrent_contexts_match_sequential(gpu):
+    """Two contexts on two streams solving from two host threads at once give
+    bit-for-bit the results of one context solving the same cases in turn
+    (no state is shared between contexts; reductions have a fixed order)."""
+    import threading
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (64, 64, 64)
+    print("case concurrent contexts 64^3", flush=True)
+    phase, _, _ = ms.random_spheres(n, 2, 3.0, 5.0, 0.30)
+    params = [1.0, 0.3, 100.0, 0.3]
+    loads = []
+    for (i, j) in ((0, 0), (1, 1), (1, 2), (0, 1)):
+        L = np.zeros((3, 3)); L[i, j] = L[j, i] = 1e-3
+        loads.append(L)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), params) as one:
+        seq = [one.solve(L, tol=1e-10)["sigma_bar"] for L in loads]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    cells = [Cell(n, "iso_phase", torch.from_numpy(phase), params, stream=s) for s in streams]
+    got = [None] * len(loads)
+    errs = []
+
+    def work(j):
+        try:
+            for k in range(j, len(loads), 2):
+                got[k] = cells[j].solve(loads[k], tol=1e-10)["sigma_bar"]
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(j,)) for j in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for c in cells:
+        c.close()
+    assert not errs, errs
+    for a, b in zip(seq, got):
+        assert np.array_equal(a, b)
