@@ -239,18 +239,28 @@ __device__ __forceinline__ cpx<T> shfl_cx(cpx<T> v, int src) {
 }
 
 // inverse real transform of one component: coefficients src[0..M] of the
-// lane's line -> packed pairs at n = t + N1 k2 in e[k2] (t < N1)
-template <typename T, int M>
+// lane's line -> packed pairs at n = t + N1 k2 in e[k2] (t < N1).  NSUM > 1
+// transforms the sum of NSUM components `sstride` apart (the transform is
+// linear).
+template <typename T, int M, int NSUM = 1>
 __device__ __forceinline__ void mixed_line_inverse(const cpx<T>* src, bool valid, int t, int tj, int partner,
                                                    cpx<T>* lds, int off, const cpx<T>* tw, const cpx<T>* rtw,
-                                                   cpx<T>* e) {
+                                                   cpx<T>* e, long long sstride = 0) {
   using L = MixedLine<M>;
   constexpr int N1 = L::N1, N2 = L::N2, EM = L::EM;
   const bool lin = valid && t < N2;
   cpx<T> X[N1];
 #pragma unroll
-  for (int n1 = 0; n1 < N1; ++n1) X[n1] = lin ? src[N2 * n1 + t] : mk<T>(0, 0);
-  const cpx<T> XN = (valid && t == 0) ? src[M] : mk<T>(0, 0);
+  for (int n1 = 0; n1 < N1; ++n1) {
+    X[n1] = lin ? src[N2 * n1 + t] : mk<T>(0, 0);
+#pragma unroll
+    for (int s = 1; s < NSUM; ++s)
+      if (lin) X[n1] = add(X[n1], src[s * sstride + N2 * n1 + t]);
+  }
+  cpx<T> XN = (valid && t == 0) ? src[M] : mk<T>(0, 0);
+#pragma unroll
+  for (int s = 1; s < NSUM; ++s)
+    if (valid && t == 0) XN = add(XN, src[s * sstride + M]);
   cpx<T> Z[EM];
 #pragma unroll
   for (int n1 = 0; n1 < N1; ++n1) {
@@ -329,38 +339,19 @@ __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out
   const bool lt = valid && t < N1;
 
   if constexpr (ISO == 1) {
-    cpx<T> e[3][EM];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      mixed_line_inverse<T, M>(inl + c * g.nh, valid, t, tj, partner, lds, off, tw, rtw, e[c]);
-    if (lt) {
-#pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int n = t + N1 * k2;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const long long vox = gl * n3 + 2 * n + h;
-          T ev[6], sv[6];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) ev[c] = (h == 0 ? e[c][k2].x : e[c][k2].y) + (T)mac[c];
-          ev[3] = ev[4] = ev[5] = (T)0;
-          tangent_small<T>(tn, vox, ev, sv);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            energy += (double)(ev[c] * sv[c]);
-            if (h == 0) e[c][k2].x = sv[c];
-            else e[c][k2].y = sv[c];
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      mixed_line_forward<T, M>(outl + c * g.nh, valid, t, tj, partner, lds, off, tw, rtw, e[c], scale);
+    // The normal components couple only through the trace: one inverse
+    // transform of their summed coefficients gives tr(eps), and every
+    // component is then transformed, updated (lam tr + 2 mu eps_c, or
+    // 2 mu eps_c for shear) and written back on its own, so at most two
+    // components are in registers.
+    cpx<T> tr[EM];
+    mixed_line_inverse<T, M, 3>(inl, valid, t, tj, partner, lds, off, tw, rtw, tr, g.nh);
+    const T trmac = (T)(mac[0] + mac[1] + mac[2]);
 #pragma unroll 1
-    for (int c = 3; c < 6; ++c) {
+    for (int c = 0; c < 6; ++c) {
       cpx<T> e1[EM];
       mixed_line_inverse<T, M>(inl + c * g.nh, valid, t, tj, partner, lds, off, tw, rtw, e1);
+      const T mc = (T)mac[c];
       if (lt) {
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
@@ -368,12 +359,28 @@ __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const long long vox = gl * n3 + 2 * n + h;
-            T ev[6] = {0, 0, 0, 0, 0, 0}, sv[6];
-            ev[c] = (h == 0 ? e1[k2].x : e1[k2].y) + (T)mac[c];
-            tangent_small<T>(tn, vox, ev, sv);
-            energy += 2.0 * (double)(ev[c] * sv[c]);
-            if (h == 0) e1[k2].x = sv[c];
-            else e1[k2].y = sv[c];
+            T lam, mu;
+            if (tn.kind == TAN_ISO_PHASE) {
+              const int p = tn.phase[vox];
+              lam = (T)tn.lam[p];
+              mu = (T)tn.mu[p];
+            } else {
+              const T E = tn.field[vox];
+              lam = (T)tn.lam1 * E;
+              mu = (T)tn.mu1 * E;
+            }
+            const T ev = (h == 0 ? e1[k2].x : e1[k2].y) + mc;
+            T sv;
+            if (c < 3) {
+              const T trv = (h == 0 ? tr[k2].x : tr[k2].y) + trmac;
+              sv = lam * trv + (mu + mu) * ev;
+              energy += (double)(ev * sv);
+            } else {
+              sv = (mu + mu) * ev;
+              energy += 2.0 * (double)(ev * sv);
+            }
+            if (h == 0) e1[k2].x = sv;
+            else e1[k2].y = sv;
           }
         }
       }
