@@ -309,14 +309,15 @@ __device__ __forceinline__ void mixed_line_forward(cpx<T>* dst, bool valid, int 
 }
 
 // fused z pass of one wave (LB lines): inverse real transforms, tangent
-// (ISO: normal components together, shear components one at a time;
-// otherwise all components), energy, forward real transforms.  Returns the
-// wave's energy sum (1/N of sum eps : sigma) in every lane.
+// (ISO: one component at a time after the trace; otherwise all
+// components), energy, forward real transforms.  Returns the wave's energy
+// sum (1/N of sum eps : sigma) in every lane.  ISO only: part 0 does the
+// normal components, part 1 the shear ones, -1 all six.
 template <typename T, int M, int KIN, int ISO>
 __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out, const Geom& g,
                                                    const cpx<T>* tw, const cpx<T>* rtw, cpx<T>* lds,
                                                    const TangentArgs<T>& tn, const double* __restrict__ macro_dev,
-                                                   long long block, int lane) {
+                                                   long long block, int lane, int part = -1) {
   using L = MixedLine<M>;
   constexpr int N1 = L::N1, N2 = L::N2, EM = L::EM, TL = L::TL, LB = L::LB, PITCH = L::PITCH;
   constexpr int NC = (KIN == KIN_SMALL) ? 6 : 9;
@@ -345,10 +346,11 @@ __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out
     // 2 mu eps_c for shear) and written back on its own, so at most two
     // components are in registers.
     cpx<T> tr[EM];
-    mixed_line_inverse<T, M, 3>(inl, valid, t, tj, partner, lds, off, tw, rtw, tr, g.nh);
+    if (part != 1) mixed_line_inverse<T, M, 3>(inl, valid, t, tj, partner, lds, off, tw, rtw, tr, g.nh);
     const T trmac = (T)(mac[0] + mac[1] + mac[2]);
+    const int cbeg = (part == 1) ? 3 : 0, cend = (part == 0) ? 3 : 6;
 #pragma unroll 1
-    for (int c = 0; c < 6; ++c) {
+    for (int c = cbeg; c < cend; ++c) {
       cpx<T> e1[EM];
       mixed_line_inverse<T, M>(inl + c * g.nh, valid, t, tj, partner, lds, off, tw, rtw, e1);
       const T mc = (T)mac[c];

@@ -83,8 +83,10 @@ __global__ __launch_bounds__(64) void k_line_mixed(const cpx<T>* in, cpx<T>* out
   for (int i = threadIdx.x; i < M; i += 64) tw[i] = twg[i];
   for (int i = threadIdx.x; i <= M; i += 64) rtw[i] = rtwg[i];
   __syncthreads();
-  const double e = mixed_line_fused<T, M, KIN, ISO>(in, out, g, tw, rtw, lds, tn, macro_dev, blockIdx.x, threadIdx.x);
-  if (partials != nullptr && threadIdx.x == 0) partials[blockIdx.x] = e;
+  // isotropic: grid y splits the normal (0) and shear (1) components
+  const double e = mixed_line_fused<T, M, KIN, ISO>(in, out, g, tw, rtw, lds, tn, macro_dev, blockIdx.x, threadIdx.x,
+                                                    ISO ? (int)blockIdx.y : -1);
+  if (partials != nullptr && threadIdx.x == 0) partials[blockIdx.x + (long long)blockIdx.y * gridDim.x] = e;
 }
 
 static int mixed_lines_per_wave(int M) {
@@ -102,6 +104,8 @@ int mixed_line_blocks(const Geom& g) {
   return (int)(((long long)g.n1 * g.n2 + lb - 1) / lb);
 }
 
+int mixed_line_energy_blocks(const Geom& g, bool iso) { return mixed_line_blocks(g) * (iso ? 2 : 1); }
+
 template <typename T, int M>
 static void launch_line_mixed_m(int kin, bool iso, const void* in, void* out, const Geom& g, const void* tw,
                                 const void* rtw, const TangentArgs<T>& tan, const double* macro_dev, double* partials,
@@ -112,7 +116,7 @@ static void launch_line_mixed_m(int kin, bool iso, const void* in, void* out, co
   auto t = static_cast<const cpx<T>*>(tw);
   auto r = static_cast<const cpx<T>*>(rtw);
   if (iso)
-    DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 1>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 1>), dim3(nb, 2), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else if constexpr (sizeof(T) == 4) {
     if (kin == KIN_SMALL)
