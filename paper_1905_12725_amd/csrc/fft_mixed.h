@@ -39,11 +39,16 @@ struct MixedShape {
 // the line.  Inputs in the step-1 distribution (thread t < N2, register n1:
 // row N2 n1 + t), outputs in the step-2 one (thread t < N1, register k2:
 // row t + N1 k2).  `tw` is the N-point twiddle table in LDS, `lds` the
-// exchange buffer (N * PITCH elements).
-template <typename T, int N, int MODE>
+// exchange buffer (N * PITCH elements).  PARTS (SP_GRAD_SMALL, SP_DIV_SMALL
+// only): the small-strain gradient and divergence in three parts, so that
+// fewer vectors are live; `part` = i: the gradient writes the components
+// (i, i) and (i, i+1 mod 3) from a_i and a_(i+1), the divergence writes r_i
+// from the stress row i.  Without PARTS one call does everything.
+template <typename T, int N, int MODE, bool PARTS = false>
 __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out, const StridedGeom& sg,
                                                    const Geom& g, const cpx<T>* tw, cpx<T>* lds, T d,
-                                                   double* __restrict__ dc_out, long long tile, int tid) {
+                                                   double* __restrict__ dc_out, long long tile, int tid,
+                                                   int part = 0) {
   using S = MixedShape<N>;
   constexpr int N1 = S::N1, N2 = S::N2, EM = S::EM, TZ = S::TZ, PITCH = S::PITCH;
   const int s = tid % TZ, t = tid / TZ;
@@ -74,6 +79,32 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
   } else if constexpr (MODE == SP_GRAD_SMALL) {
     const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
     const long long co = sg.cstride_out;
+    if constexpr (PARTS) {
+      // components (i, i) and (i, j), j = i + 1 mod 3: stored 11 22 33 23 13 12
+      const int i = part, j = (part + 1) % 3;
+      const int cij = (i == 0) ? 5 : (i == 1 ? 3 : 4);
+      auto xa = [&](int a, T x1) { return a == 0 ? x1 : (a == 1 ? xi2 : xi3); };
+      cpx<T> Ai[N1], Aj[N1];
+      loadv(in + i * sg.cstride_in, Ai);
+      loadv(in + j * sg.cstride_in, Aj);
+      {
+        cpx<T> v[EM];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = muli(scl(Ai[n1], xa(i, (T)xi_of(N2 * n1 + t, g.n1))), (T)1);
+        fft(v);
+        storev(out + i * co, v);
+      }
+      {
+        cpx<T> v[EM];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+          const T x1 = (T)xi_of(N2 * n1 + t, g.n1);
+          v[n1] = muli(scl(add(scl(Ai[n1], xa(j, x1)), scl(Aj[n1], xa(i, x1))), (T)0.5), (T)1);
+        }
+        fft(v);
+        storev(out + cij * co, v);
+      }
+    } else {
     cpx<T> A0[N1], A1[N1], A2[N1];
     loadv(in, A0);
     loadv(in + sg.cstride_in, A1);
@@ -92,6 +123,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     emit(3, [&](int r, T) { return muli(scl(add(scl(A1[r], xi3), scl(A2[r], xi2)), (T)0.5), (T)1); });
     emit(4, [&](int r, T x1) { return muli(scl(add(scl(A0[r], xi3), scl(A2[r], x1)), (T)0.5), (T)1); });
     emit(5, [&](int r, T x1) { return muli(scl(add(scl(A0[r], xi2), scl(A1[r], x1)), (T)0.5), (T)1); });
+    }
   } else if constexpr (MODE == SP_GRAD_FINITE) {
     // T_i = FFT(a_i), U_i = FFT(xi1 a_i): H_i1 = i U_i, H_i2 = i xi2 T_i, H_i3 = i xi3 T_i
     const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
@@ -118,6 +150,38 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
   } else if constexpr (MODE == SP_DIV_SMALL) {
     // r_i = -i sum_j xi_j s_ij after the forward x transform
     const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
+    if constexpr (PARTS) {
+      // row i: s_i1, s_i2, s_i3 as stored components
+      const int i = part;
+      // stored index of (i, j): i for i = j, else 3 / 4 / 5 for the pairs summing to 3 / 2 / 1
+      auto comp = [&](int j) { return (i == j) ? i : 6 - (i + j); };
+      cpx<T> a[N2];
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) a[k2] = mk<T>(0, 0);
+      cpx<T> nx[N1];
+      loadv(in + comp(0) * sg.cstride_in, nx);
+#pragma unroll 1
+      for (int jj = 0; jj < 3; ++jj) {
+        const int c = comp(jj);
+        cpx<T> v[EM];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = nx[n1];
+        if (jj + 1 < 3) loadv(in + comp(jj + 1) * sg.cstride_in, nx);
+        fft(v);
+        // the row whose first index is the component's writes its mean
+        const int first = (c < 3) ? c : (c == 3 ? 1 : 0);
+        if (dc_out != nullptr && first == i && lout && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const T x1 = (T)xi_of(t + N1 * k2, g.n1);
+          const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
+          a[k2] = add(a[k2], scl(v[k2], xj));
+        }
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) a[k2] = muli(a[k2], (T)-1);
+      storev(out + i * sg.cstride_out, a);
+    } else {
     cpx<T> a0[N2], a1[N2], a2[N2];
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) a0[k2] = a1[k2] = a2[k2] = mk<T>(0, 0);
@@ -160,6 +224,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     storev(out, a0);
     storev(out + sg.cstride_out, a1);
     storev(out + 2 * sg.cstride_out, a2);
+    }
   } else {
     // SP_DIV_FINITE, row by row: r_i = -i (xi1 F[P_i1] + F[xi2 P_i2 + xi3 P_i3])
     const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);

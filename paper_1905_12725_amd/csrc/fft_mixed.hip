@@ -21,9 +21,12 @@ __global__ __launch_bounds__(MixedShape<N>::NT) void k_strided_mixed(const cpx<T
   const int per = nb >> 3;
   const int b = blockIdx.x;
   const int tile = (b < (per << 3)) ? (b & 7) * per + (b >> 3) : b;
-  const long long cz = blockIdx.z;
-  mixed_strided_tile<T, N, MODE>(in + cz * sg.cstride_in, out + cz * sg.cstride_out, sg, g, tw, lds, d, dc_out,
-                                 tile, threadIdx.x);
+  // plain: grid z is the component; small-strain gradient and divergence:
+  // grid z is the part (three)
+  constexpr bool parts = MODE == SP_GRAD_SMALL || MODE == SP_DIV_SMALL;
+  const long long cz = parts ? 0 : blockIdx.z;
+  mixed_strided_tile<T, N, MODE, parts>(in + cz * sg.cstride_in, out + cz * sg.cstride_out, sg, g, tw, lds, d,
+                                        dc_out, tile, threadIdx.x, (int)blockIdx.z);
 }
 
 bool mixed_strided_supported(int n) { return two_step_n1(n) != 0; }
@@ -34,7 +37,8 @@ static void launch_mixed_nm(const void* in, void* out, int ncomp_plain, const St
   using S = MixedShape<N>;
   const long long npair = (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
-  dim3 grid(ntiles, 1, MODE == SP_PLAIN ? ncomp_plain : 1);
+  const int nz = MODE == SP_PLAIN ? ncomp_plain : ((MODE == SP_GRAD_SMALL || MODE == SP_DIV_SMALL) ? 3 : 1);
+  dim3 grid(ntiles, 1, nz);
   DB_LAUNCH((k_strided_mixed<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
                      static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop);
 }
