@@ -2249,11 +2249,12 @@ dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int3
 // least 128^3 voxels solves the cells one after another with it: each pass
 // then already has a thousand or more blocks, and the batched passes (LDS
 // Stockham transforms, separate CG vector kernels) are slower there.
+// small-strain cells of 96^3 voxels and more: one after another with the
+// single-cell passes (measured faster than the batched ones from 96^3 up)
 static bool solve_cellwise(const Batch& B, const dbfft_opts& o) {
+  (void)o;
   for (const Ctx* c : B.cells)
-    if (!(o.fused_cg && c->kin == KIN_SMALL && fast_strided_supported(c->n[0]) && c->n[1] % 2 == 0 &&
-          c->g.nvox >= (1LL << 21)))
-      return false;
+    if (!(c->kin == KIN_SMALL && c->g.nvox >= 96LL * 96 * 96)) return false;
   return true;
 }
 
