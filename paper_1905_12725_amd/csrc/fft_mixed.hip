@@ -63,7 +63,7 @@ void launch_strided_mixed(int mode, const void* in, void* out, int ncomp_plain, 
   case NN: launch_mixed_n<T, NN>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
     DBFFT_MIX(12) DBFFT_MIX(15) DBFFT_MIX(18) DBFFT_MIX(20) DBFFT_MIX(24) DBFFT_MIX(25) DBFFT_MIX(27)
     DBFFT_MIX(30) DBFFT_MIX(36) DBFFT_MIX(40) DBFFT_MIX(45) DBFFT_MIX(48) DBFFT_MIX(50) DBFFT_MIX(54)
-    DBFFT_MIX(60) DBFFT_MIX(72) DBFFT_MIX(80) DBFFT_MIX(90) DBFFT_MIX(96)
+    DBFFT_MIX(60) DBFFT_MIX(63) DBFFT_MIX(72) DBFFT_MIX(80) DBFFT_MIX(90) DBFFT_MIX(96)
 #undef DBFFT_MIX
     default: break;
   }
@@ -143,7 +143,7 @@ void launch_line_mixed(int kin, bool iso, const void* in, void* out, const Geom&
 #define DBFFT_ZM(MM) \
   case MM: launch_line_mixed_m<T, MM>(kin, iso, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop); break;
     DBFFT_ZM(12) DBFFT_ZM(15) DBFFT_ZM(18) DBFFT_ZM(20) DBFFT_ZM(24) DBFFT_ZM(25) DBFFT_ZM(27) DBFFT_ZM(30)
-    DBFFT_ZM(36) DBFFT_ZM(40) DBFFT_ZM(45) DBFFT_ZM(48) DBFFT_ZM(50) DBFFT_ZM(54) DBFFT_ZM(60) DBFFT_ZM(72)
+    DBFFT_ZM(36) DBFFT_ZM(40) DBFFT_ZM(45) DBFFT_ZM(48) DBFFT_ZM(50) DBFFT_ZM(54) DBFFT_ZM(60) DBFFT_ZM(63) DBFFT_ZM(72)
     DBFFT_ZM(80) DBFFT_ZM(90) DBFFT_ZM(96)
 #undef DBFFT_ZM
     default: break;

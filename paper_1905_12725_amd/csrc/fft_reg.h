@@ -93,12 +93,12 @@ constexpr int reg_first_factor(int R) {
 }
 
 // R-point DFT of v in registers, exponent sign d (-1 forward, +1 inverse),
-// R a product of 2, 3 and 5 up to 16
+// R a product of 2, 3 and 5 up to 16, or 7
 template <typename T, int R>
 __device__ __forceinline__ void reg_dft(cpx<T>* v, T d) {
   if constexpr (R == 1) {
     return;
-  } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
+  } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5 || R == 7 || R == 8) {
     dftR<T, R>(v, d);
   } else {
     constexpr int A = reg_first_factor(R);
@@ -174,6 +174,7 @@ constexpr int two_step_n1(int n) {
     case 50: return 5;
     case 54: return 6;
     case 60: return 6;
+    case 63: return 7;
     case 72: return 8;
     case 80: return 8;
     case 90: return 9;
