@@ -168,6 +168,12 @@ bool fast_strided_supported(int n);
 // tangent in FP32
 bool mixed_line_supported(int n3, int elem_bytes, bool iso);
 int mixed_line_blocks(const Geom& g);
+// fused z pass of the odd length 63 (isotropic small strains), two parts
+bool odd_line_supported(int n3);
+int odd_line_energy_blocks(const Geom& g);
+template <typename T>
+void launch_line_odd(const void* in, void* out, const Geom& g, const void* tw, const TangentArgs<T>& tan,
+                     const double* macro_dev, double* partials, hipStream_t st, const int* stop);
 // energy partials of the two-step z pass (isotropic: two blocks per line group)
 int mixed_line_energy_blocks(const Geom& g, bool iso);
 template <typename T>

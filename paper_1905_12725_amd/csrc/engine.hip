@@ -1430,7 +1430,8 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
       HIPCK(hipMemcpy(c->tanf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
       launch_convert<double, float>(c->tanf32, c->tanf, 10 * N, c->st);
     }
-    const int zparts = mixed_line_supported(g.n3, 16, true) ? mixed_line_energy_blocks(g, true) : 0;
+    const int zparts = std::max(mixed_line_supported(g.n3, 16, true) ? mixed_line_energy_blocks(g, true) : 0,
+                                odd_line_supported(g.n3) ? odd_line_energy_blocks(g) : 0);
     const int nparts = std::max(std::max(std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
                                                   tangent_mean_block_count(g) * 81),
                                          fused_cg_partials(g)),

@@ -154,4 +154,175 @@ template void launch_line_mixed<double>(int, bool, const void*, void*, const Geo
 template void launch_line_mixed<float>(int, bool, const void*, void*, const Geom&, const void*, const void*,
                                        const TangentArgs<float>&, const double*, double*, hipStream_t, const int*);
 
+// ---------------------------------------------------------------- odd z pass
+// Fused z pass for an odd length N = n3 (two-step N1 x N2), isotropic
+// small-strain tangent.  A line's samples are real, so two components ride
+// in one complex transform (z_a + i z_b) and come apart by conjugate
+// symmetry on the way back: S_a(k) = (Y(k) + conj Y(N-k))/2, S_b(k) =
+// (Y(k) - conj Y(N-k))/(2i).  The stored half spectrum k = 0..(N-1)/2 is
+// extended by X(N-k) = conj X(k).  One wave handles LB lines; grid y splits
+// the components: part 0 the pairs (11, 22) and (33, 23), part 1 (13, 12).
+template <int N>
+struct OddLine {
+  static constexpr int N1 = two_step_n1(N);
+  static constexpr int N2 = N / N1;
+  static constexpr int TL = N1 > N2 ? N1 : N2;
+  static constexpr int LB = 64 / TL;
+  static constexpr int NH = (N + 1) / 2;
+  static constexpr int PITCH = N + TL + 1;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(64) void k_line_odd(const cpx<T>* in, cpx<T>* out, Geom g,
+                                                 const cpx<T>* __restrict__ twg, TangentArgs<T> tn,
+                                                 const double* __restrict__ macro_dev, double* __restrict__ partials,
+                                                 const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
+  using L = OddLine<N>;
+  constexpr int N1 = L::N1, N2 = L::N2, TL = L::TL, LB = L::LB, NH = L::NH, PITCH = L::PITCH;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[LB * PITCH];
+  __shared__ cpx<T> ybuf[LB * N];
+  for (int i = threadIdx.x; i < N; i += 64) tw[i] = twg[i];
+  __syncthreads();
+  const int lane = threadIdx.x, line = lane / TL, t = lane % TL;
+  const bool active = line < LB;
+  const long long nlines = (long long)g.n1 * g.n2;
+  const long long gl = (long long)blockIdx.x * LB + line;
+  const bool valid = active && gl < nlines;
+  const int tj = active ? t : TL;  // lanes past the last line take no part
+  const int off = (active ? line : 0) * PITCH;
+  const int part = blockIdx.y;
+  const T scale = (T)g.inv_nvox;
+  double mac[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) mac[c] = macro_dev ? macro_dev[c] : 0.0;
+  const cpx<T>* inl = in + (valid ? gl : 0) * NH;
+  cpx<T>* outl = out + (valid ? gl : 0) * NH;
+  cpx<T>* yb = ybuf + (active ? line : 0) * N;
+
+  // inverse: z_a + i z_b from the half spectra of components ca, cb;
+  // thread t < N1 then holds the samples n = t + N1 k2 (k2 < N2)
+  auto inverse_pair = [&](int ca, int cb, cpx<T>* Z) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int k = N2 * n1 + t;
+      cpx<T> xa = mk<T>(0, 0), xb = mk<T>(0, 0);
+      if (valid && t < N2) {
+        if (k < NH) {
+          xa = inl[ca * g.nh + k];
+          xb = inl[cb * g.nh + k];
+        } else {
+          xa = conj(inl[ca * g.nh + (N - k)]);
+          xb = conj(inl[cb * g.nh + (N - k)]);
+        }
+      }
+      Z[n1] = add(xa, muli(xb, (T)1));
+    }
+    two_step_fft<T, N1, N2, 1>(Z, tj, lds, 1, off, tw, (T)1);
+  };
+  // forward of the pair held as z = s_a + i s_b (thread t < N1, samples
+  // t + N1 k2), separated and stored scaled
+  auto forward_pair = [&](int ca, int cb, cpx<T>* Z) {
+    two_step_fft<T, N2, N1, 1>(Z, tj, lds, 1, off, tw, (T)-1);
+    // thread t < N2 holds Y(t + N2 m), m < N1
+    if (active && t < N2) {
+#pragma unroll
+      for (int m = 0; m < N1; ++m) yb[t + N2 * m] = Z[m];
+    }
+    __syncthreads();
+    if (valid && t < N2) {
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+        const int k = t + N2 * m;
+        if (k < NH) {
+          const cpx<T> Yk = Z[m];
+          const cpx<T> Ym = conj(yb[(N - k) % N]);
+          const cpx<T> Sa = scl(add(Yk, Ym), (T)0.5);
+          const cpx<T> Sb = muli(scl(sub(Yk, Ym), (T)0.5), (T)-1);
+          outl[ca * g.nh + k] = scl(Sa, scale);
+          outl[cb * g.nh + k] = scl(Sb, scale);
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  double energy = 0.0;
+  const bool lt = valid && t < N1;
+  if (part == 0) {
+    cpx<T> P[N2 > N1 ? N2 : N1], Q[N2 > N1 ? N2 : N1];
+    inverse_pair(0, 1, P);  // 11 + i 22
+    inverse_pair(2, 3, Q);  // 33 + i 23
+    if (lt) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const long long vox = gl * N + t + N1 * k2;
+        T lam, mu;
+        if (tn.kind == TAN_ISO_PHASE) {
+          const int p = tn.phase[vox];
+          lam = (T)tn.lam[p];
+          mu = (T)tn.mu[p];
+        } else {
+          const T E = tn.field[vox];
+          lam = (T)tn.lam1 * E;
+          mu = (T)tn.mu1 * E;
+        }
+        const T m2 = mu + mu;
+        const T e11 = P[k2].x + (T)mac[0], e22 = P[k2].y + (T)mac[1];
+        const T e33 = Q[k2].x + (T)mac[2], e23 = Q[k2].y + (T)mac[3];
+        const T tr = e11 + e22 + e33;
+        const T s11 = lam * tr + m2 * e11, s22 = lam * tr + m2 * e22, s33 = lam * tr + m2 * e33;
+        const T s23 = m2 * e23;
+        energy += (double)(e11 * s11 + e22 * s22 + e33 * s33) + 2.0 * (double)(e23 * s23);
+        P[k2] = mk<T>(s11, s22);
+        Q[k2] = mk<T>(s33, s23);
+      }
+    }
+    forward_pair(0, 1, P);
+    forward_pair(2, 3, Q);
+  } else {
+    cpx<T> P[N2 > N1 ? N2 : N1];
+    inverse_pair(4, 5, P);  // 13 + i 12
+    if (lt) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const long long vox = gl * N + t + N1 * k2;
+        T mu;
+        if (tn.kind == TAN_ISO_PHASE) mu = (T)tn.mu[tn.phase[vox]];
+        else mu = (T)tn.mu1 * tn.field[vox];
+        const T m2 = mu + mu;
+        const T e13 = P[k2].x + (T)mac[4], e12 = P[k2].y + (T)mac[5];
+        const T s13 = m2 * e13, s12 = m2 * e12;
+        energy += 2.0 * (double)(e13 * s13 + e12 * s12);
+        P[k2] = mk<T>(s13, s12);
+      }
+    }
+    forward_pair(4, 5, P);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) energy += __shfl_xor(energy, o, 64);
+  if (partials != nullptr && threadIdx.x == 0)
+    partials[blockIdx.x + (long long)blockIdx.y * gridDim.x] = energy * g.inv_nvox;
+}
+
+bool odd_line_supported(int n3) { return n3 == 63; }
+
+int odd_line_energy_blocks(const Geom& g) {
+  const int lb = OddLine<63>::LB;
+  return 2 * (int)(((long long)g.n1 * g.n2 + lb - 1) / lb);
+}
+
+template <typename T>
+void launch_line_odd(const void* in, void* out, const Geom& g, const void* tw, const TangentArgs<T>& tan,
+                     const double* macro_dev, double* partials, hipStream_t st, const int* stop) {
+  const int nb = odd_line_energy_blocks(g) / 2;
+  DB_LAUNCH((k_line_odd<T, 63>), dim3(nb, 2), dim3(64), 0, st, static_cast<const cpx<T>*>(in),
+            static_cast<cpx<T>*>(out), g, static_cast<const cpx<T>*>(tw), tan, macro_dev, partials, stop);
+}
+template void launch_line_odd<double>(const void*, void*, const Geom&, const void*, const TangentArgs<double>&,
+                                      const double*, double*, hipStream_t, const int*);
+template void launch_line_odd<float>(const void*, void*, const Geom&, const void*, const TangentArgs<float>&,
+                                     const double*, double*, hipStream_t, const int*);
+
 }  // namespace dbfft

@@ -122,6 +122,11 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
     return;
   }
   const bool iso = kin == KIN_SMALL && (tan.kind == TAN_ISO_PHASE || tan.kind == TAN_ISO_FIELD);
+  if (mode == LP_FUSED && macro_add == nullptr && iso && odd_line_supported(g.n3)) {
+    if (nblocks_out) *nblocks_out = odd_line_energy_blocks(g);
+    launch_line_odd<T>(in, out, g, tw, tan, macro_dev, partials, st, stop);
+    return;
+  }
   if (mode == LP_FUSED && macro_add == nullptr && mixed_line_supported(g.n3, (int)sizeof(cpx<T>), iso)) {
     if (nblocks_out) *nblocks_out = mixed_line_energy_blocks(g, iso);
     launch_line_mixed<T>(kin, iso, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
@@ -176,6 +181,7 @@ template void launch_line<float>(int, int, const void*, void*, const Geom&, cons
 int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes, int tan_kind) {
   const bool iso = (ncomp == 6) && (tan_kind == TAN_ISO_PHASE || tan_kind == TAN_ISO_FIELD);
   if (fast_line_supported(g.n3) && (elem_bytes == 8 || iso)) return fast_line_blocks(g, elem_bytes);
+  if (iso && odd_line_supported(g.n3)) return odd_line_energy_blocks(g);
   if (mixed_line_supported(g.n3, elem_bytes, iso)) return mixed_line_energy_blocks(g, iso);
   const int L = line_lines_per_block(g, ncomp, elem_bytes);
   return (int)(((long long)g.n1 * g.n2 + L - 1) / L);

@@ -66,7 +66,7 @@ def test_odd_real_apply_iso_phase(gpu, n):
 
 
 @pytest.mark.parametrize("kin", ["small", "finite"])
-@pytest.mark.parametrize("n", [(9, 7, 15), (7, 7, 7), (14, 21, 9), (63, 6, 126)])
+@pytest.mark.parametrize("n", [(9, 7, 15), (7, 7, 7), (14, 21, 9), (63, 6, 126), (7, 6, 63)])
 def test_odd_real_apply_fp32(gpu, n, kin):
     import torch
     from paper_1905_12725_amd.api import Cell
@@ -138,7 +138,7 @@ def test_odd_fourier_apply_with_macro(gpu, n):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
-@pytest.mark.parametrize("n", [(15, 21, 9), (21, 21, 21)])
+@pytest.mark.parametrize("n", [(15, 21, 9), (21, 21, 21), (7, 6, 63)])
 def test_odd_solve_parity_mixed_control(gpu, n, prec):
     """Uniaxial strain with the two lateral normal stresses prescribed to
     zero, odd grids: homogenized stress, solution coefficients and macro
