@@ -168,7 +168,8 @@ bool fast_strided_supported(int n);
 // tangent in FP32
 bool mixed_line_supported(int n3, int elem_bytes, bool iso);
 int mixed_line_blocks(const Geom& g);
-// fused z pass of the odd length 63 (isotropic small strains), two parts
+// fused z pass of the odd two-step lengths 15, 25, 27, 45, 63 (isotropic
+// small strains), two parts
 bool odd_line_supported(int n3);
 int odd_line_energy_blocks(const Geom& g);
 template <typename T>

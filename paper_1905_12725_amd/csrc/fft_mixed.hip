@@ -306,10 +306,21 @@ __global__ __launch_bounds__(64) void k_line_odd(const cpx<T>* in, cpx<T>* out, 
     partials[blockIdx.x + (long long)blockIdx.y * gridDim.x] = energy * g.inv_nvox;
 }
 
-bool odd_line_supported(int n3) { return n3 == 63; }
+// the odd lengths of the two-step set
+bool odd_line_supported(int n3) { return n3 == 15 || n3 == 25 || n3 == 27 || n3 == 45 || n3 == 63; }
+
+static int odd_lines_per_wave(int n3) {
+  switch (n3) {
+    case 15: return OddLine<15>::LB;
+    case 25: return OddLine<25>::LB;
+    case 27: return OddLine<27>::LB;
+    case 45: return OddLine<45>::LB;
+    default: return OddLine<63>::LB;
+  }
+}
 
 int odd_line_energy_blocks(const Geom& g) {
-  const int lb = OddLine<63>::LB;
+  const int lb = odd_lines_per_wave(g.n3);
   return 2 * (int)(((long long)g.n1 * g.n2 + lb - 1) / lb);
 }
 
@@ -317,8 +328,16 @@ template <typename T>
 void launch_line_odd(const void* in, void* out, const Geom& g, const void* tw, const TangentArgs<T>& tan,
                      const double* macro_dev, double* partials, hipStream_t st, const int* stop) {
   const int nb = odd_line_energy_blocks(g) / 2;
-  DB_LAUNCH((k_line_odd<T, 63>), dim3(nb, 2), dim3(64), 0, st, static_cast<const cpx<T>*>(in),
-            static_cast<cpx<T>*>(out), g, static_cast<const cpx<T>*>(tw), tan, macro_dev, partials, stop);
+  auto i = static_cast<const cpx<T>*>(in);
+  auto o = static_cast<cpx<T>*>(out);
+  auto t = static_cast<const cpx<T>*>(tw);
+  switch (g.n3) {
+#define DBFFT_ZO(NN) \
+  case NN: DB_LAUNCH((k_line_odd<T, NN>), dim3(nb, 2), dim3(64), 0, st, i, o, g, t, tan, macro_dev, partials, stop); break;
+    DBFFT_ZO(15) DBFFT_ZO(25) DBFFT_ZO(27) DBFFT_ZO(45) DBFFT_ZO(63)
+#undef DBFFT_ZO
+    default: break;
+  }
 }
 template void launch_line_odd<double>(const void*, void*, const Geom&, const void*, const TangentArgs<double>&,
                                       const double*, double*, hipStream_t, const int*);

@@ -46,7 +46,8 @@ def oracle_residuals(n, tan, load, mask, a, eps_bar):
 
 
 @pytest.mark.parametrize("n", [(7, 9, 15), (21, 15, 9), (15, 14, 21), (63, 7, 5), (5, 63, 7), (9, 10, 63),
-                               (49, 6, 7), (8, 8, 7), (3, 5, 1), (6, 8, 126)])
+                               (49, 6, 7), (8, 8, 7), (3, 5, 1), (6, 8, 126), (6, 5, 25), (4, 6, 27),
+                               (5, 4, 45)])
 def test_odd_real_apply_iso_phase(gpu, n):
     import torch
     from paper_1905_12725_amd.api import Cell
