@@ -84,6 +84,64 @@ __device__ __forceinline__ void seq_n(const double* sg, double& seq, double* n) 
   for (int a = 0; a < 6; ++a) n[a] = 1.5 * s[a] / seq;
 }
 
+// Cholesky factor of a symmetric positive definite 6x6 matrix (lower
+// triangle of A used), all indices compile-time so nothing leaves registers
+__device__ __forceinline__ bool chol6(const double (&A)[6][6], double (&L)[6][6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double d = A[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0)) return false;
+    const double ljj = sqrt(d);
+    L[j][j] = ljj;
+    const double inv = 1.0 / ljj;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v * inv;
+    }
+  }
+  return true;
+}
+
+// solves L L^T x = b in place
+__device__ __forceinline__ void chol6_solve(const double (&L)[6][6], double (&b)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= L[i][k] * b[k];
+    b[i] = v / L[i][i];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) v -= L[k][i] * b[k];
+    b[i] = v / L[i][i];
+  }
+}
+
+// M = S + c1 (P_dev - (2/3) n n^T) + c2 n n^T, S the grain's compliance
+__device__ __forceinline__ void flow_matrix(const double* __restrict__ S36, const double (&n)[6], double c1, double c2,
+                                            double (&M)[6][6]) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const double pd = ((a == b) ? 1.0 : 0.0) - ((a < 3 && b < 3) ? 1.0 / 3.0 : 0.0);
+      M[a][b] = S36[a * 6 + b] + c1 * (pd - (2.0 / 3.0) * n[a] * n[b]) + c2 * n[a] * n[b];
+    }
+}
+
+// Backward-Euler J2 viscoplastic update in (sigma, y = ln dp).  The 7x7
+// Newton system [[A, e^y n], [(m/s_eq) n^T, -1]] is reduced to its 6x6 Schur
+// complement A + e^y (m/s_eq) n n^T (symmetric positive definite: A = S +
+// e^y (3/(2 s_eq)) (P_dev - (2/3) n n^T)), solved by Cholesky; the
+// consistent tangent is the inverse of the same form at the converged state.
 __global__ __launch_bounds__(kMatThreads) void k_j2_update(const double* __restrict__ eps,
                                                           const double* __restrict__ epsp_n,
                                                           const int32_t* __restrict__ grain,
@@ -94,21 +152,20 @@ __global__ __launch_bounds__(kMatThreads) void k_j2_update(const double* __restr
   const long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x;
   if (v >= nvox) return;
   const int gid = grain[v];
-  double C[6][6], S[6][6];
-  for (int a = 0; a < 6; ++a)
-    for (int b = 0; b < 6; ++b) {
-      C[a][b] = gC[(long long)gid * 36 + a * 6 + b];
-      S[a][b] = gS[(long long)gid * 36 + a * 6 + b];
-    }
+  const double* C36 = gC + (long long)gid * 36;
+  const double* S36 = gS + (long long)gid * 36;
   double ee[6];
+#pragma unroll
   for (int a = 0; a < 6; ++a) {
     const double e = eps[(long long)a * nvox + v];
     ee[a] = ((a < 3) ? e : kR2 * e) - epsp_n[(long long)a * nvox + v];
   }
   double str[6];
+#pragma unroll
   for (int a = 0; a < 6; ++a) {
     double acc = 0.0;
-    for (int b = 0; b < 6; ++b) acc += C[a][b] * ee[b];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) acc += C36[a * 6 + b] * ee[b];
     str[a] = acc;
   }
   double seq_tr, ntr[6];
@@ -116,22 +173,33 @@ __global__ __launch_bounds__(kMatThreads) void k_j2_update(const double* __restr
     const double p = (str[0] + str[1] + str[2]) / 3.0;
     const double s[6] = {str[0] - p, str[1] - p, str[2] - p, str[3], str[4], str[5]};
     double ss = 0.0;
+#pragma unroll
     for (int a = 0; a < 6; ++a) ss += s[a] * s[a];
     seq_tr = sqrt(1.5 * ss);
+#pragma unroll
     for (int a = 0; a < 6; ++a) ntr[a] = (seq_tr > 0.0) ? 1.5 * s[a] / seq_tr : 0.0;
   }
-  double sg[6], Ct[6][6], dp = 0.0, n[6];
-  for (int a = 0; a < 6; ++a) n[a] = 0.0;
-  if (!(seq_tr > 1e-12 * s0)) {
-    for (int a = 0; a < 6; ++a) {
-      sg[a] = str[a];
-      for (int b = 0; b < 6; ++b) Ct[a][b] = C[a][b];
-    }
-  } else {
+  double sg[6], dp = 0.0, n[6];
+  bool elastic = !(seq_tr > 1e-12 * s0);
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    n[a] = 0.0;
+    sg[a] = str[a];
+  }
+  if (!elastic) {
     const double logc = log(edot0 * dt);
+    double Cn[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) acc += C36[a * 6 + b] * ntr[b];
+      Cn[a] = acc;
+    }
     double h = 0.0;
-    for (int a = 0; a < 6; ++a)
-      for (int b = 0; b < 6; ++b) h += ntr[a] * C[a][b] * ntr[b];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) h += ntr[a] * Cn[a];
     double lo = fmin(log(0.5 * seq_tr / h), logc + m * log(0.5 * seq_tr / s0));
     double hi = log(seq_tr / h);
     double y = 0.5 * (lo + hi);
@@ -149,64 +217,83 @@ __global__ __launch_bounds__(kMatThreads) void k_j2_update(const double* __restr
     }
     {
       const double ey = exp(y);
-      for (int a = 0; a < 6; ++a) {
-        double acc = 0.0;
-        for (int b = 0; b < 6; ++b) acc += C[a][b] * ntr[b];
-        sg[a] = str[a] - ey * acc;
-      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) sg[a] = str[a] - ey * Cn[a];
     }
-    bool ok = true;
     for (int it = 0; it < 100; ++it) {
       double seq;
       seq_n(sg, seq, n);
       const double ey = exp(y);
-      double J[7][7], R[7];
+      double R[6];
+#pragma unroll
       for (int a = 0; a < 6; ++a) {
         double acc = 0.0;
-        for (int b = 0; b < 6; ++b) acc += S[a][b] * sg[b];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc += S36[a * 6 + b] * sg[b];
         R[a] = -(acc - ee[a] + ey * n[a]);
       }
-      R[6] = -(m * log(seq / s0) - y + logc);
-      const double f = 1.5 / seq;
-      for (int a = 0; a < 6; ++a) {
-        for (int b = 0; b < 6; ++b) {
-          const double pd = ((a == b) ? 1.0 : 0.0) - ((a < 3 && b < 3) ? 1.0 / 3.0 : 0.0);
-          J[a][b] = S[a][b] + ey * f * (pd - (2.0 / 3.0) * n[a] * n[b]);
-        }
-        J[a][6] = ey * n[a];
-        J[6][a] = (m / seq) * n[a];
-      }
-      J[6][6] = -1.0;
-      if (!gauss_solve<7>(J, R, 7)) {
+      const double R6 = -(m * log(seq / s0) - y + logc);
+      double A[6][6], L[6][6];
+      flow_matrix(S36, n, ey * 1.5 / seq, ey * m / seq, A);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) R[a] += ey * R6 * n[a];
+      if (!chol6(A, L)) {
         ok = false;
         break;
       }
-      double dmax = 0.0;
+      chol6_solve(L, R);
+      double nd = 0.0, dmax = 0.0;
+#pragma unroll
       for (int a = 0; a < 6; ++a) {
+        nd += n[a] * R[a];
         sg[a] += R[a];
         dmax = fmax(dmax, fabs(R[a]));
       }
-      y += R[6];
-      if (dmax <= 1e-11 * s0 && fabs(R[6]) <= 1e-11) break;
+      const double dy = (m / seq) * nd - R6;
+      y += dy;
+      if (dmax <= 1e-11 * s0 && fabs(dy) <= 1e-11) break;
     }
     double seq;
     seq_n(sg, seq, n);
     dp = exp(y);
-    double A[6][6];
-    const double f = 1.5 / seq;
-    for (int a = 0; a < 6; ++a)
-      for (int b = 0; b < 6; ++b) {
-        const double pd = ((a == b) ? 1.0 : 0.0) - ((a < 3 && b < 3) ? 1.0 / 3.0 : 0.0);
-        A[a][b] = S[a][b] + dp * f * (pd - (2.0 / 3.0) * n[a] * n[b]) + dp * (m / seq) * n[a] * n[b];
-      }
-    if (!inv6(A, Ct)) ok = false;
-    if (!ok || !(dp == dp)) atomicOr(fail, 1);
   }
   // outputs: stress in stored tensor order, tangent upper triangle, plastic strain (Mandel)
+#pragma unroll
   for (int a = 0; a < 6; ++a) sig_out[(long long)a * nvox + v] = (a < 3) ? sg[a] : sg[a] / kR2;
-  int idx = 0;
-  for (int a = 0; a < 6; ++a)
-    for (int b = a; b < 6; ++b) tan21[(long long)(idx++) * nvox + v] = 0.5 * (Ct[a][b] + Ct[b][a]);
+  if (elastic) {
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a; b < 6; ++b) tan21[(long long)(idx++) * nvox + v] = 0.5 * (C36[a * 6 + b] + C36[b * 6 + a]);
+  } else {
+    // consistent tangent: inverse of S + dp (3/(2 s_eq)) (P_dev - (2/3) n n^T) + dp (m/s_eq) n n^T
+    double seq;
+    {
+      double nn[6];
+      seq_n(sg, seq, nn);
+    }
+    double A[6][6], L[6][6];
+    flow_matrix(S36, n, dp * 1.5 / seq, dp * m / seq, A);
+    if (!chol6(A, L)) ok = false;
+    double Ct[6][6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double e[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) e[i] = (i == c) ? 1.0 : 0.0;
+      chol6_solve(L, e);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) Ct[i][c] = e[i];
+    }
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a; b < 6; ++b) tan21[(long long)(idx++) * nvox + v] = 0.5 * (Ct[a][b] + Ct[b][a]);
+  }
+  if (!ok || !(dp == dp)) atomicOr(fail, 1);
+#pragma unroll
   for (int a = 0; a < 6; ++a) epsp_new[(long long)a * nvox + v] = epsp_n[(long long)a * nvox + v] + dp * n[a];
 }
 
