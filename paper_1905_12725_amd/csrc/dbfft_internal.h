@@ -168,6 +168,12 @@ bool fast_strided_supported(int n);
 // tangent in FP32
 bool mixed_line_supported(int n3, int elem_bytes, bool iso);
 int mixed_line_blocks(const Geom& g);
+// real z transforms (LP_C2R with macro_dev + macro_add, LP_R2C scaled 1/N),
+// one component per grid y, for even n3 with n3/2 in the two-step set
+bool real_line_supported(int n3);
+template <typename T>
+void launch_line_real(int mode, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
+                      const double* mac_a, const double* mac_b, int ncomp, hipStream_t st);
 // fused z pass of the odd two-step lengths 15, 25, 27, 45, 63 (isotropic
 // small strains), two parts
 bool odd_line_supported(int n3);

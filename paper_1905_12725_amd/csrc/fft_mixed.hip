@@ -154,6 +154,122 @@ template void launch_line_mixed<double>(int, bool, const void*, void*, const Geo
 template void launch_line_mixed<float>(int, bool, const void*, void*, const Geom&, const void*, const void*,
                                        const TangentArgs<float>&, const double*, double*, hipStream_t, const int*);
 
+// ---------------------------------------------------------------- real z transforms
+// Inverse (C2R, + macro) or forward (R2C, scaled 1/N) real transforms of
+// one component per grid y, LB lines per wave, even n3 with n3/2 in the
+// two-step set (powers of two included): the strain fields and stress
+// residuals of the Newton steps.
+template <typename T, int M>
+__global__ __launch_bounds__(64) void k_line_c2r(const cpx<T>* in, T* out, Geom g, const cpx<T>* __restrict__ twg,
+                                                 const cpx<T>* __restrict__ rtwg, const double* __restrict__ mac_a,
+                                                 const double* __restrict__ mac_b) {
+  using L = MixedLine<M>;
+  constexpr int N1 = L::N1, N2 = L::N2, EM = L::EM, TL = L::TL, LB = L::LB, PITCH = L::PITCH;
+  __shared__ cpx<T> tw[M];
+  __shared__ cpx<T> rtw[M + 1];
+  __shared__ cpx<T> lds[LB * PITCH];
+  for (int i = threadIdx.x; i < M; i += 64) tw[i] = twg[i];
+  for (int i = threadIdx.x; i <= M; i += 64) rtw[i] = rtwg[i];
+  __syncthreads();
+  const int lane = threadIdx.x, line = lane / TL, t = lane % TL;
+  const bool active = line < LB;
+  const long long gl = (long long)blockIdx.x * LB + line;
+  const bool valid = active && gl < (long long)g.n1 * g.n2;
+  const int tj = active ? t : TL;
+  const int partner = active ? line * TL + ((t < N2) ? (N2 - t) % N2 : t) : lane;
+  const int off = (active ? line : 0) * PITCH;
+  const int c = blockIdx.y;
+  const T mc = (T)((mac_a ? mac_a[c] : 0.0) + (mac_b ? mac_b[c] : 0.0));
+  cpx<T> e[EM];
+  mixed_line_inverse<T, M>(in + (long long)c * g.nh + (valid ? gl : 0) * g.nh3, valid, t, tj, partner, lds, off, tw,
+                           rtw, e);
+  if (valid && t < N1) {
+    T* o = out + (long long)c * g.nvox + gl * g.n3;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int n = t + N1 * k2;
+      o[2 * n] = e[k2].x + mc;
+      o[2 * n + 1] = e[k2].y + mc;
+    }
+  }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(64) void k_line_r2c(const T* in, cpx<T>* out, Geom g, const cpx<T>* __restrict__ twg,
+                                                 const cpx<T>* __restrict__ rtwg) {
+  using L = MixedLine<M>;
+  constexpr int N1 = L::N1, N2 = L::N2, EM = L::EM, TL = L::TL, LB = L::LB, PITCH = L::PITCH;
+  __shared__ cpx<T> tw[M];
+  __shared__ cpx<T> rtw[M + 1];
+  __shared__ cpx<T> lds[LB * PITCH];
+  for (int i = threadIdx.x; i < M; i += 64) tw[i] = twg[i];
+  for (int i = threadIdx.x; i <= M; i += 64) rtw[i] = rtwg[i];
+  __syncthreads();
+  const int lane = threadIdx.x, line = lane / TL, t = lane % TL;
+  const bool active = line < LB;
+  const long long gl = (long long)blockIdx.x * LB + line;
+  const bool valid = active && gl < (long long)g.n1 * g.n2;
+  const int tj = active ? t : TL;
+  const int partner = active ? line * TL + ((t < N2) ? (N2 - t) % N2 : t) : lane;
+  const int off = (active ? line : 0) * PITCH;
+  const int c = blockIdx.y;
+  cpx<T> e[EM];
+#pragma unroll
+  for (int k2 = 0; k2 < EM; ++k2) e[k2] = mk<T>(0, 0);
+  if (valid && t < N1) {
+    const T* x = in + (long long)c * g.nvox + gl * g.n3;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int n = t + N1 * k2;
+      e[k2] = mk<T>(x[2 * n], x[2 * n + 1]);
+    }
+  }
+  mixed_line_forward<T, M>(out + (long long)c * g.nh + (valid ? gl : 0) * g.nh3, valid, t, tj, partner, lds, off, tw,
+                           rtw, e, (T)g.inv_nvox);
+}
+
+bool real_line_supported(int n3) {
+  switch (n3 / 2) {
+    case 12: case 15: case 16: case 18: case 20: case 24: case 25: case 27: case 30: case 32: case 36: case 40:
+    case 45: case 48: case 50: case 54: case 60: case 63: case 64: case 72: case 80: case 90: case 96:
+      return n3 % 2 == 0;
+    default: return false;
+  }
+}
+
+template <typename T, int M>
+static void launch_line_real_m(int mode, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
+                               const double* mac_a, const double* mac_b, int ncomp, hipStream_t st) {
+  const int lb = MixedLine<M>::LB;
+  const int nb = (int)(((long long)g.n1 * g.n2 + lb - 1) / lb);
+  auto t = static_cast<const cpx<T>*>(tw);
+  auto r = static_cast<const cpx<T>*>(rtw);
+  if (mode == LP_C2R)
+    DB_LAUNCH((k_line_c2r<T, M>), dim3(nb, ncomp), dim3(64), 0, st, static_cast<const cpx<T>*>(in),
+              static_cast<T*>(out), g, t, r, mac_a, mac_b);
+  else
+    DB_LAUNCH((k_line_r2c<T, M>), dim3(nb, ncomp), dim3(64), 0, st, static_cast<const T*>(in),
+              static_cast<cpx<T>*>(out), g, t, r);
+}
+
+template <typename T>
+void launch_line_real(int mode, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
+                      const double* mac_a, const double* mac_b, int ncomp, hipStream_t st) {
+  switch (g.n3 / 2) {
+#define DBFFT_ZR(MM) \
+  case MM: launch_line_real_m<T, MM>(mode, in, out, g, tw, rtw, mac_a, mac_b, ncomp, st); break;
+    DBFFT_ZR(12) DBFFT_ZR(15) DBFFT_ZR(16) DBFFT_ZR(18) DBFFT_ZR(20) DBFFT_ZR(24) DBFFT_ZR(25) DBFFT_ZR(27)
+    DBFFT_ZR(30) DBFFT_ZR(32) DBFFT_ZR(36) DBFFT_ZR(40) DBFFT_ZR(45) DBFFT_ZR(48) DBFFT_ZR(50) DBFFT_ZR(54)
+    DBFFT_ZR(60) DBFFT_ZR(63) DBFFT_ZR(64) DBFFT_ZR(72) DBFFT_ZR(80) DBFFT_ZR(90) DBFFT_ZR(96)
+#undef DBFFT_ZR
+    default: break;
+  }
+}
+template void launch_line_real<double>(int, const void*, void*, const Geom&, const void*, const void*, const double*,
+                                       const double*, int, hipStream_t);
+template void launch_line_real<float>(int, const void*, void*, const Geom&, const void*, const void*, const double*,
+                                      const double*, int, hipStream_t);
+
 // ---------------------------------------------------------------- odd z pass
 // Fused z pass for an odd length N = n3 (two-step N1 x N2), isotropic
 // small-strain tangent.  A line's samples are real, so two components ride

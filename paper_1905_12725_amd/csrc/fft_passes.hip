@@ -122,6 +122,11 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
     return;
   }
   const bool iso = kin == KIN_SMALL && (tan.kind == TAN_ISO_PHASE || tan.kind == TAN_ISO_FIELD);
+  if ((mode == LP_C2R || mode == LP_R2C) && ncomp <= 9 && real_line_supported(g.n3)) {
+    if (nblocks_out) *nblocks_out = 0;
+    launch_line_real<T>(mode, in, out, g, tw, rtw, macro_dev, macro_add, ncomp, st);
+    return;
+  }
   if (mode == LP_FUSED && macro_add == nullptr && iso && odd_line_supported(g.n3)) {
     if (nblocks_out) *nblocks_out = odd_line_energy_blocks(g);
     launch_line_odd<T>(in, out, g, tw, tan, macro_dev, partials, st, stop);
