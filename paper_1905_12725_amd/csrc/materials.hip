@@ -396,6 +396,72 @@ constexpr int kMeanBlocks = 512;
 int tangent_mean_block_count(const Geom&) { return kMeanBlocks; }
 int tangent_mean_nvals(int kin) { return kin == KIN_SMALL ? 21 : 81; }
 
+// finite strains: all 81 components of a voxel from one read of its field
+// entries; each component gets the same terms, in the same voxel order and
+// with the same block sums, as a sweep of its own would give
+template <typename T>
+__global__ __launch_bounds__(kMatThreads) void k_tangent_mean_finite(TangentArgs<T> tn, Geom g,
+                                                                    double* __restrict__ partials) {
+  // finite strains: all 81 components of a voxel from one read of its
+  // field entries; each component gets the same terms, in the same voxel
+  // order, as a sweep of its own would give
+  double acc[81];
+#pragma unroll
+  for (int c = 0; c < 81; ++c) acc[c] = 0.0;
+  for (long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x; v < g.nvox;
+       v += (long long)gridDim.x * kMatThreads) {
+    const int p = tn.phase[v];
+    const double mu = tn.mu[p], lam = tn.lam[p];
+    if (tn.kind == TAN_SVK_FIELD) {
+      // K_iJkL = d_ik S_LJ + lam F_iJ F_kL + mu (F_iL F_kJ + (F F^T)_ik d_JL)
+      const int smap[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};  // (a, b) -> stored index
+      double F[9], S[6];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) F[q] = (double)tn.field[(long long)q * g.nvox + v];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) S[q] = (double)tn.field[(long long)(9 + q) * g.nvox + v];
+#pragma unroll
+      for (int c = 0; c < 81; ++c) {
+        const int L = c % 3, k = (c / 3) % 3, J = (c / 9) % 3, i = c / 27;
+        double FFt = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) FFt += F[i * 3 + q] * F[k * 3 + q];
+        acc[c] += ((i == k) ? S[smap[L * 3 + J]] : 0.0) + lam * F[i * 3 + J] * F[k * 3 + L] +
+                  mu * (F[i * 3 + L] * F[k * 3 + J] + ((J == L) ? FFt : 0.0));
+      }
+    } else {
+      // K_iJkL = mu d_ik d_JL + (mu - lam ln J) Finv_Li Finv_Jk + lam Finv_Ji Finv_Lk
+      double Fi[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Fi[q] = (double)tn.field[(long long)q * g.nvox + v];
+      const double lnJ = (double)tn.field[9LL * g.nvox + v];
+#pragma unroll
+      for (int c = 0; c < 81; ++c) {
+        const int L = c % 3, k = (c / 3) % 3, J = (c / 9) % 3, i = c / 27;
+        acc[c] += ((i == k && J == L) ? mu : 0.0) + (mu - lam * lnJ) * Fi[L * 3 + i] * Fi[J * 3 + k] +
+                  lam * Fi[J * 3 + i] * Fi[L * 3 + k];
+      }
+    }
+  }
+  // block sums as block_sum forms them (wave shuffles, then the waves in
+  // order), all components at once
+  __shared__ double wred[81][kMatThreads / 64];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 81; ++c) {
+    double s = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (ln == 0) wred[c][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 81) {
+    double s = 0.0;
+    for (int w = 0; w < kMatThreads / 64; ++w) s += wred[threadIdx.x][w];
+    partials[(long long)blockIdx.x * 81 + threadIdx.x] = s;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kMatThreads) void k_tangent_mean(TangentArgs<T> tn, int kin, Geom g,
                                                              double* __restrict__ partials) {
@@ -467,7 +533,10 @@ __global__ __launch_bounds__(kMatThreads) void k_tangent_mean(TangentArgs<T> tn,
 template <typename T>
 void launch_tangent_mean(const TangentArgs<T>& tan, int kin, const Geom& g, double* partials, int nblocks,
                          hipStream_t st) {
-  hipLaunchKernelGGL((k_tangent_mean<T>), dim3(nblocks), dim3(kMatThreads), 0, st, tan, kin, g, partials);
+  if (kin == KIN_SMALL)
+    hipLaunchKernelGGL((k_tangent_mean<T>), dim3(nblocks), dim3(kMatThreads), 0, st, tan, kin, g, partials);
+  else
+    hipLaunchKernelGGL((k_tangent_mean_finite<T>), dim3(nblocks), dim3(kMatThreads), 0, st, tan, g, partials);
 }
 template void launch_tangent_mean<double>(const TangentArgs<double>&, int, const Geom&, double*, int, hipStream_t);
 template void launch_tangent_mean<float>(const TangentArgs<float>&, int, const Geom&, double*, int, hipStream_t);
