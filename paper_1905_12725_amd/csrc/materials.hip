@@ -465,62 +465,40 @@ __global__ __launch_bounds__(kMatThreads) void k_tangent_mean_finite(TangentArgs
 template <typename T>
 __global__ __launch_bounds__(kMatThreads) void k_tangent_mean(TangentArgs<T> tn, int kin, Geom g,
                                                              double* __restrict__ partials) {
+  // small strains: the 21 Mandel upper-triangle components, one sweep each
   __shared__ double red[kMatThreads / 64];
-  const int nv = (kin == KIN_SMALL) ? 21 : 81;
+  (void)kin;
+  constexpr int nv = 21;
   for (int c = 0; c < nv; ++c) {
     double acc = 0.0;
+    // Mandel upper-triangle index c -> (a, b)
+    int a = 0, b = 0, idx = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i; j < 6; ++j) {
+        if (idx == c) {
+          a = i;
+          b = j;
+        }
+        ++idx;
+      }
     for (long long v = (long long)blockIdx.x * kMatThreads + threadIdx.x; v < g.nvox;
          v += (long long)gridDim.x * kMatThreads) {
-      double val = 0.0;
-      if (kin == KIN_SMALL) {
-        // Mandel upper-triangle index c -> (a, b)
-        int a = 0, b = 0, idx = 0;
-        for (int i = 0; i < 6; ++i)
-          for (int j = i; j < 6; ++j) {
-            if (idx == c) {
-              a = i;
-              b = j;
-            }
-            ++idx;
-          }
-        if (tn.kind == TAN_ISO_PHASE || tn.kind == TAN_ISO_FIELD) {
-          double lam, mu;
-          if (tn.kind == TAN_ISO_PHASE) {
-            lam = tn.lam[tn.phase[v]];
-            mu = tn.mu[tn.phase[v]];
-          } else {
-            const double E = (double)tn.field[v];
-            lam = tn.lam1 * E;
-            mu = tn.mu1 * E;
-          }
-          val = ((a < 3 && b < 3) ? lam : 0.0) + ((a == b) ? 2.0 * mu : 0.0);
-        } else if (tn.kind == TAN_ANISO_GRAIN) {
-          val = tn.grain_table[(long long)tn.grain[v] * 21 + c];
+      double val;
+      if (tn.kind == TAN_ISO_PHASE || tn.kind == TAN_ISO_FIELD) {
+        double lam, mu;
+        if (tn.kind == TAN_ISO_PHASE) {
+          lam = tn.lam[tn.phase[v]];
+          mu = tn.mu[tn.phase[v]];
         } else {
-          val = (double)tn.field[(long long)c * g.nvox + v];
+          const double E = (double)tn.field[v];
+          lam = tn.lam1 * E;
+          mu = tn.mu1 * E;
         }
-      } else if (tn.kind == TAN_SVK_FIELD) {
-        // K_iJkL = d_ik S_LJ + lam F_iJ F_kL + mu (F_iL F_kJ + (F F^T)_ik d_JL)
-        const int L = c % 3, k = (c / 3) % 3, J = (c / 9) % 3, i = c / 27;
-        auto Fv = [&](int r, int q) { return (double)tn.field[(long long)(r * 3 + q) * g.nvox + v]; };
-        const int smap[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};  // (a, b) -> stored index
-        const int p = tn.phase[v];
-        const double mu = tn.mu[p], lam = tn.lam[p];
-        double FFt = 0.0;
-        for (int q = 0; q < 3; ++q) FFt += Fv(i, q) * Fv(k, q);
-        val = ((i == k) ? (double)tn.field[(long long)(9 + smap[L * 3 + J]) * g.nvox + v] : 0.0) +
-              lam * Fv(i, J) * Fv(k, L) + mu * (Fv(i, L) * Fv(k, J) + ((J == L) ? FFt : 0.0));
+        val = ((a < 3 && b < 3) ? lam : 0.0) + ((a == b) ? 2.0 * mu : 0.0);
+      } else if (tn.kind == TAN_ANISO_GRAIN) {
+        val = tn.grain_table[(long long)tn.grain[v] * 21 + c];
       } else {
-        // K_iJkL, c = ((i*3+J)*3+k)*3+L
-        const int L = c % 3, k = (c / 3) % 3, J = (c / 9) % 3, i = c / 27;
-        const double Fi_Li = (double)tn.field[(long long)(L * 3 + i) * g.nvox + v];
-        const double Fi_Jk = (double)tn.field[(long long)(J * 3 + k) * g.nvox + v];
-        const double Fi_Ji = (double)tn.field[(long long)(J * 3 + i) * g.nvox + v];
-        const double Fi_Lk = (double)tn.field[(long long)(L * 3 + k) * g.nvox + v];
-        const double lnJ = (double)tn.field[9LL * g.nvox + v];
-        const int p = tn.phase[v];
-        const double mu = tn.mu[p], lam = tn.lam[p];
-        val = ((i == k && J == L) ? mu : 0.0) + (mu - lam * lnJ) * Fi_Li * Fi_Jk + lam * Fi_Ji * Fi_Lk;
+        val = (double)tn.field[(long long)c * g.nvox + v];
       }
       acc += val;
     }
