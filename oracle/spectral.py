@@ -66,16 +66,73 @@ def half_weights(shape):
     return w
 
 
+# ---------------------------------------------------------------------------
+# The oracle's own discrete Fourier transform: the defining sums
+#   X(k) = sum_j x(j) exp(-2 pi i j k / n)
+# evaluated axis by axis as products with dense n x n matrices (no fast
+# algorithm).  Angles are formed from the integer j k mod n, so every entry
+# is the FP64 cos / sin of 2 pi m / n for an exact integer m.
+# ---------------------------------------------------------------------------
+
+def dft_matrix(n, sign=-1):
+    """W[j, k] = exp(sign 2 pi i j k / n).  The angle is taken from
+    min(m, n - m) with m = j k mod n and the sine's sign restored, so that
+    W[j, n - k] = conj W[j, k] holds exactly: the transform of a real field
+    is then exactly Hermitian, X(-k) = conj X(k)."""
+    k = np.arange(n)
+    m = np.outer(k, k) % n
+    mr = np.minimum(m, n - m)
+    ang = 2.0 * np.pi * mr / n
+    sgn = np.where(m > n - m, -1.0, 1.0)
+    return np.cos(ang) + sign * 1j * sgn * np.sin(ang)
+
+
+def _along(W, x, axis):
+    """sum_j W[k, j] x[..., j, ...] along `axis` (W symmetric here)."""
+    x = np.moveaxis(x, axis, 0)
+    lead = x.shape[0]
+    y = W @ x.reshape(lead, -1)
+    return np.moveaxis(y.reshape((W.shape[0],) + x.shape[1:]), 0, axis)
+
+
+def dft_r2c(field, shape):
+    """Unnormalized forward DFT of a real field over its last three axes,
+    k3 = 0..n3//2 kept (the other half is the complex conjugate)."""
+    n1, n2, n3 = shape
+    h3 = n3 // 2 + 1
+    W3 = dft_matrix(n3)[:, :h3]
+    f = np.asarray(field, dtype=np.float64)
+    out = (f @ W3.real) + 1j * (f @ W3.imag)
+    out = _along(dft_matrix(n2), out, -2)
+    return _along(dft_matrix(n1), out, -3)
+
+
+def dft_c2r(coeffs, shape):
+    """Unnormalized inverse DFT back to a real field: the sum over the full
+    spectrum of the half spectrum extended by X(-k) = conj X(k).  On the
+    self-conjugate planes k3 = 0 and k3 = n3/2 (even n3) only the real part
+    of the k3 sum counts, as for any real synthesis."""
+    n1, n2, n3 = shape
+    h3 = n3 // 2 + 1
+    c = _along(dft_matrix(n1, +1), np.asarray(coeffs, dtype=complex), -3)
+    c = _along(dft_matrix(n2, +1), c, -2)
+    mult = np.full(h3, 2.0)
+    mult[0] = 1.0
+    if n3 % 2 == 0:
+        mult[-1] = 1.0
+    E = dft_matrix(n3, +1)[:h3, :] * mult[:, None]
+    return c.real @ E.real - c.imag @ E.imag
+
+
 def fourier(field, shape):
     """Normalized forward transform F[f]/N over the last three axes."""
     N = float(np.prod(shape))
-    return np.fft.rfftn(field, axes=(-3, -2, -1)) / N
+    return dft_r2c(field, shape) / N
 
 
 def real_field(coeffs, shape):
     """Synthesis u(x) = sum_k a(k) exp(i xi.x) (unnormalized inverse DFT)."""
-    N = float(np.prod(shape))
-    return np.fft.irfftn(coeffs, s=shape, axes=(-3, -2, -1)) * N
+    return dft_c2r(coeffs, shape)
 
 
 def sym_grad(a, xi):

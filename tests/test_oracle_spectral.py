@@ -1,5 +1,8 @@
 """Pins of the oracle's Fourier operators against definitions that use no FFT.
 
+* The oracle's own DFT (dense per-axis sums) equals a brute-force triple
+  sum on tiny grids, the library FFT on the workload sizes, keeps
+  Parseval's identity and maps a delta to a constant.
 * The spectral differentiation matrix is checked against closed-form
   derivatives of trigonometric polynomials.
 * The FFT-based operator K (Sec. 2.2 eq. lineqf, sign-flipped; Sec. 2.3 for
@@ -13,6 +16,58 @@ import numpy as np
 import pytest
 
 from oracle import dense, spectral as sp, solver as so, materials as mt
+
+
+def _brute_dft(f):
+    """X(k) = sum_x f(x) exp(-2 pi i k.x / n), one term at a time."""
+    n1, n2, n3 = f.shape
+    X = np.zeros((n1, n2, n3 // 2 + 1), dtype=complex)
+    for k1 in range(n1):
+        for k2 in range(n2):
+            for k3 in range(n3 // 2 + 1):
+                acc = 0j
+                for x1 in range(n1):
+                    for x2 in range(n2):
+                        for x3 in range(n3):
+                            ph = -2 * np.pi * (k1 * x1 / n1 + k2 * x2 / n2 + k3 * x3 / n3)
+                            acc += f[x1, x2, x3] * complex(np.cos(ph), np.sin(ph))
+                X[k1, k2, k3] = acc
+    return X
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (4, 2, 6), (5, 3, 3)])
+def test_own_dft_brute_force(shape):
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(shape)
+    X = sp.dft_r2c(f, shape)
+    assert np.allclose(X, _brute_dft(f), rtol=0, atol=1e-13 * np.abs(X).max())
+    # planted slip: the wrong sign of the exponent fails
+    assert not np.allclose(np.conj(X), _brute_dft(f), atol=1e-6)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (7, 9, 15), (12, 10, 8), (32, 6, 63)])
+def test_own_dft_library_parseval_delta(shape):
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((2,) + shape)
+    X = sp.dft_r2c(f, shape)
+    lib = np.fft.rfftn(f, axes=(-3, -2, -1))
+    assert np.allclose(X, lib, rtol=0, atol=1e-13 * np.abs(lib).max())
+    # inverse of forward is N times the identity
+    assert np.allclose(sp.dft_c2r(X, shape), np.prod(shape) * f, rtol=0, atol=1e-11 * np.prod(shape))
+    # Parseval on the half spectrum with the plane weights
+    N = float(np.prod(shape))
+    w = sp.half_weights(shape)
+    assert np.isclose(sp.inner(X, X, w) / N, np.sum(f * f), rtol=1e-12)
+    # a delta at the origin transforms to a constant
+    d = np.zeros(shape); d[0, 0, 0] = 1.0
+    assert np.allclose(sp.dft_r2c(d, shape), 1.0, atol=1e-15)
+    # the k3 = 0 plane of a real field is Hermitian (the twiddles are
+    # exactly conjugate; only the order of the library's sums differs)
+    n1, n2, _ = shape
+    i1 = (-np.arange(n1)) % n1
+    i2 = (-np.arange(n2)) % n2
+    P = X[:, :, :, 0]
+    assert np.allclose(P[:, i1][:, :, i2], np.conj(P), rtol=0, atol=1e-15 * np.abs(P).max())
 
 
 @pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9, 16])
