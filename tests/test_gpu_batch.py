@@ -256,9 +256,11 @@ def test_batch_rejects_mixed_classes(gpu):
 
 def test_batch_neohooke_smooth_sizes_fp32_vs_fp64_single(gpu):
     """Uneven-batch workload shape (neo-Hookean sphere composites, 2-3-5
-    smooth sizes): the batched FP32-mixed Newton (two-step register
-    transforms in x, y and z) against one-cell FP64 solves of the same
-    cells, which take other transform paths."""
+    smooth sizes): the batched FP32-mixed Newton against one-cell FP64
+    solves of the same cells.  Both form their Newton residuals with the
+    same real z transforms and two-step x/y transforms, so this checks the
+    batched PCG passes and the precision, not those shared kernels; the
+    oracle pins the lengths on thin cells in test_gpu_lengths.py."""
     import torch
     from paper_1905_12725_amd.api import Cell, Batch
     sizes = [32, 36, 40, 48, 50]

@@ -1,0 +1,183 @@
+"""Oracle parity of the HIP path at every line length the workloads run.
+
+The batch of uneven cells draws its sizes from the even 2-3-5-smooth lengths
+32..96 and the adjoint workload runs 96^3; each length is its own kernel
+instantiation (two-step N1 x N2 register transforms of the x, y and z
+passes, the real z transforms of the Newton fields, the batched passes).
+Thin grids put each length on one axis with small other axes, so the oracle
+finishes in milliseconds while every kernel of that length runs.
+
+Bars: FP64 operator within 1e-12 relative (max norm over the field), FP32
+within 1e-5; Newton solutions at tol 1e-12 within 1e-9 (FP64), FP32-mixed
+within 1e-6 of the FP64 oracle on the homogenized stress.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_12725_amd import microstructure as ms
+from oracle import spectral as sp, solver as so, materials as mt
+
+pytestmark = pytest.mark.gpu
+
+# z lengths n3 whose half n3/2 is a two-step length, and the x / y lengths of
+# the batch and adjoint workloads
+Z_LENGTHS = [24, 36, 40, 48, 50, 54, 72, 80, 90, 96, 108, 120, 144, 160, 180, 192]
+XY_LENGTHS = [54, 72, 80, 90, 96]
+SHAPES = ([(4, 6, n3) for n3 in Z_LENGTHS] + [(n, 6, 8) for n in XY_LENGTHS] + [(6, n, 8) for n in XY_LENGTHS]
+          + [(72, 4, 54), (8, 6, 80), (96, 6, 8), (6, 90, 8)])
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _neo_tangent_at_identity(phase, mus):
+    mus = np.asarray(mus, dtype=float)
+    lams = 3.0 * mus - 2.0 * mus / 3.0
+    F = np.broadcast_to(np.eye(3), phase.shape + (3, 3))
+    return so.GeneralTangent(mt.neohooke_tangent(F, mus[phase], lams[phase]))
+
+
+def _oracle_real_apply(n, tan, kin, u):
+    space = so.Space(n, kin=kin)
+    a = sp.fourier(u, n)
+    a[:, space.Z] = 0
+    (ka, _), _ = space.apply((a, np.zeros(0)), tan)
+    return sp.real_field(ka, n)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("kin", ["small", "finite"])
+@pytest.mark.parametrize("n", SHAPES)
+def test_real_apply_lengths(gpu, n, kin, prec):
+    """Real-space operator (the real z transforms of the input and output
+    plus the operator passes): isotropic phases (small strains) or the
+    neo-Hookean tangent at F = I (finite strains)."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case real_apply {kin} {prec} n={n}", flush=True)
+    rng = np.random.default_rng(200 + sum(n))
+    phase = (rng.random(n) < 0.35).astype(np.uint8)
+    u = rng.standard_normal((3,) + n)
+    if kin == "small":
+        E = [1.0, 7.0]
+        lam, mu = mt.lame(np.asarray(E)[phase], 0.3)
+        tan, okin = so.IsoTangent(lam, mu), so.SMALL
+        cell = Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 7.0, 0.3], precision=prec)
+    else:
+        tan, okin = _neo_tangent_at_identity(phase, [1.0, 10.0]), so.FINITE
+        cell = Cell(n, "neohooke", torch.from_numpy(phase), [1.0, 3.0, 10.0, 30.0], kinematics="finite",
+                    precision=prec)
+    with cell:
+        f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = _oracle_real_apply(n, tan, okin, u)
+    assert rel(f, ref) < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 54), (96, 6, 8), (6, 90, 8), (72, 4, 54)])
+def test_real_apply_aniso_lengths(gpu, n):
+    """Anisotropic grain stiffness (21 coefficients: the z pass that keeps
+    every component live)."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case real_apply aniso n={n}", flush=True)
+    rng = np.random.default_rng(210)
+    ng = 4
+    grain = rng.integers(0, ng, size=n).astype(np.int32)
+    A = rng.standard_normal((ng, 6, 6))
+    Cm = np.einsum("gab,gcb->gac", A, A) + 6 * np.eye(6)
+    u = rng.standard_normal((3,) + n)
+    with Cell(n, "aniso_grain", torch.from_numpy(grain), Cm.reshape(-1)) as cell:
+        f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = _oracle_real_apply(n, so.GeneralTangent(mt.mandel_to_tensor4(Cm[grain])), so.SMALL, u)
+    assert rel(f, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 90), (96, 6, 8), (6, 80, 8), (72, 4, 54)])
+def test_fourier_apply_lengths(gpu, n):
+    """The operator on Fourier unknowns with a macro strain (the fused z pass
+    as the PCG runs it) and its macroscopic row."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case fourier_apply n={n}", flush=True)
+    rng = np.random.default_rng(220)
+    phase = (rng.random(n) < 0.5).astype(np.uint8)
+    space = so.Space(n)
+    a = sp.fourier(rng.standard_normal((3,) + n), n)
+    a[:, space.Z] = 0
+    e = rng.standard_normal((3, 3)) * 0.1
+    e = 0.5 * (e + e.T)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), [2.0, 0.25, 5.0, 0.25]) as cell:
+        f, sig = cell.apply_fourier(torch.from_numpy(a).cuda(), e)
+        f = f.cpu().numpy()
+    lam, mu = mt.lame(np.array([2.0, 5.0])[phase], 0.25)
+    r, dc = space.divergence_residual(so.IsoTangent(lam, mu).stress(space.field_of(a, np.zeros(0), e)))
+    assert rel(f, -r) < 1e-12
+    assert rel(sig, dc) < 1e-12
+
+
+def _oracle_neo(n, phase, mus, Fbar, ninc, mask=None):
+    mus = np.asarray(mus, dtype=float)
+    lams = 3.0 * mus - 2.0 * mus / 3.0
+    loads = [(Fbar - np.eye(3)) * (k + 1) / ninc for k in range(ninc)]
+    if mask is not None:
+        loads = [np.where(mask, 0.0, L) for L in loads]
+    _, _, _, info = so.newton(n, so.NeoHookeLaw(mus[phase], lams[phase]), loads, mask, kin=so.FINITE, tol=1e-12,
+                              tol_load=1e-12, newton_tol=1e-11)
+    assert info.converged
+    return info
+
+
+@pytest.mark.parametrize("n", [(6, 5, 48), (4, 6, 96), (54, 4, 6), (5, 90, 4)])
+def test_neohooke_newton_lengths(gpu, n):
+    """Finite-strain Newton (Sec. 2.4) on one cell at the workload lengths:
+    FP64 against the oracle's Newton at tol 1e-12, FP32-mixed on the
+    homogenized stress."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case neohooke newton n={n}", flush=True)
+    rng = np.random.default_rng(230)
+    phase = (rng.random(n) < 0.3).astype(np.uint8)
+    mus = [1.0, 10.0]
+    Fbar = np.diag([1.1, 1.0, 1.0])
+    Fbar[0, 1] = 0.02
+    info = _oracle_neo(n, phase, mus, Fbar, 2)
+    params = [1.0, 3.0, 10.0, 30.0]
+    with Cell(n, "neohooke", torch.from_numpy(phase), params, kinematics="finite") as cell:
+        gi = cell.solve(Fbar, None, n_increments=2, tol=1e-12, tol_load=1e-12, newton_tol=1e-11)
+    assert gi["status"] == 0
+    assert rel(gi["sigma_bar"], info.sigma_bar[-1]) < 1e-9
+    with Cell(n, "neohooke", torch.from_numpy(phase), params, kinematics="finite", precision="fp32_mixed") as cell:
+        gi = cell.solve(Fbar, None, n_increments=2, tol=1e-10, tol_load=1e-10, newton_tol=1e-10)
+    assert gi["status"] == 0
+    assert rel(gi["sigma_bar"], info.sigma_bar[-1]) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+def test_batch_neohooke_lengths_vs_oracle(gpu, prec):
+    """Batched Newton over cells that carry the batch workload's lengths on
+    every axis (batched two-step x, y and z passes), each cell against the
+    oracle's own Newton solve, not against another GPU path."""
+    import torch
+    from paper_1905_12725_amd.api import Batch, Cell
+    shapes = [(54, 4, 6), (6, 72, 4), (4, 6, 80), (6, 4, 90), (4, 4, 96), (96, 6, 4), (4, 90, 6), (6, 6, 54)]
+    print(f"case batch neohooke lengths {prec}", flush=True)
+    mus = [1.0, 10.0]
+    Fbar = np.diag([1.1, 1.0, 1.0])
+    cells, refs = [], []
+    for i, n in enumerate(shapes):
+        phase = (np.random.default_rng(240 + i).random(n) < 0.3).astype(np.uint8)
+        refs.append(_oracle_neo(n, phase, mus, Fbar, 2).sigma_bar[-1])
+        cells.append(Cell(n, "neohooke", torch.from_numpy(phase), [1.0, 3.0, 10.0, 30.0], kinematics="finite",
+                          precision=prec))
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    with Batch(cells) as b:
+        infos = b.solve([Fbar] * len(cells), None, n_increments=2, tol=tol, tol_load=tol, newton_tol=1e-11)
+    bar = 1e-9 if prec == "fp64" else 1e-6
+    for i, n in enumerate(shapes):
+        err = rel(infos[i]["sigma_bar"], refs[i])
+        print(f"  {n}: newton {infos[i]['newton_iters']} pcg {infos[i]['pcg_iters']} rel {err:.2e}", flush=True)
+        assert infos[i]["status"] == 0
+        assert err < bar, n
+    for c in cells:
+        c.close()

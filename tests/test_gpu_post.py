@@ -1,0 +1,189 @@
+"""Failure statuses and post-processing outputs of the HIP path against the
+oracle.
+
+  * The iteration cap of Sec. 3.1 (ENOTCONV, with the info filled) for the
+    linear PCG, FP64 and FP32-mixed, for Newton and for a batch.
+  * CG breakdown (EBREAKDOWN): a voxel with a negative modulus makes the
+    tangent indefinite (the oracle breaks down on its first step); a NaN
+    modulus makes <p, K p> NaN.  Both are normal status returns, and the
+    library keeps working afterwards.
+  * dbfft_homogenize's fields (Sec. 2.2 eqs. disp_decomp and strain_decomp):
+    strain (or displacement gradient), stress (or first Piola-Kirchhoff
+    stress) and displacement fluctuation against the oracle's fields, on
+    z lengths served by the two-step real z transforms and by the others.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_12725_amd import microstructure as ms
+from oracle import spectral as sp, solver as so, materials as mt
+
+pytestmark = pytest.mark.gpu
+
+ENOTCONV, EBREAKDOWN = 4, 5
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _sphere_cell(n, prec="fp64"):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    phase = ms.centred_sphere(n, 0.2)
+    return phase, Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 10.0, 0.3], precision=prec)
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+def test_iteration_cap_linear_fp64(gpu, fused):
+    """max_iter = 3: status ENOTCONV after exactly three iterations; the
+    residual reported equals the oracle's after its three iterations."""
+    n = (16, 16, 16)
+    print(f"case enotconv linear fp64 fused={fused}", flush=True)
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3
+    phase, cell = _sphere_cell(n)
+    with cell:
+        info = cell.solve(load, tol=1e-12, tol_load=1e-12, max_iter=3, fused_cg=fused, raise_on_fail=False)
+    assert info["status"] == ENOTCONV
+    assert info["pcg_iters"] == 3
+    lam, mu = mt.lame(np.where(phase == 1, 10.0, 1.0), 0.3)
+    ref = so.solve_linear(n, so.IsoTangent(lam, mu), load, tol=1e-12, tol_load=1e-12, max_iter=3)
+    assert not ref.info.converged and ref.info.iterations == 3
+    assert abs(info["eq_res"] - ref.info.eq_res) < 1e-9 * ref.info.eq_res
+    assert rel(info["sigma_bar"], ref.sigma_bar) < 1e-12
+
+
+def test_iteration_cap_linear_fp32_mixed(gpu):
+    n = (16, 16, 16)
+    print("case enotconv linear fp32", flush=True)
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3
+    _, cell = _sphere_cell(n, "fp32_mixed")
+    with cell:
+        info = cell.solve(load, tol=1e-12, tol_load=1e-12, max_iter=3, raise_on_fail=False)
+    assert info["status"] == ENOTCONV
+    assert info["pcg_iters"] <= 3
+    assert np.isfinite(info["eq_res"]) and info["eq_res"] > 1e-12
+
+
+def test_iteration_cap_newton(gpu):
+    """max_newton = 1 on a neo-Hookean stretch that needs several Newton
+    iterations: ENOTCONV with the increments and iterations reported."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (8, 8, 8)
+    print("case enotconv newton", flush=True)
+    phase = ms.centred_sphere(n, 0.2)
+    with Cell(n, "neohooke", torch.from_numpy(phase), [1.0, 3.0, 10.0, 30.0], kinematics="finite") as cell:
+        info = cell.solve(np.diag([1.2, 1.0, 1.0]), None, n_increments=1, max_newton=1, raise_on_fail=False)
+    assert info["status"] == ENOTCONV
+    assert info["newton_iters"] == 1
+    assert info["increments"] == 0
+
+
+def test_iteration_cap_batch(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Batch, Cell
+    print("case enotconv batch", flush=True)
+    cells = []
+    for n in [(16, 16, 16), (12, 10, 8)]:
+        phase = ms.centred_sphere(n, 0.2)
+        cells.append(Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 10.0, 0.3]))
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3
+    with Batch(cells) as b:
+        infos = b.solve([load] * 2, None, tol=1e-12, tol_load=1e-12, max_iter=3, raise_on_fail=False)
+    for inf in infos:
+        assert inf["status"] == ENOTCONV
+        assert inf["pcg_iters"] == 3
+    for c in cells:
+        c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("bad", ["negative", "nan"])
+def test_breakdown_status(gpu, bad, prec):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (8, 8, 8)
+    print(f"case ebreakdown {bad} {prec}", flush=True)
+    E = np.ones(n)
+    E[0, 0, 0] = -50.0 if bad == "negative" else np.nan
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3
+    if bad == "negative":
+        lam, mu = mt.lame(E, 0.3)
+        ref = so.solve_linear(n, so.IsoTangent(lam, mu), load, tol=1e-12, tol_load=1e-12, max_iter=200)
+        assert ref.info.breakdown and ref.info.iterations == 0
+    with Cell(n, "iso_field", torch.from_numpy(E), [0.3], precision=prec) as cell:
+        info = cell.solve(load, tol=1e-12, tol_load=1e-12, max_iter=200, raise_on_fail=False)
+    assert info["status"] == EBREAKDOWN
+    assert info["pcg_iters"] == 0
+    # the library keeps working: a sound cell solves normally afterwards
+    phase, cell = _sphere_cell((8, 8, 8), prec)
+    with cell:
+        ok = cell.solve(load, tol=1e-10, tol_load=1e-10)
+    assert ok["status"] == 0
+
+
+def _oracle_linear(n, phase, E, nu, load, mask):
+    lam, mu = mt.lame(np.asarray(E)[phase], nu)
+    tan = so.IsoTangent(lam, mu)
+    res = so.solve_linear(n, tan, load, mask, tol=1e-13, tol_load=1e-13)
+    assert res.info.converged
+    eps = res.strain_field()
+    return res, eps, tan.stress(eps), sp.real_field(res.a, n)
+
+
+def _sym6(t):
+    """3x3 field -> the 6 stored components 11 22 33 23 13 12."""
+    return np.stack([t[0, 0], t[1, 1], t[2, 2], t[1, 2], t[0, 2], t[0, 1]])
+
+
+@pytest.mark.parametrize("n", [(12, 10, 16), (8, 6, 14), (6, 8, 15), (10, 8, 48), (6, 4, 96)])
+def test_homogenize_fields_small_strain(gpu, n):
+    """Mixed control (uniaxial stress: strain 11 prescribed, the other
+    stresses zero): strain, stress and displacement fluctuation fields."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case homogenize fields small n={n}", flush=True)
+    rng = np.random.default_rng(250)
+    phase = (rng.random(n) < 0.3).astype(np.uint8)
+    E = [1.0, 8.0]
+    mask = np.ones((3, 3), bool); mask[0, 0] = False
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3
+    res, eps, sig, u = _oracle_linear(n, phase, E, 0.3, load, mask)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 8.0, 0.3]) as cell:
+        cell.solve(load, mask, tol=1e-13, tol_load=1e-13)
+        h = cell.homogenize(strain=True, stress=True, displacement=True)
+    assert rel(h["strain"].cpu().numpy(), _sym6(eps)) < 1e-10
+    assert rel(h["stress"].cpu().numpy(), _sym6(sig)) < 1e-10
+    assert rel(h["displacement"].cpu().numpy(), u) < 1e-10
+    assert rel(h["sigma_bar"], res.sigma_bar) < 1e-10
+    assert rel(h["eps_bar"], res.eps_bar) < 1e-10
+
+
+@pytest.mark.parametrize("n", [(8, 6, 16), (6, 8, 15), (6, 5, 48)])
+def test_homogenize_fields_finite_strain(gpu, n):
+    """Neo-Hookean stretch: displacement gradient H = F - I, first
+    Piola-Kirchhoff stress P and displacement fluctuation."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case homogenize fields finite n={n}", flush=True)
+    rng = np.random.default_rng(251)
+    phase = (rng.random(n) < 0.3).astype(np.uint8)
+    mus = np.array([1.0, 10.0])
+    lams = 3.0 * mus - 2.0 * mus / 3.0
+    Fbar = np.diag([1.1, 1.0, 1.0])
+    loads = [(Fbar - np.eye(3)) * (k + 1) / 2 for k in range(2)]
+    a, e, st, info = so.newton(n, so.NeoHookeLaw(mus[phase], lams[phase]), loads, None, kin=so.FINITE,
+                               tol=1e-13, tol_load=1e-13, newton_tol=1e-12)
+    assert info.converged
+    space = so.Space(n, kin=so.FINITE)
+    H = space.field_of(a, e, loads[-1])
+    F = H + np.eye(3)[:, :, None, None, None]
+    P = mt.neohooke_stress(np.moveaxis(F, (0, 1), (-2, -1)), mus[phase], lams[phase])
+    P = np.moveaxis(P, (-2, -1), (0, 1))
+    with Cell(n, "neohooke", torch.from_numpy(phase), [1.0, 3.0, 10.0, 30.0], kinematics="finite") as cell:
+        cell.solve(Fbar, None, n_increments=2, tol=1e-13, tol_load=1e-13, newton_tol=1e-12)
+        h = cell.homogenize(strain=True, stress=True, displacement=True)
+    assert rel(h["strain"].cpu().numpy(), H.reshape((9,) + n)) < 1e-9
+    assert rel(h["stress"].cpu().numpy(), P.reshape((9,) + n)) < 1e-9
+    assert rel(h["displacement"].cpu().numpy(), sp.real_field(a, n)) < 1e-9
