@@ -161,6 +161,32 @@ dbfft_status dbfft_apply(dbfft_ctx* ctx, const double* u_dev, double* f_dev);
 dbfft_status dbfft_apply_fourier(dbfft_ctx* ctx, const void* a_dev, const double* e_macro, void* f_dev,
                                  double* sigma_bar_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the operator of
+ * dbfft_apply (FP64, small strains, elastic tangent) without a context.
+ * It calls no hipMalloc, hipFree or other allocating routine; its workspace
+ * (twiddle tables, 12 half-spectrum components, partial sums, a checked copy
+ * of the phase map) lives in a static device array of 64 MiB that every
+ * GPU the library runs on holds until the process ends.  Grids whose
+ * workspace exceeds it (about 12 n1 n2 (n3/2+1) x 16 bytes; 84^3 fits, 96^3
+ * does not) are rejected with DBFFT_EUNSUPPORTED before any GPU work.
+ * n: grid (host, 3 values, checked as in dbfft_setup); material
+ * DBFFT_MAT_ISO_PHASE (field_dev uint8 phase ids, params (E, nu) per phase)
+ * or DBFFT_MAT_ISO_FIELD (field_dev double E(x), params (nu)); u_dev, f_dev:
+ * device doubles [3][n1][n2][n3] as for dbfft_apply; hip_stream: the stream
+ * to enqueue on, whose device must be the current one.
+ * Unlike every other entry point it does not synchronize: it enqueues its
+ * kernels and returns, and f_dev is ready when the stream's work is done.
+ * The field is read in place, not copied: keep it valid until then.  Phase
+ * ids at or above the number of phases cannot be reported without reading
+ * device memory back: f_dev is then filled with NaN.  All calls on one GPU
+ * share its array, which keeps the last call's contents (every call clears
+ * what must start at zero): calls enqueued on one stream run one after the
+ * other, calls that overlap on one GPU (several streams or host threads)
+ * race and must not be made. */
+dbfft_status dbfft_apply_noalloc(const int64_t n[3], int32_t material, const void* field_dev, const double* params,
+                                 int32_t nparams, const double* u_dev, double* f_dev, void* hip_stream);
+
 /* Solves the cell problem (Sec. 2.2-2.5): PCG with the preconditioner
  * [xi.Cbar.xi]^-1 (eqs. pred2/pred3); Newton over increments for J2VP_CUBIC,
  * NEOHOOKE and SVK.  load: 9 host doubles, row-major; on components whose

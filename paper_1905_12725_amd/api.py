@@ -43,6 +43,32 @@ def _info_dict(info):
     }
 
 
+def apply_noalloc(n, material, field, params, u, out, stream=None):
+    """dbfft_apply_noalloc: the FP64 small-strain operator of Cell.apply for
+    an "iso_phase" or "iso_field" material, with no context and no device
+    allocation by the library (its workspace is a static device array).
+    `field`, `u` and `out` must already be contiguous device tensors of the
+    right dtype (uint8 or float64 field; float64 (3, n1, n2, n3) u and out).
+    Asynchronous: `out` is ready when `stream` (default: the current one)
+    has run the work."""
+    kind, dtype = _MAT[material]
+    if material not in ("iso_phase", "iso_field"):
+        raise ValueError("apply_noalloc takes iso_phase or iso_field materials")
+    n = tuple(int(v) for v in n)
+    for t, dt in ((field, dtype), (u, torch.float64), (out, torch.float64)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise ValueError("field, u and out must be contiguous device tensors of the documented dtypes")
+    if field.numel() != int(np.prod(n)) or u.shape != (3,) + n or out.shape != (3,) + n:
+        raise ValueError("shapes do not match the grid")
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device)
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    dims = (ct.c_int64 * 3)(*n)
+    nat.check(nat.lib().dbfft_apply_noalloc(dims, kind, _ptr(field), p.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                            int(p.size), _ptr(u), _ptr(out), ct.c_void_p(stream.cuda_stream)))
+    return out
+
+
 class Cell:
     """One periodic cell (grid + material) bound to a HIP stream."""
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1226,21 +1227,65 @@ static void release(Ctx* c) {
   if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
 }
 
-static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const void* field, const double* params,
-                  int nparams, void* stream) {
+// grid checks shared by every entry point that takes a grid: smooth sizes,
+// and the LDS limits of the x/y passes (one line plus twiddles per tile
+// column) and of the z pass (one z line of every component), 64 KiB each
+static void check_grid(const int64_t n[3], int kin) {
   if (!n) DB_THROW(DBFFT_EINVAL, "null grid size");
   for (int a = 0; a < 3; ++a)
     if (n[a] < 1 || n[a] > 4096 || !smooth(n[a])) DB_THROW(DBFFT_EINVAL, "grid sizes must be 2^a 3^b 5^c 7^d");
-  {
-    // the x/y passes keep one line (plus twiddles) of every tile column in
-    // LDS, the z pass one z line of every component: both within 64 KiB
-    const int nc = (kin == DBFFT_FINITE) ? 9 : 6;
-    for (int a = 0; a < 2; ++a)
-      if ((size_t)3 * n[a] * 16 > 64 * 1024) DB_THROW(DBFFT_EUNSUPPORTED, "n1 and n2 must be <= 1365");
-    const size_t M = (size_t)n[2] / 2;
-    if ((2 * M + 1) * 16 + 2 * M * 16 + (M + 1) * 16 + (size_t)nc * n[2] * 8 > 64 * 1024)
-      DB_THROW(DBFFT_EUNSUPPORTED, "n3 too large for the z pass");
+  const int nc = (kin == DBFFT_FINITE) ? 9 : 6;
+  for (int a = 0; a < 2; ++a)
+    if ((size_t)3 * n[a] * 16 > 64 * 1024) DB_THROW(DBFFT_EUNSUPPORTED, "n1 and n2 must be <= 1365");
+  const size_t M = (size_t)n[2] / 2;
+  if ((2 * M + 1) * 16 + 2 * M * 16 + (M + 1) * 16 + (size_t)nc * n[2] * 8 > 64 * 1024)
+    DB_THROW(DBFFT_EUNSUPPORTED, "n3 too large for the z pass");
+}
+
+// geometry and transform plans of a checked grid (host only, allocates nothing)
+static void init_grid(Ctx* c, const int64_t n[3], int kin, int prec, int mat, void* stream) {
+  for (int a = 0; a < 3; ++a) c->n[a] = (int)n[a];
+  c->kin = kin;
+  c->prec = prec;
+  c->mat = mat;
+  c->ncomp = (kin == DBFFT_SMALL) ? 6 : 9;
+  c->st = static_cast<hipStream_t>(stream);
+  Geom& g = c->g;
+  g.n1 = c->n[0];
+  g.n2 = c->n[1];
+  g.n3 = c->n[2];
+  g.nh3 = g.n3 / 2 + 1;
+  g.nh = (long long)g.n1 * g.n2 * g.nh3;
+  g.nvox = (long long)g.n1 * g.n2 * g.n3;
+  g.inv_nvox = 1.0 / (double)g.nvox;
+  if (!make_plan(g.n1, c->p1) || !make_plan(g.n2, c->p2) || !make_plan(z_length(g.n3), c->p3))
+    DB_THROW(DBFFT_EINVAL, "cannot plan the transform lengths");
+}
+
+// partial sums any kernel of a context writes (energy, CG dots, mean tangent)
+static int partial_count(const Geom& g) {
+  const int zparts = std::max(mixed_line_supported(g.n3, 16, true) ? mixed_line_energy_blocks(g, true) : 0,
+                              odd_line_supported(g.n3) ? odd_line_energy_blocks(g) : 0);
+  return std::max(std::max(std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
+                                    tangent_mean_block_count(g) * 81),
+                           fused_cg_partials(g)),
+                  zparts) + 64;
+}
+
+// Lame constants of the (E, nu) pairs of an isotropic phase table
+static void iso_phase_table(const double* params, int nparams, int& nphase, double* lam, double* mu) {
+  if (nparams % 2 != 0 || nparams / 2 > kMaxPhases) DB_THROW(DBFFT_EINVAL, "phase parameters: pairs, at most 8 phases");
+  nphase = nparams / 2;
+  for (int p = 0; p < nphase; ++p) {
+    const double a = params[2 * p], b = params[2 * p + 1];
+    lam[p] = a * b / ((1.0 + b) * (1.0 - 2.0 * b));
+    mu[p] = a / (2.0 * (1.0 + b));
   }
+}
+
+static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const void* field, const double* params,
+                  int nparams, void* stream) {
+  check_grid(n, kin);
   if (kin != DBFFT_SMALL && kin != DBFFT_FINITE) DB_THROW(DBFFT_EINVAL, "unknown kinematics");
   if (prec != DBFFT_FP64 && prec != DBFFT_FP32_MIXED) DB_THROW(DBFFT_EINVAL, "unknown precision");
   if (mat < 0 || mat > DBFFT_MAT_SVK) DB_THROW(DBFFT_EINVAL, "unknown material kind");
@@ -1250,22 +1295,8 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
   if (!params || nparams < 1) DB_THROW(DBFFT_EINVAL, "null material parameters");
 
   {
-    for (int a = 0; a < 3; ++a) c->n[a] = (int)n[a];
-    c->kin = kin;
-    c->prec = prec;
-    c->mat = mat;
-    c->ncomp = (kin == DBFFT_SMALL) ? 6 : 9;
-    c->st = static_cast<hipStream_t>(stream);
+    init_grid(c, n, kin, prec, mat, stream);
     Geom& g = c->g;
-    g.n1 = c->n[0];
-    g.n2 = c->n[1];
-    g.n3 = c->n[2];
-    g.nh3 = g.n3 / 2 + 1;
-    g.nh = (long long)g.n1 * g.n2 * g.nh3;
-    g.nvox = (long long)g.n1 * g.n2 * g.n3;
-    g.inv_nvox = 1.0 / (double)g.nvox;
-    if (!make_plan(g.n1, c->p1) || !make_plan(g.n2, c->p2) || !make_plan(z_length(g.n3), c->p3))
-      DB_THROW(DBFFT_EINVAL, "cannot plan the transform lengths");
     std::vector<double> re, im;
     twiddles(g.n1, g.n1, g.n1, re, im);
     c->td.tw1 = upload_table<double>(re, im);
@@ -1284,18 +1315,13 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
     const long long N = g.nvox;
     // material
     if (mat == DBFFT_MAT_ISO_PHASE || mat == DBFFT_MAT_NEOHOOKE || mat == DBFFT_MAT_SVK) {
-      if (nparams % 2 != 0 || nparams / 2 > kMaxPhases) DB_THROW(DBFFT_EINVAL, "phase parameters: pairs, at most 8 phases");
-      c->nphase = nparams / 2;
-      for (int p = 0; p < c->nphase; ++p) {
-        const double a = params[2 * p], b = params[2 * p + 1];
-        if (mat == DBFFT_MAT_ISO_PHASE || mat == DBFFT_MAT_SVK) {
-          c->lam[p] = a * b / ((1.0 + b) * (1.0 - 2.0 * b));
-          c->mu[p] = a / (2.0 * (1.0 + b));
-        } else {
-          c->mu[p] = a;
-          c->lam[p] = b - 2.0 * a / 3.0;
+      iso_phase_table(params, nparams, c->nphase, c->lam, c->mu);
+      if (mat == DBFFT_MAT_NEOHOOKE)
+        for (int p = 0; p < c->nphase; ++p) {
+          // (mu, kappa) pairs: lambda = kappa - 2 mu / 3
+          c->mu[p] = params[2 * p];
+          c->lam[p] = params[2 * p + 1] - 2.0 * params[2 * p] / 3.0;
         }
-      }
       std::vector<uint8_t> hp(N);
       HIPCK(hipMemcpy(hp.data(), field, N, hipMemcpyDeviceToHost));
       for (long long v = 0; v < N; ++v)
@@ -1430,12 +1456,7 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
       HIPCK(hipMemcpy(c->tanf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
       launch_convert<double, float>(c->tanf32, c->tanf, 10 * N, c->st);
     }
-    const int zparts = std::max(mixed_line_supported(g.n3, 16, true) ? mixed_line_energy_blocks(g, true) : 0,
-                                odd_line_supported(g.n3) ? odd_line_energy_blocks(g) : 0);
-    const int nparts = std::max(std::max(std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
-                                                  tangent_mean_block_count(g) * 81),
-                                         fused_cg_partials(g)),
-                                zparts) + 64;
+    const int nparts = partial_count(g);
     c->npart = nparts;
     c->partA = static_cast<double*>(dalloc(nparts * sizeof(double)));
     c->partB = static_cast<double*>(dalloc(nparts * sizeof(double)));
@@ -1942,6 +1963,118 @@ static void batch_release(Batch* B) {
   if (B->st) (void)hipStreamDestroy(B->st);
 }
 
+// ------------------------------------------------------------------ allocation-free apply
+// dbfft_apply_noalloc keeps everything beyond the caller's inputs and
+// outputs in this array: twiddle tables, the spectral workspace (6 + 3 + 3
+// half-spectrum components), partial sums, the macro block, a status word
+// and a checked copy of the phase map.  Every GPU the library runs on holds
+// its own copy until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress gives on that device (the array's name
+// is a host-side stand-in there, not a device address).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {nullptr};
+
+// device address of `scratch` on the current device, looked up once per device
+static unsigned char* scratch_on_current_device() {
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) DB_THROW(DBFFT_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    HIPCK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (ptr == nullptr) DB_THROW(DBFFT_EHIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
+
+// Twiddle tables w(k) = exp(-2 pi i k / denom), k < count, of the four
+// transform axes (the values the context tables hold, computed on the
+// device), and zeros over the macro block, the DC output and the status word.
+struct TwiddleSegs {
+  double* p[4];
+  int denom[4];
+  int count[4];
+};
+
+__global__ void k_noalloc_init(TwiddleSegs ts, double* zero, int nzero) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
+  for (int a = 0; a < 4; ++a)
+    for (int k = gid; k < ts.count[a]; k += gs) {
+      double sn, cs;
+      sincospi(2.0 * (double)k / (double)ts.denom[a], &sn, &cs);
+      ts.p[a][2 * k] = cs;
+      ts.p[a][2 * k + 1] = -sn;
+    }
+  for (int i = gid; i < nzero; i += gs) zero[i] = 0.0;
+}
+
+// copy of the phase map with out-of-range ids replaced by 0 and flagged
+__global__ void k_noalloc_phase(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, long long n, int nphase,
+                                int* __restrict__ bad) {
+  int seen = 0;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+    uint8_t ph = in[v];
+    if (ph >= nphase) {
+      ph = 0;
+      seen = 1;
+    }
+    out[v] = ph;
+  }
+  if (seen) *bad = 1;
+}
+
+// NaN over the output when the phase check flagged an id
+__global__ void k_noalloc_poison(double* __restrict__ f, long long n, const int* __restrict__ bad) {
+  if (*bad == 0) return;
+  const double nan = __builtin_nan("");
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x)
+    f[v] = nan;
+}
+
+// Carves the scratch array for one grid: returns the bytes needed and, when
+// `base` is not null, sets the context's tables and workspaces to point into it.
+struct NoallocLayout {
+  double* zero;      // macro block (16), DC output (16), status word (as int)
+  int nzero;
+  uint8_t* phase;
+  size_t bytes;
+};
+
+static NoallocLayout noalloc_layout(Ctx& c, unsigned char* base, bool phase_copy) {
+  size_t off = 0;
+  auto take = [&](size_t nbytes) -> unsigned char* {
+    unsigned char* p = base ? base + off : nullptr;
+    off += (nbytes + 255) / 256 * 256;
+    return p;
+  };
+  const Geom& g = c.g;
+  const int Z = z_length(g.n3), M = g.n3 / 2;
+  c.td.tw1 = take((size_t)g.n1 * 16);
+  c.td.tw2 = take((size_t)g.n2 * 16);
+  c.td.tw3 = take((size_t)std::max(Z, 1) * 16);
+  c.td.rtw = take((size_t)(M + 1) * 16);
+  NoallocLayout L;
+  L.nzero = 40;
+  L.zero = reinterpret_cast<double*>(take((size_t)L.nzero * sizeof(double)));
+  c.mac_dev = L.zero;
+  c.dc_dev = L.zero ? L.zero + 16 : nullptr;
+  c.npart = (size_t)partial_count(g);
+  c.partA = reinterpret_cast<double*>(take(c.npart * sizeof(double)));
+  L.phase = phase_copy ? take((size_t)g.nvox) : nullptr;
+  const size_t vb = 3 * (size_t)g.nh * 2 * sizeof(double);
+  c.W = take(2 * vb);
+  c.p = take(vb);
+  c.q = take(vb);
+  L.bytes = off;
+  return L;
+}
+
 }  // namespace dbfft
 
 using namespace dbfft;
@@ -2067,6 +2200,73 @@ dbfft_status dbfft_apply(dbfft_ctx* ctx, const double* u_dev, double* f_dev) {
   }
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(c.st));
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_apply_noalloc(const int64_t n[3], int32_t material, const void* field_dev, const double* params,
+                                 int32_t nparams, const double* u_dev, double* f_dev, void* hip_stream) {
+  g_err.clear();
+  API_BEGIN
+  if (!n || !field_dev || !params || !u_dev || !f_dev) DB_THROW(DBFFT_EINVAL, "null argument");
+  check_grid(n, DBFFT_SMALL);
+  if (material != DBFFT_MAT_ISO_PHASE && material != DBFFT_MAT_ISO_FIELD)
+    DB_THROW(DBFFT_EUNSUPPORTED, "dbfft_apply_noalloc takes ISO_PHASE or ISO_FIELD materials");
+  if (nparams < 1) DB_THROW(DBFFT_EINVAL, "null material parameters");
+  Ctx c;
+  init_grid(&c, n, DBFFT_SMALL, DBFFT_FP64, material, hip_stream);
+  TangentArgs<double> tan;
+  std::memset(&tan, 0, sizeof(tan));
+  if (material == DBFFT_MAT_ISO_PHASE) {
+    tan.kind = TAN_ISO_PHASE;
+    iso_phase_table(params, nparams, tan.nphase, tan.lam, tan.mu);
+  } else {
+    tan.kind = TAN_ISO_FIELD;
+    const double nu = params[0];
+    tan.lam1 = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    tan.mu1 = 1.0 / (2.0 * (1.0 + nu));
+    tan.field = static_cast<const double*>(field_dev);
+  }
+  const bool by_phase = material == DBFFT_MAT_ISO_PHASE;
+  const size_t need = noalloc_layout(c, nullptr, by_phase).bytes;
+  if (need > kScratchBytes)
+    DB_THROW(DBFFT_EUNSUPPORTED, "grid needs " + std::to_string(need) + " bytes of device scratch, above the " +
+                                     std::to_string(kScratchBytes) +
+                                     " bytes dbfft_apply_noalloc holds; use dbfft_setup and dbfft_apply");
+  unsigned char* base = scratch_on_current_device();
+  const NoallocLayout L = noalloc_layout(c, base, by_phase);
+  const Geom& g = c.g;
+  const long long N = g.nvox;
+  int* bad = reinterpret_cast<int*>(L.zero + 32);
+  TwiddleSegs ts;
+  const int Z = z_length(g.n3), M = g.n3 / 2;
+  const void* tabs[4] = {c.td.tw1, c.td.tw2, c.td.tw3, c.td.rtw};
+  const int denom[4] = {g.n1, g.n2, std::max(Z, 1), g.n3}, count[4] = {g.n1, g.n2, std::max(Z, 1), M + 1};
+  for (int a = 0; a < 4; ++a) {
+    ts.p[a] = static_cast<double*>(const_cast<void*>(tabs[a]));
+    ts.denom[a] = denom[a];
+    ts.count[a] = count[a];
+  }
+  hipLaunchKernelGGL(k_noalloc_init, dim3(16), dim3(256), 0, c.st, ts, L.zero, L.nzero);
+  const int vb = (int)std::min<long long>((N + 255) / 256, 2048);
+  if (by_phase) {
+    hipLaunchKernelGGL(k_noalloc_phase, dim3(vb), dim3(256), 0, c.st, static_cast<const uint8_t*>(field_dev),
+                       L.phase, N, tan.nphase, bad);
+    tan.phase = L.phase;
+  }
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  Tables<double>& tb = c.td;
+  launch_line<double>(LP_R2C, c.kin, u_dev, c.W, g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3, c.st,
+                      nullptr, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, 3, sy, g, c.p2, tb.tw2, -1, nullptr, c.st, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.p, 3, sx, g, c.p1, tb.tw1, -1, nullptr, c.st, nullptr);
+  apply_K<double>(c, c.p, c.q, c.mac_dev, nullptr, tan, c.partA, c.dc_dev, nullptr);
+  launch_strided<double>(SP_PLAIN, c.q, c.W, 3, sx, g, c.p1, tb.tw1, +1, nullptr, c.st, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, 3, sy, g, c.p2, tb.tw2, +1, nullptr, c.st, nullptr);
+  launch_line<double>(LP_C2R, c.kin, c.W, f_dev, g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, 3, c.st,
+                      nullptr, nullptr);
+  if (by_phase) hipLaunchKernelGGL(k_noalloc_poison, dim3(vb), dim3(256), 0, c.st, f_dev, 3 * N, bad);
+  HIPCK(hipGetLastError());
   return DBFFT_OK;
   API_END
 }

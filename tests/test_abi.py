@@ -107,3 +107,15 @@ def test_null_handles_are_rejected():
     assert lib.dbfft_batch_create(None, None, 0, 1) == 1
     assert lib.dbfft_batch_solve(None, load, mask, 1, 1.0, None, ctypes.byref(info)) == 1
     lib.dbfft_destroy(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdbfft.so not built")
+def test_apply_noalloc_rejects_null_arguments_without_gpu():
+    """The allocation-free apply checks its arguments before any GPU call."""
+    from paper_1905_12725_amd import _native
+    lib = _native.lib()
+    n = (ctypes.c_int64 * 3)(8, 8, 8)
+    params = (ctypes.c_double * 2)(1.0, 0.3)
+    assert lib.dbfft_apply_noalloc(n, 0, None, params, 2, None, None, None) == 1
+    assert lib.dbfft_apply_noalloc(None, 0, None, params, 2, None, None, None) == 1
+    assert "null" in lib.dbfft_last_error().decode()
