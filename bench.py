@@ -127,42 +127,87 @@ def ceff(cols):
     return M / 1e-3
 
 
-def cpu_baseline(n, phase, E, nu, loads, seconds):
-    """The oracle (NumPy, FP64) doing CG iterations of the same problem."""
+def cpu_worker(case, n, seconds):
+    """One oracle process of the CPU baseline: builds load case `case` of
+    the bench cell, reports "ready", waits for "go" on stdin, then runs CG
+    iterations for about `seconds` (sized by the time of the right-hand
+    side's operator application) and prints its iterations, wall and CPU
+    time as JSON."""
     import psutil
+    from paper_1905_12725_amd import microstructure as ms
     from oracle import materials as omt, solver as oso
-    lam, mu = omt.lame(np.asarray(E)[phase], nu)
+    phase, _, _ = ms.random_spheres(n, 2, 6.0, 10.0, 0.30)
+    lam, mu = omt.lame(np.asarray([1.0, 100.0])[phase], 0.3)
     tan = oso.IsoTangent(lam, mu)
     space = oso.Space(n)
-    proc = psutil.Process()
-    L = loads[0]
+    L = mandel_loads()[case]
     t0 = time.perf_counter()
     (ka, _), dc0 = space.apply(space.zeros(), tan, L)
+    t_apply = time.perf_counter() - t0
     b = (-ka, np.zeros(0))
     M = space.preconditioner(tan.mean())
-    t1 = time.perf_counter()
-    # one iteration to size the sample
-    c0 = proc.cpu_times()
-    w0 = time.perf_counter()
-    _, _, info = oso.pcg(space, tan, M, b, dc0, tol=0.0, tol_load=0.0, max_iter=1)
-    one = time.perf_counter() - w0
-    k = max(2, int(seconds / max(one, 1e-3)))
+    k = max(1, int(round(seconds / max(t_apply, 1e-3))))
+    print("ready", flush=True)
+    sys.stdin.readline()
+    proc = psutil.Process()
     c0 = proc.cpu_times()
     w0 = time.perf_counter()
     _, _, info = oso.pcg(space, tan, M, b, dc0, tol=0.0, tol_load=0.0, max_iter=k)
     wall = time.perf_counter() - w0
     c1 = proc.cpu_times()
-    cpu = (c1.user - c0.user) + (c1.system - c0.system)
-    cores = max(1, int(round(cpu / wall)))
+    print(json.dumps({"iters": info.iterations, "wall": wall,
+                      "cpu": (c1.user - c0.user) + (c1.system - c0.system)}), flush=True)
+
+
+def cpu_baseline(n, seconds):
+    """The oracle (NumPy, FP64) doing CG iterations of the bench workload on
+    the host's cores: one process per load case (six, or fewer when the
+    host has fewer cores), the host's cores split evenly between them as
+    BLAS threads.  The processes build their problems, start together, and
+    the rate is their summed iterations over the wall time from the start
+    to the last one's end."""
+    import subprocess
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nproc = max(1, min(6, ncpu))
+    threads = max(1, ncpu // nproc)
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[v] = str(threads)
+    env["HIP_VISIBLE_DEVICES"] = ""  # the oracle processes never touch the GPU
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(j),
+                               "--n", str(n[0]), "--cpu-seconds", str(seconds)],
+                              stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+             for j in range(nproc)]
+    try:
+        for pr in procs:
+            line = pr.stdout.readline()
+            if line.strip() != "ready":
+                raise RuntimeError(f"oracle worker did not start: {line!r}")
+        w0 = time.perf_counter()
+        for pr in procs:
+            pr.stdin.write("go\n")
+            pr.stdin.flush()
+        res = [json.loads(pr.stdout.readline()) for pr in procs]
+        wall = time.perf_counter() - w0
+    finally:
+        for pr in procs:
+            try:
+                pr.stdin.close()
+            except OSError:
+                pass
+            pr.wait(timeout=600)
+    iters = sum(r["iters"] for r in res)
+    cpu = sum(r["cpu"] for r in res)
     return {
-        "value": info.iterations / wall,
+        "value": iters / wall,
         "unit": "applies/s",
-        "cores": cores,
+        "cores": max(1, int(round(cpu / wall))),
         "kind": "oracle",
-        "sample": f"{info.iterations} CG iterations (one operator application each) of load case 11 "
-                  f"of the same {n[0]}^3 cell, FP64 NumPy oracle, {wall:.1f} s wall; "
-                  f"setup {t1 - t0:.1f} s not counted",
-        "host_cpu_count": os.cpu_count(),
+        "sample": f"{iters} CG iterations (one operator application each) of the same {n[0]}^3 cell, "
+                  f"{nproc} oracle processes (one load case each, {threads} BLAS thread{'s' if threads > 1 else ''} each) started "
+                  f"together, {wall:.1f} s wall, {cpu:.1f} s CPU; setup not counted",
+        "host_cpu_count": ncpu,
+        "processes": nproc,
     }
 
 
@@ -170,11 +215,12 @@ def batched_leg(log, ncell=32, ninc=10, seed=4, only_batched=False):
     """Uneven batch: `ncell` cubic cells with sizes drawn from the even
     2-3-5-smooth sizes in [32, 96], each a neo-Hookean two-phase sphere
     composite (centred sphere at 20 %, mu 1 / 10, kappa = 3 mu), stretched to
-    F11 = 1.1 in `ninc` increments under strain control.  Times the batched
-    FP32-mixed solve (one launch per pass over all cells, graph-replayed PCG
-    chunks, autotuned tiles) against the same cells solved one after the
-    other in plain FP64; both at PCG tol 1e-6 and Newton tol 1e-7, errors
-    against a batched FP64 solve at 1e-10.  `only_batched` runs the batched
+    F11 = 1.1 in `ninc` increments under strain control.  Times four legs:
+    the cells solved one after the other and as one batch (one launch per
+    pass over all cells, graph-replayed PCG chunks, autotuned tiles), each
+    in plain FP64 and in FP32-mixed, so that the gain of batching and the
+    gain of precision are reported apart; all at PCG tol 1e-6 and Newton
+    tol 1e-7, errors against a batched FP64 solve at 1e-10.  `only_batched` runs the batched
     FP32-mixed solve alone (no reference, no sequential leg), for profiling."""
     import torch
     from paper_1905_12725_amd import microstructure as ms
@@ -219,26 +265,37 @@ def batched_leg(log, ncell=32, ninc=10, seed=4, only_batched=False):
 
     t64, i64 = timed(lambda: [c.solve(Fbar, None, n_increments=ninc, **opts) for c in c64])
     log(f"[bench] batch workload: sequential FP64 {t64:.3f} s")
+    with Batch(c64) as b:
+        tb64, ib64 = timed(lambda: b.solve([Fbar] * ncell, None, n_increments=ninc, **opts))
+    log(f"[bench] batch workload: batched FP64 {tb64:.3f} s")
     for c in c64:
         c.close()
     c32 = make("fp32_mixed")
+    t32, i32 = timed(lambda: [c.solve(Fbar, None, n_increments=ninc, **opts) for c in c32])
+    log(f"[bench] batch workload: sequential FP32-mixed {t32:.3f} s")
     b32 = Batch(c32)
     tb, ib = timed(lambda: b32.solve([Fbar] * ncell, None, n_increments=ninc, **opts))
     log(f"[bench] batch workload: batched FP32-mixed {tb:.3f} s")
     b32.close()
     for c in c32:
         c.close()
+
+    def leg(t, infos):
+        return {"time_s": t, "sigma_rel_err": err(infos), "pcg_iters": int(sum(i["pcg_iters"] for i in infos)),
+                "newton_iters": int(sum(i["newton_iters"] for i in infos))}
     return {
         "workload": f"{ncell} neo-Hookean sphere composites, cubic grids from the 2-3-5-smooth even sizes in "
                     f"[32, 96] (seed {seed}), F11 = 1.1 in {ninc} increments, strain control",
         "sizes": sizes,
         "voxels": int(sum(s ** 3 for s in sizes)),
-        "sequential_fp64": {"time_s": t64, "sigma_rel_err": err(i64),
-                            "pcg_iters": int(sum(i["pcg_iters"] for i in i64)),
-                            "newton_iters": int(sum(i["newton_iters"] for i in i64))},
-        "batched_fp32_mixed": {"time_s": tb, "sigma_rel_err": err(ib),
-                               "pcg_iters": int(sum(i["pcg_iters"] for i in ib)),
-                               "newton_iters": int(sum(i["newton_iters"] for i in ib))},
+        "sequential_fp64": leg(t64, i64),
+        "batched_fp64": leg(tb64, ib64),
+        "sequential_fp32_mixed": leg(t32, i32),
+        "batched_fp32_mixed": leg(tb, ib),
+        "speedup_batching_fp64": t64 / tb64,
+        "speedup_batching_fp32_mixed": t32 / tb,
+        "speedup_precision_sequential": t64 / t32,
+        "speedup_precision_batched": tb64 / tb,
         "speedup_batched_fp32_mixed_vs_sequential_fp64": t64 / tb,
         "target_sigma_rel_err": 1e-6,
     }
@@ -516,6 +573,58 @@ def contrast_sweep(log, grids=((63, 63, 63), (64, 64, 64))):
     return out
 
 
+# PCG tolerances tried, loosest first (about four per decade)
+TOL_SWEEP = (1.0, 0.5, 0.3, 0.2, 0.1, 0.05, 0.03, 0.02, 0.01, 5e-3, 3e-3, 2e-3, 1e-3, 5e-4, 3e-4, 2e-4, 1e-4,
+             5e-5, 3e-5, 2e-5, 1e-5, 5e-6, 3e-6, 2e-6, 1e-6, 1e-7, 1e-8)
+
+
+def bracket_equal_accuracy(cell, mixed, loads, err, fo, log, target=1e-6, repeats=3):
+    """Each precision timed at the loosest PCG tolerance whose effective
+    stiffness meets `target` (max relative error against the tight FP64
+    reference).  Tolerances are tried loosest first; the first that meets
+    the target is timed `repeats` times (median), and the tolerance tried
+    just before it (which missed) is reported beside it, so the chosen
+    tolerance is bracketed.  FP32-mixed also sweeps the inner FP32 solve's
+    relative tolerance and keeps the fastest setting."""
+    import torch
+
+    def run(c, tol, **kw):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cols, it, rf = run_cases(c, loads, tol=tol, **fo, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, cols, it, rf
+
+    def sweep(name, c, **kw):
+        prev = None
+        for tol in TOL_SWEEP:
+            dt, cols, it, rf = run(c, tol, **kw)
+            e = err(cols)
+            log(f"[bench] {name} {kw} tol={tol:g}: {dt:.3f} s, {it} iters, Ceff rel err {e:.2e}")
+            if e <= target:
+                times = sorted([dt] + [run(c, tol, **kw)[0] for _ in range(repeats - 1)])
+                return {"tol": tol, "time_s": times[len(times) // 2], "pcg_iters": it, "refine_steps": rf,
+                        "ceff_rel_err": e, "bracketed": prev is not None,
+                        "missed_at_looser_tol": prev, **{k: v for k, v in kw.items()}}
+            prev = {"tol": tol, "ceff_rel_err": e, "pcg_iters": it}
+        return None
+
+    res = {"fp64": sweep("fp64", cell)}
+    best = None
+    variants = []
+    for inner in (1e-1, 1e-2, 1e-3, 1e-4):
+        r = sweep("fp32_mixed", mixed, inner_tol=inner)
+        variants.append(r)
+        if r is not None and (best is None or r["time_s"] < best["time_s"]):
+            best = r
+    res["fp32_mixed"] = best
+    res["fp32_mixed_by_inner_tol"] = variants
+    if res["fp64"] and best:
+        res["speedup_fp32_mixed_vs_fp64"] = res["fp64"]["time_s"] / best["time_s"]
+    res["target_ceff_rel_err"] = target
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,9 +642,13 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched FP32-mixed solve of the uneven neo-Hookean batch (for profiling)")
     ap.add_argument("--unfused", action="store_true", help="separate CG vector kernels (fused_cg = 0)")
+    ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker, (args.n,) * 3, args.cpu_seconds)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the DBFFT hot path here is a single-GPU build "
               "(no multi-GPU sharding); use --gpus 1", file=sys.stderr)
@@ -668,25 +781,8 @@ def main():
         run_cases(mixed, loads, tol=1e-8, **fo)
         kt32 = mixed.kernel_timing(False)
         out["fp32_mixed_kernels_us"] = {k: ms_tot / cnt * 1e3 for k, (ms_tot, cnt) in kt32.items() if cnt > 0}
-        res = {}
-        for name, c in (("fp64", cell), ("fp32_mixed", mixed)):
-            best = None
-            for tol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                cols, it, rf = run_cases(c, loads, tol=tol, **fo)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t
-                e = err(cols)
-                log(f"[bench] {name} tol={tol:g}: {dt:.3f} s, {it} iters, Ceff rel err {e:.2e}")
-                if e <= 1e-6:
-                    best = {"tol": tol, "time_s": dt, "pcg_iters": it, "refine_steps": rf, "ceff_rel_err": e}
-                    break
-            res[name] = best
+        res = bracket_equal_accuracy(cell, mixed, loads, err, fo, log)
         mixed.close()
-        if res.get("fp64") and res.get("fp32_mixed"):
-            res["speedup_fp32_mixed_vs_fp64"] = res["fp64"]["time_s"] / res["fp32_mixed"]["time_s"]
-        res["target_ceff_rel_err"] = 1e-6
         out["equal_accuracy_1e-6"] = res
         out["ceff_rel_err_fp64_tol1e-8"] = err(cols64)
     cell.close()
@@ -705,7 +801,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(n, phase, E, nu, loads, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
