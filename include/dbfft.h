@@ -98,8 +98,9 @@ typedef struct {
   double newton_tol;   /* max change of any strain / F component in a Newton update (Sec. 2.4); 1e-6 */
   int32_t max_newton;  /* Newton iterations per increment; 25 */
   int32_t refresh;     /* preconditioner mean tangent: 0 every increment, 1 first increment only (Sec. 2.5) */
-  double inner_tol;    /* FP32_MIXED: relative reduction asked of each inner FP32 solve; 1e-4 */
-  int32_t max_refine;  /* FP32_MIXED: outer FP64 residual corrections; 30 */
+  double inner_tol;    /* FP32_MIXED: reduction of the FP32 recursive residual, relative to the last
+                          FP64 residual, after which the FP64 residual b - K x replaces it; 1e-2 */
+  int32_t max_refine;  /* FP32_MIXED: FP64 residual replacements; 30 */
   int32_t check_every; /* PCG iterations enqueued between host convergence polls; 8 */
   int32_t fused_cg;    /* 1: fused CG iteration where it applies (small strains, n1 a power of two
                           from 8 to 256, n2 even): the divergence pass updates the residual, no

@@ -252,15 +252,28 @@ class HomogenizedResponse(torch.autograd.Function):
     @staticmethod
     def forward(ctx, E, load, stress_mask, G, H, nu, precision, tol):
         cell = Cell(E.shape, "iso_field", E.detach(), [nu], precision=precision, device=E.device)
-        cell.solve(load, stress_mask, tol=tol, tol_load=tol)
-        grad, J = cell.adjoint(G, H)
-        cell.close()
-        ctx.save_for_backward(grad)
+        try:
+            cell.solve(load, stress_mask, tol=tol, tol_load=tol)
+            h = cell.homogenize()
+        except Exception:
+            cell.close()
+            raise
+        J = float(np.sum(np.asarray(G) * h["sigma_bar"]) + np.sum(np.asarray(H) * h["eps_bar"]))
+        if ctx.needs_input_grad[0]:
+            # the adjoint solve runs in backward, on this cell's solution
+            ctx.cell, ctx.G, ctx.H = cell, G, H
+        else:
+            cell.close()
         return torch.tensor(J, dtype=torch.float64, device=E.device)
 
     @staticmethod
     def backward(ctx, gout):
-        (grad,) = ctx.saved_tensors
+        cell = ctx.cell
+        try:
+            grad, _ = cell.adjoint(ctx.G, ctx.H)
+        finally:
+            cell.close()
+            ctx.cell = None
         return gout * grad, None, None, None, None, None, None, None
 
 

@@ -224,6 +224,11 @@ void launch_pcg_pupdate(void* p, const void* r, const PcgScalars* sc, const Prec
 template <typename T>
 void launch_precond_init(void* p, void* r, const PrecondArgs& pa, const Geom& g, double* partials,
                          int nblocks, hipStream_t st);
+// the Hermitian projection of r and the partial sums of <r, M r> and <r, r>
+// (launch_precond_init without writing p)
+template <typename T>
+void launch_precond_dots(void* r, const PrecondArgs& pa, const Geom& g, double* partials, int nblocks,
+                         hipStream_t st);
 // Fused CG iteration (small strains, register-FFT x pass, n2 even): alpha
 // after the z pass (first block of the y pass, or its own kernel); the
 // divergence pass updates r in place, projects it onto Hermitian pairs on

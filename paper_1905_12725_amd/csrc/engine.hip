@@ -635,6 +635,36 @@ static void pcg_begin(Ctx& c, const PrecondArgs& pa, const PcgConst& pc, void* x
   HIPCK(hipStreamSynchronize(c.st));
 }
 
+// Goes on with the direction p after the residual in r was replaced by a
+// recomputed one (precision T): x = 0 for the next segment's step sum,
+// the scalars take the recomputed <sigma> and macro residual, r is
+// projected onto Hermitian pairs, and p = M r + beta p with
+// beta = <r, M r> / rho_prev (rho_prev: the <r, M r> the direction was last
+// formed with).  The iteration counter restarts at 0.  Synchronizes.
+template <typename T>
+static void pcg_resume(Ctx& c, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r, void* p,
+                       const double sig[9], const double re[kMaxMacro], double rho_prev) {
+  const size_t vbytes = 3 * (size_t)c.g.nh * 2 * sizeof(T);
+  HIPCK(hipMemsetAsync(x, 0, vbytes, c.st));
+  PcgScalars& h = *c.sc_host;
+  for (int i = 0; i < 9; ++i) h.sig[i] = sig[i];
+  for (int a = 0; a < kMaxMacro; ++a) {
+    h.re[a] = re[a];
+    h.xe[a] = 0.0;
+  }
+  h.rz = rho_prev;
+  h.iter = 0;
+  h.converged = 0;
+  h.pending = 0;
+  HIPCK(hipMemcpyAsync(c.sc_dev, c.sc_host, sizeof(PcgScalars), hipMemcpyHostToDevice, c.st));
+  const int nb = pcg_block_count(c.g);
+  launch_precond_dots<T>(r, pa, c.g, c.partB, nb, c.st);
+  launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 2, c.st);
+  launch_pcg_pupdate<T>(p, r, c.sc_dev, pa, c.g, nb, c.st);
+  HIPCK(hipMemcpyAsync(c.sc_host, c.sc_dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+}
+
 static PcgOut pcg_result(Ctx& c) {
   const PcgScalars& h = *c.sc_host;
   if (g_verbose)
@@ -684,10 +714,14 @@ static std::vector<unsigned char> chunk_key(const Ctx& c, const TangentArgs<T>& 
 // solve that needs more captures one chunk in a HIP graph (unless kernel
 // timing is on) and replays it, which takes the per-launch host cost out of
 // every later chunk.
+// rho_prev > 0: go on with the direction in p (pcg_resume) instead of
+// starting from p = M r.
 template <typename T>
 static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, const PcgConst& pc, void* x, void* r,
-                      void* p, void* q, const double sig0[9], const double re0[kMaxMacro], int check_every) {
-  pcg_begin<T>(c, pa, pc, x, r, p, sig0, re0);
+                      void* p, void* q, const double sig0[9], const double re0[kMaxMacro], int check_every,
+                      double rho_prev = 0.0) {
+  if (rho_prev > 0.0) pcg_resume<T>(c, pa, pc, x, r, p, sig0, re0, rho_prev);
+  else pcg_begin<T>(c, pa, pc, x, r, p, sig0, re0);
   const int nb = pcg_block_count(c.g);
   const int neb = energy_blocks<T>(c, tan.kind);
   const double* pmac = reinterpret_cast<const double*>(reinterpret_cast<const char*>(c.sc_dev) + offsetof(PcgScalars, pmac));
@@ -835,7 +869,13 @@ static LinOut linear_solve_b(Ctx& c, const MacroSet& ms, const double dc0[9], co
     return out;
   }
 
-  // FP32 inner PCG with FP64 outer corrections (iterative refinement)
+  // FP32 PCG with FP64 residual replacement: the FP32 iteration runs until
+  // its recursively updated residual has dropped by inner_tol; then the
+  // step sum joins the FP64 solution, the FP64 residual b - K64 x replaces
+  // the FP32 one, and the iteration goes on with the same direction
+  // (beta from the replaced residual), so the Krylov space built so far is
+  // kept.  A segment that stops at its first test has no direction yet and
+  // starts from p = M r.
   TangentArgs<float> tan32 = elastic_tangent<float>(c);
   HIPCK(hipMemsetAsync(sol_out, 0, v64, c.st));
   double e[kMaxMacro] = {0};
@@ -844,6 +884,7 @@ static LinOut linear_solve_b(Ctx& c, const MacroSet& ms, const double dc0[9], co
   for (int a = 0; a < kMaxMacro; ++a) re[a] = re0[a];
   void* r64 = c.t64;
   HIPCK(hipMemcpyAsync(r64, c.b, v64, hipMemcpyDeviceToDevice, c.st));
+  double rho_prev = 0.0, rec_eq = 0.0, rec_ld = 0.0;
   for (int it = 0;; ++it) {
     if (it > 0) {
       // r64 = b - K64 [x; e]
@@ -865,6 +906,11 @@ static LinOut linear_solve_b(Ctx& c, const MacroSet& ms, const double dc0[9], co
     rl = std::sqrt(rl);
     const double eq = nrm > 0 ? ra / nrm : (ra == 0 ? 0.0 : INFINITY);
     const double ld = nrm > 0 ? rl / nrm : (rl == 0 ? 0.0 : INFINITY);
+    // The direction is kept only while the FP32 recursion still tracks the
+    // true residual (within a factor of 10 at the segment's end); past that
+    // the old direction no longer fits the replaced residual, and the next
+    // segment starts from p = M r.
+    if (rho_prev > 0.0 && (eq > 10.0 * rec_eq || ld > 10.0 * std::max(rec_ld, 0.1 * o.tol_load))) rho_prev = 0.0;
     out.eq = eq;
     out.ld = ld;
     for (int i = 0; i < 9; ++i) out.sig_st[i] = sig[i];
@@ -882,13 +928,18 @@ static LinOut linear_solve_b(Ctx& c, const MacroSet& ms, const double dc0[9], co
     pci.tol_load = std::max(ld * o.inner_tol, 0.5 * o.tol_load);
     pci.max_iter = std::max(1, o.max_iter - out.iters);
     launch_convert<double, float>(c.r, r64, 6 * c.g.nh, c.st);
-    PcgOut po = run_pcg<float>(c, tan32, pa, pci, c.x, c.r, c.p, c.q, sig, re, o.check_every);
+    PcgOut po = run_pcg<float>(c, tan32, pa, pci, c.x, c.r, c.p, c.q, sig, re, o.check_every, rho_prev);
     out.iters += po.iters;
     out.refine += 1;
     if (po.status == 2) {
       out.status = DBFFT_EBREAKDOWN;
       break;
     }
+    // <r, M r> the last direction was formed with: rz_(k+1) / beta_(k+1)
+    const PcgScalars& hs = *c.sc_host;
+    rho_prev = (po.status == 1 && hs.beta > 0.0 && hs.rz > 0.0) ? hs.rz / hs.beta : 0.0;
+    rec_eq = po.eq;
+    rec_ld = po.ld;
     // sol += delta
     launch_convert<float, double>(c.q, c.x, 6 * c.g.nh, c.st);
     launch_axpby<double>(sol_out, c.q, 1.0, 1.0, 6 * c.g.nh, c.st);
@@ -1673,16 +1724,21 @@ static void batch_upload(Batch& B, const std::vector<PrecondArgs>& pa, const std
 
 // batched PCG: cells with active[r] != 0 solve K x = b (b in their r);
 // the others are marked converged and skipped by every kernel
+// rho_prev (may be null): per cell, > 0 to go on with the direction in p
+// after a residual replacement (pcg_resume) instead of starting from p = M r.
 template <typename T>
 static std::vector<PcgOut> batch_pcg(Batch& B, const std::vector<int>& active, const std::vector<PrecondArgs>& pa,
                                      const std::vector<PcgConst>& pc, const std::vector<std::array<double, 9>>& sig0,
-                                     const std::vector<std::array<double, kMaxMacro>>& re0) {
+                                     const std::vector<std::array<double, kMaxMacro>>& re0,
+                                     const std::vector<double>* rho_prev = nullptr) {
   const int n = (int)B.cells.size();
   batch_upload<T>(B, pa, pc);
   for (int r = 0; r < n; ++r) {
     Ctx& c = *B.cells[r];
     if (active[r]) {
-      pcg_begin<T>(c, pa[r], pc[r], c.x, c.r, c.p, sig0[r].data(), re0[r].data());
+      const double rho = rho_prev ? (*rho_prev)[r] : 0.0;
+      if (rho > 0.0) pcg_resume<T>(c, pa[r], pc[r], c.x, c.r, c.p, sig0[r].data(), re0[r].data(), rho);
+      else pcg_begin<T>(c, pa[r], pc[r], c.x, c.r, c.p, sig0[r].data(), re0[r].data());
     } else {
       std::memset(c.sc_host, 0, sizeof(PcgScalars));
       c.sc_host->converged = 1;
@@ -1747,6 +1803,7 @@ static std::vector<int> batch_solve_t(Batch& B, const double* loads, const uint8
     std::vector<std::array<double, kMaxMacro>> sbar(n), e(n), re_b(n);
     std::vector<std::array<double, 9>> dc0(n);
     std::vector<double> eqv(n, INFINITY), ldv(n, INFINITY);
+    std::vector<double> rho_prev(n, 0.0), rec_eq(n, 0.0), rec_ld(n, 0.0);  // FP32_MIXED residual replacement
     std::vector<int> iters(n, 0), refine(n, 0), done(n, 0);
     for (int r = 0; r < n; ++r) {
       Ctx& c = *B.cells[r];
@@ -1811,6 +1868,11 @@ static std::vector<int> batch_solve_t(Batch& B, const double* loads, const uint8
         rl = std::sqrt(rl);
         eqv[r] = nrm > 0 ? ra / nrm : (ra == 0 ? 0.0 : INFINITY);
         ldv[r] = nrm > 0 ? rl / nrm : (rl == 0 ? 0.0 : INFINITY);
+        // as in the single-cell solve: keep the direction only while the
+        // FP32 recursion tracked the true residual within a factor of 10
+        if (rho_prev[r] > 0.0 &&
+            (eqv[r] > 10.0 * rec_eq[r] || ldv[r] > 10.0 * std::max(rec_ld[r], 0.1 * o.tol_load)))
+          rho_prev[r] = 0.0;
         if (eqv[r] < o.tol && ldv[r] < o.tol_load) {
           done[r] = 1;
           status[r] = DBFFT_OK;
@@ -1838,7 +1900,7 @@ static std::vector<int> batch_solve_t(Batch& B, const double* loads, const uint8
         any = true;
       }
       if (!any) break;
-      std::vector<PcgOut> po = batch_pcg<T>(B, active, pa, pc, sig0, re0);
+      std::vector<PcgOut> po = batch_pcg<T>(B, active, pa, pc, sig0, re0, &rho_prev);
       for (int r = 0; r < n; ++r) {
         if (!active[r]) continue;
         Ctx& c = *B.cells[r];
@@ -1848,6 +1910,12 @@ static std::vector<int> batch_solve_t(Batch& B, const double* loads, const uint8
           status[r] = DBFFT_EBREAKDOWN;
           done[r] = 1;
           continue;
+        }
+        if (B.prec != DBFFT_FP64) {
+          const PcgScalars& hs = *c.sc_host;
+          rho_prev[r] = (po[r].status == 1 && hs.beta > 0.0 && hs.rz > 0.0) ? hs.rz / hs.beta : 0.0;
+          rec_eq[r] = po[r].eq;
+          rec_ld[r] = po[r].ld;
         }
         if (B.prec == DBFFT_FP64) {
           // FP64: one PCG solves the system; its recurrence decides the status
@@ -2107,7 +2175,7 @@ void dbfft_default_opts(dbfft_opts* o) {
   o->newton_tol = 1e-6;
   o->max_newton = 25;
   o->refresh = 0;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-2;
   o->max_refine = 30;
   o->check_every = 8;
   o->fused_cg = 1;

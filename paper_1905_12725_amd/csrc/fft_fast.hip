@@ -151,15 +151,9 @@ __device__ __forceinline__ void alpha_task(PcgScalars* sc, const double* __restr
 
 // Elements per thread: 4 for the passes that keep several vectors live
 // (gradient, divergence), 8 for the plain ones.
-#ifndef DBFFT_F32_FUSED_E
-#define DBFFT_F32_FUSED_E 4
-#endif
-#ifndef DBFFT_F32_LINE_E
-#define DBFFT_F32_LINE_E 4
-#endif
 template <typename T, int N, int MODE>
 constexpr int strided_E() {
-  return (MODE != SP_PLAIN && N <= 128) ? (sizeof(T) == 8 ? 4 : DBFFT_F32_FUSED_E) : 8;
+  return (MODE != SP_PLAIN && N <= 128) ? 4 : 8;
 }
 template <int N, int E>
 struct StridedShape {
@@ -170,24 +164,8 @@ struct StridedShape {
   static constexpr int PITCH = TZ + 1;
 };
 
-#ifndef DBFFT_GRAD_WAVES
-#define DBFFT_GRAD_WAVES 1
-#endif
-#ifndef DBFFT_DIV_WAVES
-#define DBFFT_DIV_WAVES 1
-#endif
-// minimum waves per SIMD the register allocation must allow (FP64 fused
-// passes; the FP32 ones fit three or more waves anyway)
-template <typename T>
-constexpr int strided_min_waves(int mode) {
-  if (sizeof(T) == 4) return 1;
-  if (mode == SP_GRAD_SMALL || mode == SP_GRAD_FINITE) return DBFFT_GRAD_WAVES;
-  if (mode == SP_DIV_SMALL || mode == SP_DIV_FINITE) return DBFFT_DIV_WAVES;
-  return 1;
-}
-
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT), (strided_min_waves<T>(MODE))) void k_strided_fast(const cpx<T>* in, cpx<T>* out, StridedGeom sg,
+__global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) void k_strided_fast(const cpx<T>* in, cpx<T>* out, StridedGeom sg,
                                                                       Geom g, const cpx<T>* __restrict__ twg, T d,
                                                                       double* __restrict__ dc_out,
                                                                       const int* __restrict__ stop,
@@ -717,17 +695,13 @@ __device__ __forceinline__ cpx<T> shfl_partner(cpx<T> v, int partner) {
 // Exchange padding of the z pass: one slot per 256 bytes of a line.
 template <typename T>
 constexpr int line_pad() {
-#ifdef DBFFT_Z_NOPAD
-  return 0;
-#else
   return sizeof(T) == 8 ? 4 : 5;
-#endif
 }
 
 // Elements per thread of the z pass.
 template <typename T>
 constexpr int line_E() {
-  return sizeof(T) == 8 ? 4 : DBFFT_F32_LINE_E;
+  return 4;
 }
 template <typename T, int M, int E>
 struct LineCtx {
@@ -959,8 +933,9 @@ __global__ __launch_bounds__(64) void k_line_fast(const cpx<T>* in, cpx<T>* out,
 bool fast_line_supported(int n3) { return n3 == 16 || n3 == 32 || n3 == 64 || n3 == 128 || n3 == 256; }
 
 int fast_line_blocks(const Geom& g, int elem_bytes) {
+  (void)elem_bytes;  // four elements per thread in both precisions
   const int M = g.n3 / 2;
-  const int E = elem_bytes == 16 ? 4 : DBFFT_F32_LINE_E;
+  const int E = 4;
   const int LB = 64 / (M / E);
   return (int)(((long long)g.n1 * g.n2 + LB - 1) / LB);
 }

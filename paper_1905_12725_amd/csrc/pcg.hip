@@ -33,10 +33,10 @@ __global__ __launch_bounds__(kVecThreads) void k_pupdate(cpx<T>* __restrict__ p,
   pupdate_core<T>(p, r, sc, pa, g, blockIdx.x, gridDim.x);
 }
 
-template <typename T>
+template <typename T, bool WRITE_P>
 __global__ __launch_bounds__(kVecThreads) void k_pinit(cpx<T>* __restrict__ p, cpx<T>* __restrict__ r,
                                                        PrecondArgs pa, Geom g, double* __restrict__ partials) {
-  pinit_core<T>(p, r, pa, g, partials, blockIdx.x, gridDim.x);
+  pinit_core<T, WRITE_P>(p, r, pa, g, partials, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_alpha(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
@@ -107,9 +107,17 @@ void launch_pcg_pupdate(void* p, const void* r, const PcgScalars* sc, const Prec
 template <typename T>
 void launch_precond_init(void* p, void* r, const PrecondArgs& pa, const Geom& g, double* partials, int nblocks,
                          hipStream_t st) {
-  DB_LAUNCH((k_pinit<T>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(p),
+  DB_LAUNCH((k_pinit<T, true>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(p),
                      static_cast<cpx<T>*>(r), pa, g, partials);
 }
+template <typename T>
+void launch_precond_dots(void* r, const PrecondArgs& pa, const Geom& g, double* partials, int nblocks,
+                         hipStream_t st) {
+  DB_LAUNCH((k_pinit<T, false>), dim3(nblocks), dim3(kVecThreads), 0, st, static_cast<cpx<T>*>(nullptr),
+                     static_cast<cpx<T>*>(r), pa, g, partials);
+}
+template void launch_precond_dots<double>(void*, const PrecondArgs&, const Geom&, double*, int, hipStream_t);
+template void launch_precond_dots<float>(void*, const PrecondArgs&, const Geom&, double*, int, hipStream_t);
 void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                       hipStream_t st) {
   DB_LAUNCH(k_alpha, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);

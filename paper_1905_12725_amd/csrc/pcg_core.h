@@ -172,7 +172,8 @@ __device__ __forceinline__ void pupdate_core(cpx<T>* __restrict__ p, const cpx<T
 
 // p = M r; partial <r, M r> and <r, r>.  r is first projected onto
 // Hermitian pairs on the self-conjugate planes (as in update_core).
-template <typename T>
+// WRITE_P = false: the projection and the partial sums only (p untouched).
+template <typename T, bool WRITE_P = true>
 __device__ __forceinline__ void pinit_core(cpx<T>* __restrict__ p, cpx<T>* __restrict__ r,
                                            const PrecondArgs& pa, const Geom& g, double* __restrict__ partials,
                                            int chunk, int nchunks) {
@@ -204,8 +205,10 @@ __device__ __forceinline__ void pinit_core(cpx<T>* __restrict__ p, cpx<T>* __res
     double a = 0.0, b = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      p[c * nh + k] = down<T>(zv[c]);
-      if (kp != k) p[c * nh + kp] = down<T>(conj(zv[c]));
+      if constexpr (WRITE_P) {
+        p[c * nh + k] = down<T>(zv[c]);
+        if (kp != k) p[c * nh + kp] = down<T>(conj(zv[c]));
+      }
       a += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
       b += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
     }
@@ -291,8 +294,11 @@ __device__ __forceinline__ void alpha_core(PcgScalars* __restrict__ sc, const do
   macro_step(sc, alpha, dc, pc);
 }
 
-// beta, macro block of p, convergence.  first != 0: initial call after
-// p = M r (no beta, iteration counter stays 0).
+// beta, macro block of p, convergence.  first == 1: initial call after
+// p = M r (no beta, iteration counter stays 0).  first == 2: the residual
+// was replaced by a recomputed one and the iteration goes on with the same
+// direction: beta = <r, M r> / rho with rho the <r, M r> the direction was
+// formed with (left in sc->rz by the host), counter unchanged.
 // dc != nullptr (fused CG): the macroscopic step of this iteration is taken
 // first, with the average stress of the direction from the divergence pass.
 __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
@@ -313,16 +319,14 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
     rz += sc->re[a] * z;
     re2 += sc->re[a] * sc->re[a];
   }
-  if (first) {
-    for (int a = 0; a < pc.nmacro; ++a) sc->pe[a] = ze[a];
+  double beta = 0.0;
+  if (first == 1) {
     sc->iter = 0;
-    sc->beta = 0.0;
   } else {
-    const double beta = rz / sc->rz;
-    sc->beta = beta;
-    for (int a = 0; a < pc.nmacro; ++a) sc->pe[a] = ze[a] + beta * sc->pe[a];
-    sc->iter += 1;
+    beta = rz / sc->rz;
+    if (first == 0) sc->iter += 1;
   }
+  sc->beta = beta;
   sc->rz = rz;
   sc->rr = rr;
   sc->re2 = re2;
@@ -338,14 +342,19 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
   }
   sc->eq_res = eq;
   sc->load_res = ld;
-  // macro tensor of p for the next operator application
+  if (eq < pc.tol && ld < pc.tol_load) sc->converged = 1;
+  else if (sc->iter >= pc.max_iter) sc->converged = 3;
+  // Macro block of the next direction, p_e = z_e + beta p_e, and its tensor
+  // for the next operator application.  Once stopped, p_e (like the field
+  // part of p, which the direction kernels leave alone then) keeps the last
+  // direction, from which an iteration with a replaced residual goes on.
+  if (sc->converged && first != 1) return;
+  for (int a = 0; a < pc.nmacro; ++a) sc->pe[a] = ze[a] + beta * sc->pe[a];
   for (int c = 0; c < 9; ++c) {
     double m = 0.0;
     for (int a = 0; a < pc.nmacro; ++a) m += sc->pe[a] * pc.basis[a][c];
     sc->pmac[c] = m;
   }
-  if (eq < pc.tol && ld < pc.tol_load) sc->converged = 1;
-  else if (sc->iter >= pc.max_iter) sc->converged = 3;
 }
 
 // fused CG: x += alpha p (if this iteration's step is pending), then

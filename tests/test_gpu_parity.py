@@ -200,6 +200,43 @@ def test_fp32_mixed_solve_accuracy(gpu):
     assert rel(sig, ref.sigma_bar) < 1e-6
 
 
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("mixed_control", [False, True])
+def test_fp32_mixed_residual_replacement(gpu, mixed_control, fused):
+    """FP32 PCG with FP64 residual replacement keeps its direction across
+    replacements (inner_tol 1e-2): <sigma> within 1e-6 of the oracle, the
+    final FP64 residual below tol, and the iteration count within 10 % of
+    the FP64 solve's (restarted refinement needed about a third more at this
+    contrast).  inner_tol 1e-4 (replacements far apart, so the FP32
+    recursion drifts and segments restart) must still converge as well."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (32, 32, 32)
+    print(f"case fp32 residual replacement mixed_control={mixed_control} fused={fused}", flush=True)
+    phase, _, _ = ms.random_spheres(n, 3, 2.0, 5.0, 0.3)
+    E = [1.0, 100.0]
+    load = np.zeros((3, 3)); load[0, 0] = 1e-3; load[0, 1] = load[1, 0] = 5e-4
+    mask = np.zeros((3, 3), bool)
+    if mixed_control:
+        mask[1, 1] = mask[2, 2] = True
+        load[1, 1] = load[2, 2] = 0.0
+    ref = so.solve_linear(n, oracle_iso(phase, E, 0.3), load, mask, tol=1e-12, tol_load=1e-12)
+    ph = torch.from_numpy(phase)
+    with Cell(n, "iso_phase", ph, iso_params(E, 0.3)) as c64:
+        it64 = c64.solve(load, mask, tol=1e-9, tol_load=1e-9, fused_cg=fused)["pcg_iters"]
+    with Cell(n, "iso_phase", ph, iso_params(E, 0.3), precision="fp32_mixed") as cell:
+        for inner in (1e-2, 1e-4):
+            info = cell.solve(load, mask, tol=1e-9, tol_load=1e-9, inner_tol=inner, fused_cg=fused)
+            sig = cell.homogenize()["sigma_bar"]
+            print(f"  inner_tol {inner:g}: {info['pcg_iters']} iterations ({it64} FP64), "
+                  f"{info['refine_steps']} segments, rel {rel(sig, ref.sigma_bar):.2e}", flush=True)
+            assert info["status"] == 0
+            assert info["eq_res"] < 1e-9 and info["load_res"] < 1e-9
+            assert rel(sig, ref.sigma_bar) < 1e-6
+            if inner == 1e-2:
+                assert info["pcg_iters"] <= 1.1 * it64 + 2, (info["pcg_iters"], it64)
+
+
 def test_laminate_closed_form_gpu(gpu):
     import torch
     from paper_1905_12725_amd.api import Cell
