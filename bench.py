@@ -416,9 +416,10 @@ def adjoint_leg(log, n=(96, 96, 96), nfd=5):
 def multi_rhs_leg(log, sizes=((64, 64, 64), (96, 96, 96), (128, 128, 128))):
     """The six Mandel load cases of the headline workload solved together:
     six contexts on the same microstructure in one batch (one launch per
-    pass for all six right-hand sides) against the six solves one after
-    the other, FP64 and FP32-mixed, PCG tol 1e-8.  Timed after one warm
-    run of each."""
+    pass for all six right-hand sides), and (FP64) block PCG with the six
+    loads in one block Krylov space, against the six solves one after the
+    other, FP64 and FP32-mixed, PCG tol 1e-8.  Timed after one warm run of
+    each."""
     import torch
     from paper_1905_12725_amd import microstructure as ms
     from paper_1905_12725_amd.api import Cell, Batch
@@ -453,6 +454,22 @@ def multi_rhs_leg(log, sizes=((64, 64, 64), (96, 96, 96), (128, 128, 128))):
                         "pcg_iters_sequential": int(it_seq),
                         "pcg_iters_batched": int(sum(i["pcg_iters"] for i in infos))}
             log(f"[bench] six cases {key}: sequential {t_seq * 1e3:.1f} ms, one batch {t_b * 1e3:.1f} ms")
+            if prec == "fp64":
+                # block PCG: the six loads in one block Krylov space
+                cell = Cell(n, "iso_phase", torch.from_numpy(phase), params, precision=prec)
+                cell.solve_block(loads, tol=1e-8)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                binfos, applies = cell.solve_block(loads, tol=1e-8)
+                torch.cuda.synchronize()
+                t_blk = time.perf_counter() - t
+                cell.close()
+                out[key]["block_pcg_s"] = t_blk
+                out[key]["block_pcg_iters"] = int(max(i["pcg_iters"] for i in binfos))
+                out[key]["block_pcg_applies"] = int(applies)
+                out[key]["block_pcg_speedup"] = t_seq / t_blk
+                log(f"[bench] six cases {key}: block PCG {t_blk * 1e3:.1f} ms, "
+                    f"{out[key]['block_pcg_iters']} block iterations, {applies} applies (sequential {it_seq})")
             if n[0] >= 128:
                 # two contexts on two streams, three cases each, from two
                 # host threads: do independent solves fill each other's gaps?

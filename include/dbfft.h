@@ -202,6 +202,25 @@ dbfft_status dbfft_apply_noalloc(const int64_t n[3], int32_t material, const voi
 dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t stress_mask[9], int32_t n_increments,
                          double dt, const dbfft_opts* opts, dbfft_info* info);
 
+/* Several loads of one linear cell solved together by block PCG: the
+ * iterates of every load come from one block Krylov space of the
+ * preconditioned operator (Sec. 3, CG for complex numbers, with the
+ * per-frequency preconditioner of Sec. 2.5 eqs. pred2/pred3), spanned by the
+ * preconditioned residuals of all loads; blocks of K-conjugate directions
+ * P give alpha = (P^T K P)^-1 P^T R and beta = -(P^T K P)^-1 (K P)^T M R,
+ * each new direction block orthonormalized (dependent directions dropped).
+ * A load whose residuals meet opts.tol / opts.tol_load stops and leaves the
+ * block.  loads: nrhs x 9 host doubles (row-major 3x3 each, strain or
+ * stress per stress_mask as for dbfft_solve, one mask for all loads);
+ * nrhs 1 .. 6.  infos: nrhs entries (pcg_iters = the block iteration at
+ * which that load stopped; sigma_bar, eps_bar and residuals recomputed from
+ * its solution).  applies (may be NULL): operator applications in all.
+ * opts.max_iter caps the block iterations.  FP64 contexts with linear
+ * materials (EUNSUPPORTED otherwise).  The context's own solution (for
+ * dbfft_homogenize, dbfft_get_solution, dbfft_adjoint) is not changed. */
+dbfft_status dbfft_solve_block(dbfft_ctx* ctx, int32_t nrhs, const double* loads, const uint8_t stress_mask[9],
+                               const dbfft_opts* opts, dbfft_info* infos, int32_t* applies);
+
 /* Homogenized response of the last solve (Sec. 3 post-processing):
  * <sigma> and <eps> (row-major, host, either may be NULL) and, when the
  * pointers are not NULL, the real fields of strain (6 or 9 comps), stress

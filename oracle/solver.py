@@ -223,6 +223,155 @@ def pcg(space, tangent, precond, b, sig0, tol=1e-8, tol_load=1e-10, max_iter=100
     return x, sig, info
 
 
+@dataclass
+class BlockPCGInfo:
+    iterations: int = 0          # block iterations
+    applies: int = 0             # operator applications (sum of the block widths)
+    converged: bool = False
+    breakdown: bool = False
+    col_iterations: list = field(default_factory=list)  # block iteration at which each column stopped
+    eq_res: list = field(default_factory=list)
+    load_res: list = field(default_factory=list)
+
+
+def _orthonormalize(space, W, drop_tol, ref=None):
+    """Orthonormal basis (for space.dot) of the span of the vectors W:
+    Cholesky factorization of their Gram matrix with diagonal pivoting,
+    G[perm][:, perm] = L L^T over the kept columns, then P = W[perm] L^-T.
+    The pivot of a column is the squared norm of its part orthogonal to the
+    kept ones; the column is dropped as dependent when that is not above
+    drop_tol times ref[j] (default: its own squared norm)."""
+    m = len(W)
+    if m == 0:
+        return []
+    G = np.array([[space.dot(W[i], W[k]) for k in range(m)] for i in range(m)])
+    d = np.diag(G).astype(np.float64).copy()
+    ref = d.copy() if ref is None else np.asarray(ref, dtype=np.float64)
+    Lrow = np.zeros((m, m))  # Lrow[i, t]: entry of original column i in pivot step t
+    perm, rest = [], list(range(m))
+    for t in range(m):
+        rest = [i for i in rest if d[i] > drop_tol * ref[i]]
+        if not rest:
+            break
+        j = max(rest, key=lambda i: d[i])
+        piv = np.sqrt(d[j])
+        Lrow[j, t] = piv
+        rest.remove(j)
+        for i in rest:
+            Lrow[i, t] = (G[i, j] - np.dot(Lrow[i, :t], Lrow[j, :t])) / piv
+            d[i] -= Lrow[i, t] ** 2
+        perm.append(j)
+    k = len(perm)
+    L = Lrow[perm, :k]                      # k x k lower triangular
+    C = np.linalg.inv(L).T                  # L^-T
+    return [(sum(C[u, t] * W[perm[u]][0] for u in range(k)), sum(C[u, t] * W[perm[u]][1] for u in range(k)))
+            for t in range(k)]
+
+
+def block_pcg(space, tangent, precond, B, sig0, tol=1e-8, tol_load=1e-10, max_iter=10000, drop_tol=1e-12):
+    """Block preconditioned CG for s right-hand sides of one operator.
+
+    The iterates of every column are taken from one block Krylov space of
+    the preconditioned operator, spanned by the preconditioned residuals of
+    all columns (the method of Sec. 3 -- CG for complex numbers with the
+    preconditioner of eqs. pred2/pred3 -- with a block of directions in place
+    of one).  With P a block of K-conjugate directions and Q = K P:
+        alpha = (P^T Q)^-1 P^T R,   X += P alpha,   R -= Q alpha,
+        beta  = -(P^T Q)^-1 Q^T Z (Z = M R),   next P: an orthonormal basis of Z + P beta,
+    which keeps the new directions K-conjugate to the old ones.  A column
+    whose residuals meet tol / tol_load (relative to its own ||<sigma>||, as
+    in pcg) stops: its iterate and residual are no longer updated and its
+    preconditioned residual leaves the block.  Dependent directions are
+    dropped by the pivoted orthonormalization.
+
+    B: list of s vectors (a, e); sig0: <sigma> of the fields that produced
+    them (s, 3, 3).  Returns the iterates, the tracked <sigma> per column and
+    a BlockPCGInfo."""
+    s = len(B)
+    info = BlockPCGInfo(col_iterations=[0] * s, eq_res=[np.inf] * s, load_res=[np.inf] * s)
+    X = [space.zeros() for _ in range(s)]
+    R = [(b[0].copy(), b[1].copy()) for b in B]
+    sig = [np.array(v, dtype=np.float64) for v in sig0]
+
+    def done(j):
+        eq, ld = residual_norms(space, R[j], sig[j])
+        info.eq_res[j], info.load_res[j] = eq, ld
+        return eq < tol and ld < tol_load
+
+    def comb(V, C, j):
+        """sum_i V_i C[i, j]"""
+        a = sum(C[i, j] * V[i][0] for i in range(len(V)))
+        e = sum(C[i, j] * V[i][1] for i in range(len(V)))
+        return a, e
+
+    active = [j for j in range(s) if not done(j)]
+    P = _orthonormalize(space, [precond(R[j]) for j in active], drop_tol) if active else []
+    while active and P and info.iterations < max_iter:
+        QD = [space.apply(p, tangent) for p in P]
+        Q = [q for q, _ in QD]
+        dcP = [dc for _, dc in QD]
+        info.applies += len(P)
+        m = len(P)
+        Gam = np.array([[space.dot(P[i], Q[k]) for k in range(m)] for i in range(m)])
+        Gam = 0.5 * (Gam + Gam.T)
+        try:
+            Lg = np.linalg.cholesky(Gam)
+        except np.linalg.LinAlgError:
+            info.breakdown = True
+            break
+        PR = np.array([[space.dot(P[i], R[j]) for j in active] for i in range(m)])
+        alpha = np.linalg.solve(Lg.T, np.linalg.solve(Lg, PR))
+        for jj, j in enumerate(active):
+            da, de = comb(P, alpha, jj)
+            qa, qe = comb(Q, alpha, jj)
+            X[j] = (X[j][0] + da, X[j][1] + de)
+            R[j] = (R[j][0] - qa, R[j][1] - qe)
+            sig[j] = sig[j] + sum(alpha[i, jj] * dcP[i] for i in range(m))
+        info.iterations += 1
+        still = []
+        for j in active:
+            if done(j):
+                info.col_iterations[j] = info.iterations
+            else:
+                still.append(j)
+        active = still
+        if not active:
+            break
+        Z = [precond(R[j]) for j in active]
+        QZ = np.array([[space.dot(Q[i], Z[jj]) for jj in range(len(active))] for i in range(m)])
+        beta = -np.linalg.solve(Lg.T, np.linalg.solve(Lg, QZ))
+        W = []
+        for jj in range(len(active)):
+            pa, pe = comb(P, beta, jj)
+            W.append((Z[jj][0] + pa, Z[jj][1] + pe))
+        # a column of W that has lost nearly all of its preconditioned
+        # residual to the conjugation brings no new direction
+        P = _orthonormalize(space, W, drop_tol, [space.dot(z, z) for z in Z])
+    for j in active:
+        info.col_iterations[j] = info.iterations
+    info.converged = not active
+    return X, sig, info
+
+
+def solve_linear_block(shape, tangent, loads, stress_mask=None, tol=1e-8, tol_load=1e-10, max_iter=10000,
+                       kin=SMALL):
+    """The linear problems of several loads (one stress mask) solved by
+    block_pcg; returns a LinearResult per load and the BlockPCGInfo."""
+    space = Space(shape, kin, stress_mask)
+    B, sig0, EUs = [], [], []
+    for load in loads:
+        E_U, sbar = split_load(space, load)
+        (ka, _), dc0 = space.apply(space.zeros(), tangent, E_U)
+        B.append((-ka, sbar - space.macro_row(dc0)))
+        sig0.append(dc0)
+        EUs.append(E_U)
+    M = space.preconditioner(tangent.mean())
+    X, sig, info = block_pcg(space, tangent, M, B, sig0, tol, tol_load, max_iter)
+    out = [LinearResult(x[0], x[1], sg, E_U + space.macro_tensor(x[1]), None, space, E_U)
+           for x, sg, E_U in zip(X, sig, EUs)]
+    return out, info
+
+
 def split_load(space, load):
     """Prescribed strain part (zero on S) and the prescribed stress row."""
     load = np.asarray(load, dtype=np.float64)

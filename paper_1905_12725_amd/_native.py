@@ -28,7 +28,7 @@ EXPORTED = (
     "dbfft_default_opts", "dbfft_setup", "dbfft_apply", "dbfft_apply_fourier", "dbfft_solve",
     "dbfft_homogenize", "dbfft_get_solution", "dbfft_adjoint", "dbfft_destroy", "dbfft_last_error",
     "dbfft_kernel_timing", "dbfft_batch_create", "dbfft_batch_solve", "dbfft_batch_tiles",
-    "dbfft_batch_destroy", "dbfft_apply_noalloc",
+    "dbfft_batch_destroy", "dbfft_apply_noalloc", "dbfft_solve_block",
 )
 KERNEL_KINDS = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div",
                 "cg_alpha", "cg_update", "cg_beta", "cg_direction")
@@ -89,6 +89,9 @@ def load_library(path=LIB_PATH):
     lib.dbfft_apply_noalloc.restype = ct.c_int
     lib.dbfft_solve.argtypes = [P, DP, ct.POINTER(ct.c_uint8), I32, D, ct.POINTER(Opts), ct.POINTER(Info)]
     lib.dbfft_solve.restype = ct.c_int
+    lib.dbfft_solve_block.argtypes = [P, I32, DP, ct.POINTER(ct.c_uint8), ct.POINTER(Opts), ct.POINTER(Info),
+                                      ct.POINTER(ct.c_int32)]
+    lib.dbfft_solve_block.restype = ct.c_int
     lib.dbfft_homogenize.argtypes = [P, DP, DP, P, P, P]
     lib.dbfft_homogenize.restype = ct.c_int
     lib.dbfft_get_solution.argtypes = [P, P, DP]

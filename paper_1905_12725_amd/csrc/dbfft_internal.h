@@ -260,6 +260,21 @@ void launch_pcg_beta(PcgScalars* sc, const double* partials, int nparts, const P
                      hipStream_t st);
 int pcg_block_count(const Geom& g);
 
+// block PCG (FP64): blocks of at most kMaxBlock 3-component half-spectrum vectors
+constexpr int kMaxBlock = 6;
+struct BlockVecs {
+  const void* v[kMaxBlock];
+};
+struct BlockCoef {
+  double c[kMaxBlock][kMaxBlock];
+};
+// partials[b][i * nb + j] of <A_i, B_j> over nblocks blocks
+void launch_block_dot(const BlockVecs& A, const BlockVecs& B, int na, int nb, const Geom& g, double* partials,
+                      int nblocks, hipStream_t st);
+// Y_j = ybeta Y_j + sum_i X_i C[i][j]; norms (may be null): partials[b][j] of |Y_j|^2
+void launch_block_comb(const BlockVecs& X, const BlockVecs& Y, int nx, int ny, const BlockCoef& C, double ybeta,
+                       const Geom& g, double* norms, int nblocks, hipStream_t st);
+
 // vector utilities
 template <typename T>
 void launch_axpby(void* y, const void* x, double a, double b, long long n2, hipStream_t st);  // y = a x + b y (n2 reals)

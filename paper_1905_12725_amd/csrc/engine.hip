@@ -209,6 +209,14 @@ struct Ctx {
   std::vector<std::array<double, 9>> ck_mt;
   double* adj_lam = nullptr;  // J2 adjoint multiplier (Mandel) 6 x N
 
+  // block PCG (dbfft_solve_block): six sets of blk_cap vectors (X R P Q Z P2),
+  // per-column macro tensors and mean stresses, block-dot partials
+  void* blk = nullptr;
+  int blk_cap = 0;
+  double* blk_mac = nullptr;
+  double* blk_dc = nullptr;
+  double* blk_part = nullptr;
+
   // solution state
   bool solved = false;
   int last_mask[9] = {0};
@@ -982,6 +990,364 @@ static void evaluate_linear(Ctx& c, const double* sol, const double mt[9], const
   ld = nrm > 0 ? rl / nrm : 0.0;
 }
 
+// ------------------------------------------------------------------ block PCG
+// Several loads of one linear cell (one stress mask) solved in one block
+// Krylov space of the preconditioned operator (FP64).  P is a block of
+// K-conjugate directions, Q = K P:
+//   alpha = (P^T Q)^-1 P^T R,  X += P alpha,  R -= Q alpha,
+//   beta = -(P^T Q)^-1 Q^T Z with Z = M R,  next P = orthonormal basis of Z + P beta,
+// with the real inner product on the half spectrum plus the Euclidean one on
+// the macro block.  Converged columns leave the block; the orthonormal basis
+// comes from a Cholesky factorization of the Gram matrix with diagonal
+// pivoting that drops dependent directions.  Block inner products and
+// combinations are vector kernels; the small matrices are solved here.
+
+// Cholesky of an n x n SPD matrix (row-major), lower factor in L; false if not SPD
+static bool chol(const std::vector<double>& A, int n, std::vector<double>& L) {
+  L.assign(n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0)) return false;
+    L[j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = v / L[j * n + j];
+    }
+  }
+  return true;
+}
+// X = A^-1 B for A = L L^T (B: n x m, row-major)
+static std::vector<double> chol_solve(const std::vector<double>& L, int n, const std::vector<double>& B, int m) {
+  std::vector<double> X(B);
+  for (int c = 0; c < m; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double v = X[i * m + c];
+      for (int k = 0; k < i; ++k) v -= L[i * n + k] * X[k * m + c];
+      X[i * m + c] = v / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = X[i * m + c];
+      for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * X[k * m + c];
+      X[i * m + c] = v / L[i * n + i];
+    }
+  }
+  return X;
+}
+
+struct BlockVec {
+  void* a = nullptr;              // device half-spectrum coefficients
+  double e[kMaxMacro] = {0};      // macro block
+};
+
+// inner products of the vectors of two lists: out[i * |B| + j]
+static std::vector<double> blk_dot(Ctx& c, const std::vector<BlockVec*>& A, const std::vector<BlockVec*>& B, int nS) {
+  const int na = (int)A.size(), nb = (int)B.size();
+  BlockVecs va{}, vb{};
+  for (int i = 0; i < na; ++i) va.v[i] = A[i]->a;
+  for (int j = 0; j < nb; ++j) vb.v[j] = B[j]->a;
+  const int nblk = pcg_block_count(c.g);
+  launch_block_dot(va, vb, na, nb, c.g, c.blk_part, nblk, c.st);
+  launch_reduce(c.blk_part, nblk, na * nb, c.red_dev, c.st);
+  HIPCK(hipMemcpyAsync(c.red_host, c.red_dev, na * nb * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  std::vector<double> out(na * nb);
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j) {
+      double v = c.red_host[i * nb + j];
+      for (int a = 0; a < nS; ++a) v += A[i]->e[a] * B[j]->e[a];
+      out[i * nb + j] = v;
+    }
+  return out;
+}
+
+// Y_j = ybeta Y_j + sum_i X_i C[i * |Y| + j] (field and macro parts); with
+// norms != null the weighted squared norms of the field parts of the Y_j
+static void blk_comb(Ctx& c, const std::vector<BlockVec*>& X, const std::vector<BlockVec*>& Y,
+                     const std::vector<double>& Cm, double ybeta, int nS, std::vector<double>* norms) {
+  const int nx = (int)X.size(), ny = (int)Y.size();
+  BlockVecs vx{}, vy{};
+  BlockCoef cf{};
+  for (int i = 0; i < nx; ++i) vx.v[i] = X[i]->a;
+  for (int j = 0; j < ny; ++j) vy.v[j] = Y[j]->a;
+  for (int i = 0; i < nx; ++i)
+    for (int j = 0; j < ny; ++j) cf.c[i][j] = Cm[i * ny + j];
+  const int nblk = pcg_block_count(c.g);
+  launch_block_comb(vx, vy, nx, ny, cf, ybeta, c.g, norms ? c.blk_part : nullptr, nblk, c.st);
+  for (int j = 0; j < ny; ++j)
+    for (int a = 0; a < nS; ++a) {
+      double v = ybeta * Y[j]->e[a];
+      for (int i = 0; i < nx; ++i) v += X[i]->e[a] * Cm[i * ny + j];
+      Y[j]->e[a] = v;
+    }
+  if (norms) {
+    launch_reduce(c.blk_part, nblk, ny, c.red_dev, c.st);
+    HIPCK(hipMemcpyAsync(c.red_host, c.red_dev, ny * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCK(hipStreamSynchronize(c.st));
+    norms->assign(c.red_host, c.red_host + ny);
+  }
+}
+
+struct BlockOut {
+  int iterations = 0, applies = 0, status = DBFFT_OK;
+  std::vector<int> col_iters, col_status;
+};
+
+// Solves the loads (s x 9 row-major, strain on the mask's zeros, stress on
+// its ones) and fills infos[s]
+static BlockOut block_solve(Ctx& c, int s, const double* loads, const int mask[9], const dbfft_opts& o,
+                            dbfft_info* infos) {
+  BlockOut out;
+  out.col_iters.assign(s, 0);
+  out.col_status.assign(s, DBFFT_ENOTCONV);
+  const MacroSet ms = macro_set(c, mask);
+  const int nS = ms.nS;
+  double C4[81];
+  mean_tangent(c, C4);
+  PrecondArgs pa{};
+  PcgConst pc{};
+  std::memset(&pc, 0, sizeof(pc));
+  build_precond(c, C4, ms, pa, pc);
+  TangentArgs<double> tan64 = elastic_tangent<double>(c);
+  const size_t v64 = 3 * (size_t)c.g.nh * 2 * sizeof(double);
+  if (c.blk_cap < s) {
+    if (c.blk) HIPCK(hipFree(c.blk));
+    c.blk = nullptr;
+    c.blk_cap = 0;
+    c.blk = dalloc(6 * (size_t)s * v64);
+    c.blk_cap = s;
+  }
+  if (!c.blk_mac) c.blk_mac = static_cast<double*>(dalloc(kMaxBlock * 16 * sizeof(double)));
+  if (!c.blk_dc) c.blk_dc = static_cast<double*>(dalloc(kMaxBlock * 16 * sizeof(double)));
+  if (!c.blk_part) c.blk_part = static_cast<double*>(dalloc((size_t)pcg_block_count(c.g) * kMaxBlock * kMaxBlock * sizeof(double)));
+  std::vector<BlockVec> X(s), R(s), P(s), Q(s), Z(s), P2(s);
+  {
+    char* base = static_cast<char*>(c.blk);
+    std::vector<BlockVec>* sets[6] = {&X, &R, &P, &Q, &Z, &P2};
+    for (int k = 0; k < 6; ++k)
+      for (int j = 0; j < s; ++j) (*sets[k])[j].a = base + ((size_t)k * s + j) * v64;
+  }
+  // right-hand sides: R_j = -K[0; EU_j], macro rows sbar_j - B : <C : EU_j>
+  std::vector<std::array<double, 9>> EU(s), sig(s);
+  std::vector<std::array<double, kMaxMacro>> sbar(s);
+  for (int j = 0; j < s; ++j) {
+    double U_rm[9], lst[9];
+    for (int i = 0; i < 9; ++i) U_rm[i] = mask[i] ? 0.0 : loads[9 * j + i];
+    rm_to_stored(c.kin, U_rm, EU[j].data());
+    rm_to_stored(c.kin, loads + 9 * j, lst);
+    sbar[j].fill(0.0);
+    for (int a = 0; a < nS; ++a) sbar[j][a] = bdot(c.kin, ms.bst[a], lst);
+    set_macro(c, EU[j].data());
+    apply_const<double>(c, R[j].a, c.mac_dev, tan64, c.dc_dev);
+    launch_axpby<double>(R[j].a, R[j].a, 0.0, -1.0, 6 * c.g.nh, c.st);
+    double d0[9];
+    read_dc(c, d0);
+    for (int i = 0; i < 9; ++i) sig[j][i] = d0[i];
+    for (int a = 0; a < nS; ++a) R[j].e[a] = sbar[j][a] - bdot(c.kin, ms.bst[a], d0);
+    HIPCK(hipMemsetAsync(X[j].a, 0, v64, c.st));
+    for (int a = 0; a < kMaxMacro; ++a) X[j].e[a] = 0.0;
+  }
+  std::vector<double> rnorm2(s);
+  {
+    std::vector<BlockVec*> all;
+    for (int j = 0; j < s; ++j) all.push_back(&R[j]);
+    const std::vector<double> G = blk_dot(c, all, all, 0);
+    for (int j = 0; j < s; ++j) rnorm2[j] = G[j * s + j];
+  }
+  auto converged = [&](int j, double& eq, double& ld) {
+    const double nrm = frob_stored(c.kin, sig[j].data());
+    const double ra = std::sqrt(std::max(rnorm2[j], 0.0));
+    double rl = 0.0;
+    for (int a = 0; a < nS; ++a) rl += R[j].e[a] * R[j].e[a];
+    rl = std::sqrt(rl);
+    eq = nrm > 0 ? ra / nrm : (ra == 0 ? 0.0 : INFINITY);
+    ld = nrm > 0 ? rl / nrm : (rl == 0 ? 0.0 : INFINITY);
+    return eq < o.tol && ld < o.tol_load;
+  };
+  std::vector<int> active;
+  for (int j = 0; j < s; ++j) {
+    double eq, ld;
+    if (converged(j, eq, ld)) out.col_status[j] = DBFFT_OK;
+    else active.push_back(j);
+  }
+  const int nblk = pcg_block_count(c.g);
+  // Z_j = M R_j over the active columns (R_j projected onto Hermitian pairs first)
+  auto precondition = [&](std::vector<BlockVec*>& Zs) {
+    Zs.clear();
+    for (size_t jj = 0; jj < active.size(); ++jj) {
+      const int j = active[jj];
+      launch_precond_init<double>(Z[j].a, R[j].a, pa, c.g, c.partB, nblk, c.st);
+      for (int a = 0; a < nS; ++a) {
+        double v = 0.0;
+        for (int b = 0; b < nS; ++b) v += pc.Me[a][b] * R[j].e[b];
+        Z[j].e[a] = v;
+      }
+      Zs.push_back(&Z[j]);
+    }
+  };
+  // orthonormal basis of the span of W into P2 (then swapped into P); width returned
+  int m = 0;
+  std::vector<BlockVec*> Pl(s), P2l(s);
+  for (int j = 0; j < s; ++j) {
+    Pl[j] = &P[j];
+    P2l[j] = &P2[j];
+  }
+  // A column's pivot is the squared norm of its part orthogonal to the kept
+  // columns; it is dropped as dependent when that is not above 1e-12 times
+  // ref[j] (its own squared norm, or that of its preconditioned residual
+  // before the conjugation).
+  auto orthonormalize = [&](std::vector<BlockVec*>& W, const std::vector<double>* ref) {
+    const int n = (int)W.size();
+    const std::vector<double> G = blk_dot(c, W, W, nS);
+    std::vector<double> d(n), Lrow(n * n, 0.0), rf(n);
+    for (int i = 0; i < n; ++i) {
+      d[i] = G[i * n + i];
+      rf[i] = ref ? (*ref)[i] : d[i];
+    }
+    std::vector<int> perm, rest;
+    for (int i = 0; i < n; ++i) rest.push_back(i);
+    for (int t = 0; t < n; ++t) {
+      std::vector<int> keep;
+      for (int i : rest)
+        if (d[i] > 1e-12 * rf[i]) keep.push_back(i);
+      rest.swap(keep);
+      if (rest.empty()) break;
+      int j = rest[0];
+      for (int i : rest)
+        if (d[i] > d[j]) j = i;
+      const double piv = std::sqrt(d[j]);
+      Lrow[j * n + t] = piv;
+      rest.erase(std::find(rest.begin(), rest.end(), j));
+      for (int i : rest) {
+        double v = G[i * n + j];
+        for (int u = 0; u < t; ++u) v -= Lrow[i * n + u] * Lrow[j * n + u];
+        Lrow[i * n + t] = v / piv;
+        d[i] -= Lrow[i * n + t] * Lrow[i * n + t];
+      }
+      perm.push_back(j);
+    }
+    const int k = (int)perm.size();
+    // C = L^-T with L the k x k factor of the kept columns (rows in pivot order)
+    std::vector<double> Lk(k * k), Cm(k * k, 0.0);
+    for (int t = 0; t < k; ++t)
+      for (int u = 0; u < k; ++u) Lk[t * k + u] = Lrow[perm[t] * n + u];
+    for (int col = 0; col < k; ++col) {
+      // solve L^T c = e_col  -> column col of L^-T
+      std::vector<double> e(k, 0.0);
+      e[col] = 1.0;
+      for (int i = k - 1; i >= 0; --i) {
+        double v = e[i];
+        for (int r = i + 1; r < k; ++r) v -= Lk[r * k + i] * Cm[r * k + col];
+        Cm[i * k + col] = v / Lk[i * k + i];
+      }
+    }
+    std::vector<BlockVec*> Wk(k), Yk(k);
+    for (int u = 0; u < k; ++u) {
+      Wk[u] = W[perm[u]];
+      Yk[u] = P2l[u];
+    }
+    if (k > 0) blk_comb(c, Wk, Yk, Cm, 0.0, nS, nullptr);
+    std::swap(Pl, P2l);
+    m = k;
+  };
+  std::vector<BlockVec*> Zs;
+  if (!active.empty()) {
+    precondition(Zs);
+    orthonormalize(Zs, nullptr);
+  }
+  while (!active.empty() && m > 0 && out.iterations < o.max_iter) {
+    // Q = K P, with the mean stress of every direction
+    for (int i = 0; i < m; ++i) {
+      double mt[16] = {0};
+      for (int a = 0; a < nS; ++a)
+        for (int k = 0; k < 9; ++k) mt[k] += Pl[i]->e[a] * ms.bst[a][k];
+      HIPCK(hipMemcpyAsync(c.blk_mac + 16 * i, mt, 16 * sizeof(double), hipMemcpyHostToDevice, c.st));
+    }
+    for (int i = 0; i < m; ++i)
+      apply_K<double>(c, Pl[i]->a, Q[i].a, c.blk_mac + 16 * i, nullptr, tan64, c.partA, c.blk_dc + 16 * i, nullptr);
+    double dcP[kMaxBlock][16];
+    HIPCK(hipMemcpyAsync(dcP, c.blk_dc, (size_t)m * 16 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCK(hipStreamSynchronize(c.st));
+    out.applies += m;
+    std::vector<BlockVec*> Ql(m), Ra;
+    for (int i = 0; i < m; ++i) {
+      Ql[i] = &Q[i];
+      for (int a = 0; a < nS; ++a) Q[i].e[a] = bdot(c.kin, ms.bst[a], dcP[i]);
+    }
+    for (int j : active) Ra.push_back(&R[j]);
+    const int na = (int)active.size();
+    std::vector<BlockVec*> Pm(Pl.begin(), Pl.begin() + m);
+    std::vector<double> Gam = blk_dot(c, Pm, Ql, nS);
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < i; ++k) Gam[i * m + k] = Gam[k * m + i] = 0.5 * (Gam[i * m + k] + Gam[k * m + i]);
+    std::vector<double> Lg;
+    if (!chol(Gam, m, Lg)) {
+      out.status = DBFFT_EBREAKDOWN;
+      for (int j : active) out.col_status[j] = DBFFT_EBREAKDOWN;
+      break;
+    }
+    const std::vector<double> alpha = chol_solve(Lg, m, blk_dot(c, Pm, Ra, nS), na);
+    std::vector<BlockVec*> Xa;
+    for (int j : active) Xa.push_back(&X[j]);
+    std::vector<double> nalpha(alpha);
+    for (double& v : nalpha) v = -v;
+    blk_comb(c, Pm, Xa, alpha, 1.0, nS, nullptr);
+    std::vector<double> rn;
+    blk_comb(c, Ql, Ra, nalpha, 1.0, nS, &rn);
+    for (int jj = 0; jj < na; ++jj) {
+      const int j = active[jj];
+      rnorm2[j] = rn[jj];
+      for (int i = 0; i < m; ++i)
+        for (int k = 0; k < 9; ++k) sig[j][k] += alpha[i * na + jj] * dcP[i][k];
+    }
+    out.iterations += 1;
+    std::vector<int> still;
+    for (int j : active) {
+      double eq, ld;
+      if (converged(j, eq, ld)) {
+        out.col_status[j] = DBFFT_OK;
+        out.col_iters[j] = out.iterations;
+      } else {
+        still.push_back(j);
+      }
+    }
+    active.swap(still);
+    if (active.empty()) break;
+    precondition(Zs);
+    const int nz = (int)Zs.size();
+    const std::vector<double> ZZ = blk_dot(c, Zs, Zs, nS);
+    std::vector<double> zref(nz);
+    for (int j = 0; j < nz; ++j) zref[j] = ZZ[j * nz + j];
+    const std::vector<double> beta0 = chol_solve(Lg, m, blk_dot(c, Ql, Zs, nS), nz);
+    std::vector<double> beta(beta0);
+    for (double& v : beta) v = -v;
+    blk_comb(c, Pm, Zs, beta, 1.0, nS, nullptr);
+    orthonormalize(Zs, &zref);
+  }
+  for (int j : active) out.col_iters[j] = out.iterations;
+  // true residuals and averages of every column
+  for (int j = 0; j < s; ++j) {
+    double mt[9], sig_st[9], eq, ld;
+    for (int i = 0; i < 9; ++i) {
+      mt[i] = EU[j][i];
+      for (int a = 0; a < nS; ++a) mt[i] += X[j].e[a] * ms.bst[a][i];
+    }
+    evaluate_linear(c, static_cast<const double*>(X[j].a), mt, ms, sbar[j].data(), sig_st, eq, ld);
+    dbfft_info& inf = infos[j];
+    std::memset(&inf, 0, sizeof(inf));
+    inf.pcg_iters = out.col_iters[j];
+    inf.increments = 1;
+    inf.status = out.col_status[j];
+    inf.eq_res = eq;
+    inf.load_res = ld;
+    stored_to_rm(c.kin, sig_st, inf.sigma_bar);
+    stored_to_rm(c.kin, mt, inf.eps_bar);
+    if (out.col_status[j] != DBFFT_OK && out.status == DBFFT_OK) out.status = out.col_status[j];
+  }
+  return out;
+}
+
 // ------------------------------------------------------------------ Newton
 static void material_update(Ctx& c, const double* fld, double* sig_out, double dt) {
   HIPCK(hipMemsetAsync(c.fail_dev, 0, sizeof(int), c.st));
@@ -1266,7 +1632,7 @@ static void release(Ctx* c) {
                  c->phase, c->E64, c->E32, c->grain, c->grain21, c->grainC, c->grainS, c->W, c->x, c->r, c->p,
                  c->q, c->b, c->t64, c->sol, c->sol2, c->fa, c->fb, c->fc, c->state, c->state_new, c->tanf,
                  c->tanf32, c->partA, c->partB, c->sc_dev, c->dc_dev, c->mac_dev, c->red_dev, c->fail_dev,
-                 c->ck_buf, c->adj_lam};
+                 c->ck_buf, c->adj_lam, c->blk, c->blk_mac, c->blk_dc, c->blk_part};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
@@ -2428,6 +2794,37 @@ dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t str
   if (status != DBFFT_OK && g_err.empty())
     g_err = status == DBFFT_ENOTCONV ? "iteration cap reached" : "breakdown: <p, K p> <= 0 or NaN";
   return (dbfft_status)status;
+  API_END
+}
+
+dbfft_status dbfft_solve_block(dbfft_ctx* ctx, int32_t nrhs, const double* loads, const uint8_t stress_mask[9],
+                               const dbfft_opts* opts, dbfft_info* infos, int32_t* applies) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !loads || !stress_mask || !infos) DB_THROW(DBFFT_EINVAL, "null argument");
+  Ctx& c = *C(ctx);
+  if (nrhs < 1 || nrhs > kMaxBlock) DB_THROW(DBFFT_EINVAL, "nrhs must be 1 .. 6");
+  if (!c.linear_material()) DB_THROW(DBFFT_EUNSUPPORTED, "block solves take linear materials");
+  if (c.prec != DBFFT_FP64) DB_THROW(DBFFT_EUNSUPPORTED, "block solves run in FP64");
+  dbfft_opts o;
+  if (opts) o = *opts;
+  else dbfft_default_opts(&o);
+  int mask[9];
+  for (int i = 0; i < 9; ++i) mask[i] = stress_mask[i] ? 1 : 0;
+  if (c.kin == KIN_SMALL) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        if (mask[i * 3 + j] != mask[j * 3 + i]) DB_THROW(DBFFT_EINVAL, "small strains need a symmetric stress mask");
+        for (int r = 0; r < nrhs; ++r)
+          if (loads[9 * r + i * 3 + j] != loads[9 * r + j * 3 + i])
+            DB_THROW(DBFFT_EINVAL, "small strains need symmetric loads");
+      }
+  }
+  const BlockOut bo = block_solve(c, nrhs, loads, mask, o, infos);
+  if (applies) *applies = bo.applies;
+  if (bo.status != DBFFT_OK && g_err.empty())
+    g_err = bo.status == DBFFT_ENOTCONV ? "iteration cap reached" : "breakdown: block <P, K P> not positive definite";
+  return (dbfft_status)bo.status;
   API_END
 }
 

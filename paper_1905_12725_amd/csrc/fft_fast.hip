@@ -430,6 +430,11 @@ __device__ __forceinline__ void div_pair(long long pr, int n2, int nh3, bool& va
   }
 }
 
+// Row of the divergence a stored stress component (11 22 33 23 13 12)
+// enters through its first index, and the row it enters through its second.
+__host__ __device__ constexpr int div_row_i(int c) { return c < 3 ? c : (c == 3 ? 1 : 0); }
+__host__ __device__ constexpr int div_row_j(int c) { return c < 3 ? c : (c == 5 ? 1 : 2); }
+
 template <typename T, int N>
 __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::NT)) void k_div_update_fast(
     const cpx<T>* in, cpx<T>* r, StridedGeom sg, Geom g, const cpx<T>* __restrict__ twg,
@@ -462,12 +467,18 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
   };
   const T xi2 = (T)xi_of(o, g.n2);
   const T xi3 = (T)xi_of(col, g.n3);
-  cpx<T> a0[E], a1[E], a2[E];
+  // a_i = sum_j xi_j s_ij on the output distribution of the transform
+  cpx<T> acc[3][E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) a0[q] = a1[q] = a2[q] = mk<T>(0, 0);
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int q = 0; q < E; ++q) acc[i][q] = mk<T>(0, 0);
   cpx<T> nx[E];
   loadv(in, nx);
-  const long long cs = sg.cstride_out;
+  // Six stress components in a rolled loop: the next one is loaded while
+  // this one is transformed, then it is added to every row with its
+  // coefficient (zero for the rows it does not enter), so no accumulator is
+  // selected at run time.
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
     cpx<T> v[E];
@@ -476,33 +487,28 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
     if (c + 1 < 6) loadv(in + (c + 1) * sg.cstride_in, nx);
     fast_fft<T, N, E>(v, t, lds, PITCH, s, tw, d);
     if (dc_out != nullptr && valid && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
-    // stored order 11 22 33 23 13 12
-    const int ii = (c < 3) ? c : (c == 3 ? 1 : 0);
-    const int jj = (c < 3) ? c : (c == 5 ? 1 : 2);
+    const int ii = div_row_i(c), jj = div_row_j(c);
 #pragma unroll
     for (int gq = 0; gq < E; ++gq) {
       const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
       const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
       const T xi_ = (ii == 0) ? x1 : (ii == 1 ? xi2 : xi3);
-      const cpx<T> t1 = scl(v[gq], xj);
-      if (ii == 0) a0[gq] = add(a0[gq], t1);
-      else if (ii == 1) a1[gq] = add(a1[gq], t1);
-      else a2[gq] = add(a2[gq], t1);
-      if (ii != jj) {
-        const cpx<T> t2 = scl(v[gq], xi_);
-        if (jj == 0) a0[gq] = add(a0[gq], t2);
-        else if (jj == 1) a1[gq] = add(a1[gq], t2);
-        else a2[gq] = add(a2[gq], t2);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T cf = (k == ii ? xj : (T)0) + ((k == jj && ii != jj) ? xi_ : (T)0);
+        acc[k][gq] = add(acc[k][gq], scl(v[gq], cf));
       }
     }
   }
+
+  const long long cs = sg.cstride_out;
   const double alpha = sc->alpha;
   // r -= alpha q with q = -i a, rounded to the storage precision
   cpx<T> rn[3][E];
 #pragma unroll
   for (int gq = 0; gq < E; ++gq) {
     const long long off = base + (long long)(t + TL * fast_out_pos<N, E>(gq)) * ls;
-    const cpx<T> qv[3] = {muli(a0[gq], (T)-1), muli(a1[gq], (T)-1), muli(a2[gq], (T)-1)};
+    const cpx<T> qv[3] = {muli(acc[0][gq], (T)-1), muli(acc[1][gq], (T)-1), muli(acc[2][gq], (T)-1)};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cpx<T> rv0 = valid ? r[off + c * cs] : mk<T>(0, 0);

@@ -217,4 +217,104 @@ void launch_reduce(const double* partials, int nparts, int nvals, double* out, h
   DB_LAUNCH(k_reduce, dim3(1), dim3(kVecThreads), 0, st, partials, nparts, nvals, out);
 }
 
+// ------------------------------------------------------------- block PCG
+// Inner products of two blocks of 3-component half-spectrum vectors (FP64):
+// partials[b * na * nb + i * nb + j] = block b's part of
+// sum_k w(k3) Re(conj(A_i(k)) B_j(k)), the weighted real inner product.
+__global__ __launch_bounds__(kVecThreads) void k_block_dot(BlockVecs A, BlockVecs B, int na, int nb, Geom g,
+                                                           double* __restrict__ partials) {
+  __shared__ double red[kVecThreads / 64];
+  double acc[kMaxBlock][kMaxBlock];
+#pragma unroll
+  for (int i = 0; i < kMaxBlock; ++i)
+#pragma unroll
+    for (int j = 0; j < kMaxBlock; ++j) acc[i][j] = 0.0;
+  const long long nh = g.nh;
+  for (long long k = (long long)blockIdx.x * kVecThreads + threadIdx.x; k < nh;
+       k += (long long)gridDim.x * kVecThreads) {
+    const double w = half_weight((int)(k % g.nh3), g.n3);
+    cpx<double> a[kMaxBlock][3];
+#pragma unroll
+    for (int i = 0; i < kMaxBlock; ++i)
+      if (i < na)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[i][c] = static_cast<const cpx<double>*>(A.v[i])[c * nh + k];
+#pragma unroll
+    for (int j = 0; j < kMaxBlock; ++j) {
+      if (j >= nb) break;
+      cpx<double> bv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bv[c] = static_cast<const cpx<double>*>(B.v[j])[c * nh + k];
+#pragma unroll
+      for (int i = 0; i < kMaxBlock; ++i)
+        if (i < na) {
+          double t = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) t += a[i][c].x * bv[c].x + a[i][c].y * bv[c].y;
+          acc[i][j] += w * t;
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxBlock; ++i)
+#pragma unroll
+    for (int j = 0; j < kMaxBlock; ++j)
+      if (i < na && j < nb) {
+        const double sum = block_sum<kVecThreads>(acc[i][j], red);
+        if (threadIdx.x == 0) partials[(long long)blockIdx.x * na * nb + i * nb + j] = sum;
+      }
+}
+
+// Y_j = ybeta Y_j + sum_i X_i C[i][j] (j < ny, i < nx), FP64.  norms != null:
+// block partials of the weighted squared norm of every Y_j after the update,
+// partials[b * ny + j].
+__global__ __launch_bounds__(kVecThreads) void k_block_comb(BlockVecs X, BlockVecs Y, int nx, int ny, BlockCoef C,
+                                                            double ybeta, Geom g, double* __restrict__ norms) {
+  __shared__ double red[kVecThreads / 64];
+  double nrm[kMaxBlock];
+#pragma unroll
+  for (int j = 0; j < kMaxBlock; ++j) nrm[j] = 0.0;
+  const long long nh = g.nh;
+  for (long long k = (long long)blockIdx.x * kVecThreads + threadIdx.x; k < nh;
+       k += (long long)gridDim.x * kVecThreads) {
+    const double w = half_weight((int)(k % g.nh3), g.n3);
+    cpx<double> x[kMaxBlock][3];
+#pragma unroll
+    for (int i = 0; i < kMaxBlock; ++i)
+      if (i < nx)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[i][c] = static_cast<const cpx<double>*>(X.v[i])[c * nh + k];
+#pragma unroll
+    for (int j = 0; j < kMaxBlock; ++j) {
+      if (j >= ny) break;
+      cpx<double>* y = static_cast<cpx<double>*>(const_cast<void*>(Y.v[j]));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cpx<double> v = (ybeta != 0.0) ? scl(y[c * nh + k], ybeta) : mk<double>(0, 0);
+#pragma unroll
+        for (int i = 0; i < kMaxBlock; ++i)
+          if (i < nx) v = add(v, scl(x[i][c], C.c[i][j]));
+        y[c * nh + k] = v;
+        nrm[j] += w * (v.x * v.x + v.y * v.y);
+      }
+    }
+  }
+  if (norms == nullptr) return;
+#pragma unroll
+  for (int j = 0; j < kMaxBlock; ++j)
+    if (j < ny) {
+      const double sum = block_sum<kVecThreads>(nrm[j], red);
+      if (threadIdx.x == 0) norms[(long long)blockIdx.x * ny + j] = sum;
+    }
+}
+
+void launch_block_dot(const BlockVecs& A, const BlockVecs& B, int na, int nb, const Geom& g, double* partials,
+                      int nblocks, hipStream_t st) {
+  DB_LAUNCH(k_block_dot, dim3(nblocks), dim3(kVecThreads), 0, st, A, B, na, nb, g, partials);
+}
+void launch_block_comb(const BlockVecs& X, const BlockVecs& Y, int nx, int ny, const BlockCoef& C, double ybeta,
+                       const Geom& g, double* norms, int nblocks, hipStream_t st) {
+  DB_LAUNCH(k_block_comb, dim3(nblocks), dim3(kVecThreads), 0, st, X, Y, nx, ny, C, ybeta, g, norms);
+}
+
 }  // namespace dbfft

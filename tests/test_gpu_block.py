@@ -1,0 +1,112 @@
+"""Block PCG (dbfft_solve_block) through the C ABI against the oracle's
+block PCG and against one-load solves.
+
+Bars: FP64 homogenized stress and strain within 1e-10 relative of the
+oracle's block solve and of the one-load GPU solves (all at tol 1e-11);
+block iteration counts within +-2 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_12725_amd import microstructure as ms
+from oracle import solver as so, materials as mt
+
+pytestmark = pytest.mark.gpu
+
+
+def iso_params(E, nu):
+    out = []
+    for e in E:
+        out += [e, nu]
+    return out
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def mandel_loads(scale=1e-3):
+    out = []
+    for i, j in [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]:
+        L = np.zeros((3, 3))
+        L[i, j] = L[j, i] = scale
+        out.append(L)
+    return out
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_block_vs_oracle_block(gpu, mixed):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (16, 16, 16)
+    print(f"case block pcg vs oracle mixed={mixed}", flush=True)
+    phase, _, _ = ms.random_spheres(n, 9, 1.5, 3.0, 0.3)
+    E = [1.0, 50.0]
+    mask = np.zeros((3, 3), bool)
+    loads = mandel_loads()
+    if mixed:
+        mask[1, 1] = mask[2, 2] = True
+        loads = [L * (1.0 - mask) + 1e-3 * mask * (k % 3) for k, L in enumerate(loads)]
+    lam, mu = mt.lame(np.asarray(E)[phase], 0.3)
+    ref, rinfo = so.solve_linear_block(n, so.IsoTangent(lam, mu), loads, mask, tol=1e-11, tol_load=1e-11)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params(E, 0.3)) as cell:
+        infos, applies = cell.solve_block(loads, mask, tol=1e-11, tol_load=1e-11)
+        singles = [cell.solve(L, mask, tol=1e-11, tol_load=1e-11) for L in loads]
+    its = [i["pcg_iters"] for i in infos]
+    print(f"  GPU block {max(its)} iterations, {applies} applies; oracle {rinfo.iterations} / {rinfo.applies}; "
+          f"single {[s['pcg_iters'] for s in singles]}", flush=True)
+    assert abs(max(its) - rinfo.iterations) <= 2
+    assert applies <= 6 * max(its)
+    for inf, r, sg in zip(infos, ref, singles):
+        assert inf["status"] == 0
+        assert inf["eq_res"] < 1.05e-11 and inf["load_res"] < 1.05e-11
+        assert rel(inf["sigma_bar"], r.sigma_bar) < 1e-10
+        assert rel(inf["eps_bar"], r.eps_bar) < 1e-10
+        assert rel(inf["sigma_bar"], sg["sigma_bar"]) < 1e-10
+
+
+def test_block_single_load_is_pcg(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (32, 16, 24)
+    print("case block pcg one load", flush=True)
+    phase, _, _ = ms.random_spheres(n, 4, 2.0, 4.0, 0.25)
+    L = np.array([[1e-3, 2e-4, 0], [2e-4, -3e-4, 1e-4], [0, 1e-4, 5e-4]])
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params([1.0, 20.0], 0.3)) as cell:
+        (inf,), applies = cell.solve_block([L], tol=1e-10)
+        one = cell.solve(L, tol=1e-10, fused_cg=0)
+    assert abs(inf["pcg_iters"] - one["pcg_iters"]) <= 1
+    assert applies == inf["pcg_iters"]
+    assert rel(inf["sigma_bar"], one["sigma_bar"]) < 1e-10
+
+
+def test_block_dependent_loads(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    n = (16, 16, 16)
+    print("case block pcg dependent loads", flush=True)
+    phase, _, _ = ms.random_spheres(n, 5, 1.5, 3.0, 0.3)
+    L1, L2 = mandel_loads()[0], mandel_loads()[5]
+    with Cell(n, "iso_phase", torch.from_numpy(phase), iso_params([1.0, 10.0], 0.3)) as cell:
+        infos, applies = cell.solve_block([L1, 2.0 * L1, L2], tol=1e-11)
+        one = cell.solve(L2, tol=1e-11)
+    it = max(i["pcg_iters"] for i in infos)
+    assert applies <= 2 * it
+    assert rel(infos[1]["sigma_bar"], 2.0 * infos[0]["sigma_bar"]) < 1e-10
+    assert rel(infos[2]["sigma_bar"], one["sigma_bar"]) < 1e-10
+
+
+def test_block_rejects(gpu):
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    from paper_1905_12725_amd._native import DbfftError
+    n = (8, 8, 8)
+    ph = torch.zeros(n, dtype=torch.uint8)
+    with Cell(n, "iso_phase", ph, [1.0, 0.3], precision="fp32_mixed") as cell:
+        with pytest.raises(DbfftError) as ei:
+            cell.solve_block(mandel_loads()[:2])
+        assert ei.value.status == 6
+    with Cell(n, "iso_phase", ph, [1.0, 0.3]) as cell:
+        with pytest.raises(DbfftError) as ei:
+            cell.solve_block(mandel_loads() + mandel_loads()[:1])
+        assert ei.value.status == 1
