@@ -558,7 +558,9 @@ def contrast_sweep(log, grids=((63, 63, 63), (64, 64, 64))):
     inclusion E = k * 70 for k = 1e-5 ... 1e4, nu = 0.3; uniaxial strain
     1e-3, or uniaxial stress with the other five components zero; FP64 PCG
     to 1e-8 equilibrium and 1e-10 loading residual, at most 1e4 iterations.
-    The odd 63^3 grid is the paper's; 64^3 is its power-of-two neighbour."""
+    The odd 63^3 grid is the paper's; 64^3 is its power-of-two neighbour.
+    Under strain control the two-level preconditioner (coarse_kc 1 and 2,
+    through the block solver with one load) is swept beside M(xi)."""
     import torch
     from paper_1905_12725_amd import microstructure as ms
     from paper_1905_12725_amd.api import Cell
@@ -587,6 +589,18 @@ def contrast_sweep(log, grids=((63, 63, 63), (64, 64, 64))):
             key = f"{n[0]}x{n[1]}x{n[2]}_{control}"
             out[key] = {"pcg_iters": iters, "solve_s": times}
             log(f"[bench] contrast sweep {key}: iterations {iters}")
+            if control == "strain":
+                # the two-level preconditioner (exact operator block on the
+                # coarse frequencies |m_a| <= kc) against M(xi) alone
+                for kc in (1, 2):
+                    its2 = []
+                    for k in ks:
+                        with Cell(n, "iso_phase", torch.from_numpy(phase), [70.0, 0.3, 70.0 * k, 0.3]) as cell:
+                            (inf,), _ = cell.solve_block([load], mask, tol=1e-8, tol_load=1e-10, max_iter=10000,
+                                                         coarse_kc=kc, raise_on_fail=False)
+                        its2.append(int(inf["pcg_iters"]))
+                    out[key][f"pcg_iters_two_level_kc{kc}"] = its2
+                    log(f"[bench] contrast sweep {key}: two-level kc={kc} iterations {its2}")
     return out
 
 

@@ -115,6 +115,11 @@ typedef struct {
                           24 N + 48 N bytes per increment, held by the context until the next
                           solve) for dbfft_adjoint; single-cell solves only (a batch keeps
                           none); 0 */
+  int32_t coarse_kc;   /* dbfft_solve_block: 0 uses M(xi) of Sec. 2.5 everywhere; kc >= 1 a two-level
+                          preconditioner: on the coarse Fourier set (every signed frequency
+                          |m_a| <= kc, xi != 0) the inverse of the operator's own block there
+                          (assembled by applying the operator to every coarse unknown, 6 per
+                          point), M(xi) elsewhere; 0 */
 } dbfft_opts;
 
 typedef struct {

@@ -151,6 +151,99 @@ class Space:
         return apply_m
 
 
+def coarse_points(space, kc):
+    """Half-spectrum points of the coarse Fourier set: every signed
+    frequency |m_a| <= kc on all three axes, xi != 0, and on the
+    self-conjugate planes one point of each pair (k, -k).  Returns a list
+    of (k1, k2, k3)."""
+    n1, n2, n3 = space.shape
+    h3 = n3 // 2 + 1
+
+    def sgn(k, n):
+        return k if k <= n // 2 else k - n
+
+    pts, seen = [], set()
+    for k1 in range(n1):
+        for k2 in range(n2):
+            for k3 in range(h3):
+                if max(abs(sgn(k1, n1)), abs(sgn(k2, n2)), abs(sgn(k3, n3))) > kc or space.Z[k1, k2, k3]:
+                    continue
+                plane = k3 == 0 or (n3 % 2 == 0 and k3 == n3 // 2)
+                if plane:
+                    kp = ((-k1) % n1, (-k2) % n2, k3)
+                    if kp in seen:
+                        continue
+                    seen.add((k1, k2, k3))
+                pts.append((k1, k2, k3))
+    return pts
+
+
+class TwoLevelPreconditioner:
+    """Preconditioner with an exact coarse block (a two-level variant of
+    Sec. 2.5 eqs. pred2/pred3).  M(xi) = [xi.Cbar.xi]^-1 is the inverse of
+    the operator's per-frequency diagonal block for the homogeneous mean
+    medium.  Here the unknowns on the coarse Fourier set (coarse_points)
+    instead get the inverse of the heterogeneous operator's own block on
+    that set, E = e_i . K e_j, with e_i the orthonormal real basis of the
+    coarse unknowns (a unit or imaginary unit at one point and component,
+    scaled by 1/sqrt(2), with its conjugate partner on the self-conjugate
+    planes); every other frequency keeps M(xi), the macro block keeps
+    [B:Cbar:B]^-1.  The result is block diagonal with SPD blocks, so SPD.
+    E is built by applying K to every coarse basis vector (its definition)."""
+
+    def __init__(self, space, tangent, kc):
+        self.space = space
+        self.M0 = space.preconditioner(tangent.mean())
+        self.pts = coarse_points(space, kc)
+        self.m = 6 * len(self.pts)
+        cols = []
+        for j in range(self.m):
+            (q, _), _ = space.apply((self.basis(j), np.zeros(len(space.S))), tangent)
+            cols.append(self.coords(q))
+        E = np.array(cols).T
+        self.E = 0.5 * (E + E.T)
+        self.Einv = np.linalg.inv(self.E)
+
+    def _unit(self, j):
+        p, rest = divmod(j, 6)
+        c, part = divmod(rest, 2)
+        return self.pts[p], c, (1j if part else 1.0)
+
+    def basis(self, j):
+        """Coarse basis vector j (field part)."""
+        space = self.space
+        n1, n2, n3 = space.shape
+        a = np.zeros((3,) + sp.half_shape(space.shape), dtype=complex)
+        k, c, u = self._unit(j)
+        a[(c,) + k] = u / np.sqrt(2.0)
+        if k[2] == 0 or (n3 % 2 == 0 and k[2] == n3 // 2):
+            kp = ((-k[0]) % n1, (-k[1]) % n2, k[2])
+            a[(c,) + kp] = np.conj(u) / np.sqrt(2.0)
+        return a
+
+    def coords(self, a):
+        """<e_j, a> for every coarse basis vector: sqrt(2) Re(conj(u) a(k))."""
+        out = np.zeros(self.m)
+        for j in range(self.m):
+            k, c, u = self._unit(j)
+            out[j] = np.sqrt(2.0) * float(np.real(np.conj(u) * a[(c,) + k]))
+        return out
+
+    def __call__(self, r):
+        za, ze = self.M0(r)
+        za = za.copy()
+        y = self.Einv @ self.coords(r[0])
+        n1, n2, n3 = self.space.shape
+        for j in range(self.m):
+            k, c, u = self._unit(j)
+            za[(c,) + k] = 0.0
+            if k[2] == 0 or (n3 % 2 == 0 and k[2] == n3 // 2):
+                za[(c,) + ((-k[0]) % n1, (-k[1]) % n2, k[2])] = 0.0
+        for j in range(self.m):
+            za = za + y[j] * self.basis(j)
+        return za, ze
+
+
 @dataclass
 class PCGInfo:
     iterations: int = 0
@@ -354,7 +447,7 @@ def block_pcg(space, tangent, precond, B, sig0, tol=1e-8, tol_load=1e-10, max_it
 
 
 def solve_linear_block(shape, tangent, loads, stress_mask=None, tol=1e-8, tol_load=1e-10, max_iter=10000,
-                       kin=SMALL):
+                       kin=SMALL, coarse_kc=None):
     """The linear problems of several loads (one stress mask) solved by
     block_pcg; returns a LinearResult per load and the BlockPCGInfo."""
     space = Space(shape, kin, stress_mask)
@@ -365,7 +458,7 @@ def solve_linear_block(shape, tangent, loads, stress_mask=None, tol=1e-8, tol_lo
         B.append((-ka, sbar - space.macro_row(dc0)))
         sig0.append(dc0)
         EUs.append(E_U)
-    M = space.preconditioner(tangent.mean())
+    M = space.preconditioner(tangent.mean()) if coarse_kc is None else TwoLevelPreconditioner(space, tangent, coarse_kc)
     X, sig, info = block_pcg(space, tangent, M, B, sig0, tol, tol_load, max_iter)
     out = [LinearResult(x[0], x[1], sg, E_U + space.macro_tensor(x[1]), None, space, E_U)
            for x, sg, E_U in zip(X, sig, EUs)]
@@ -394,7 +487,7 @@ class LinearResult:
 
 
 def solve_linear(shape, tangent, load, stress_mask=None, tol=1e-8, tol_load=1e-10,
-                 max_iter=10000, x0=None, keep_history=False, kin=SMALL):
+                 max_iter=10000, x0=None, keep_history=False, kin=SMALL, coarse_kc=None):
     """Linear DBFFT solve (Sec. 2.2 strain control, Sec. 2.3 stress/mixed
     control): small-strain elasticity, or (kin=FINITE) the linearized
     finite-strain problem with a fixed tangent K (the system of one Newton
@@ -405,7 +498,7 @@ def solve_linear(shape, tangent, load, stress_mask=None, tol=1e-8, tol_load=1e-1
     E_U, sbar = split_load(space, load)
     (ka, _), dc0 = space.apply(space.zeros(), tangent, E_U)
     b = (-ka, sbar - space.macro_row(dc0))
-    M = space.preconditioner(tangent.mean())
+    M = space.preconditioner(tangent.mean()) if coarse_kc is None else TwoLevelPreconditioner(space, tangent, coarse_kc)
     x, sig, info = pcg(space, tangent, M, b, dc0, tol, tol_load, max_iter, x0, keep_history)
     eps_bar = E_U + space.macro_tensor(x[1])
     return LinearResult(x[0], x[1], sig, eps_bar, info, space, E_U)

@@ -48,6 +48,7 @@ class Opts(ct.Structure):
         ("fused_cg", ct.c_int32),
         ("graph", ct.c_int32),
         ("checkpoint", ct.c_int32),
+        ("coarse_kc", ct.c_int32),
     ]
 
 

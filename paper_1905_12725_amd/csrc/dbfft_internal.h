@@ -275,6 +275,13 @@ void launch_block_dot(const BlockVecs& A, const BlockVecs& B, int na, int nb, co
 void launch_block_comb(const BlockVecs& X, const BlockVecs& Y, int nx, int ny, const BlockCoef& C, double ybeta,
                        const Geom& g, double* norms, int nblocks, hipStream_t st);
 
+// two-level preconditioner (FP64): coordinates of the coarse unknowns of a
+// 3-component vector at the listed half-spectrum points, and their
+// write-back (with the conjugate at plane partners, partner >= 0)
+void launch_coarse_gather(const void* v, const long long* idx, int npts, long long nh, double* out, hipStream_t st);
+void launch_coarse_scatter(void* v, const long long* idx, const long long* partner, int npts, long long nh,
+                           const double* y, hipStream_t st);
+
 // vector utilities
 template <typename T>
 void launch_axpby(void* y, const void* x, double a, double b, long long n2, hipStream_t st);  // y = a x + b y (n2 reals)

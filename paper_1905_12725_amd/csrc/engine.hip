@@ -1089,6 +1089,99 @@ static void blk_comb(Ctx& c, const std::vector<BlockVec*>& X, const std::vector<
   }
 }
 
+// Two-level preconditioner: M(xi) everywhere except on the coarse Fourier
+// set (every signed frequency |m_a| <= kc, xi != 0; one point of each
+// conjugate pair on the self-conjugate planes), whose unknowns get the
+// inverse of the operator's own block E there, E_ij = e_i . K e_j over the
+// orthonormal coarse basis (6 per point: 3 components x real/imaginary
+// unit, scaled by 1/sqrt(2), conjugate partner on the planes).
+struct CoarseLevel {
+  int npts = 0, m = 0;
+  long long* idx = nullptr;      // device: linear half-spectrum index of every point
+  long long* partner = nullptr;  // device: partner index on the planes, -1 elsewhere
+  double* y = nullptr;           // device: m coordinates
+  std::vector<double> L;         // Cholesky factor of E (host)
+  std::vector<double> hy;
+  void release() {
+    for (void* p : {(void*)idx, (void*)partner, (void*)y})
+      if (p) (void)hipFree(p);
+    idx = partner = nullptr;
+    y = nullptr;
+  }
+  ~CoarseLevel() { release(); }
+};
+
+static int signed_freq(int k, int n) { return k <= n / 2 ? k : k - n; }
+// the wavenumber is zero on this axis (k = 0, or the Nyquist index of an even size)
+static bool zero_freq(int k, int n) { return k == 0 || (n % 2 == 0 && k == n / 2); }
+
+static void coarse_build(Ctx& c, CoarseLevel& cl, int kc, const TangentArgs<double>& tan64, void* tmp_a, void* tmp_q) {
+  const Geom& g = c.g;
+  std::vector<long long> hidx, hpar;
+  std::vector<char> seen((size_t)g.nh, 0);
+  for (int k1 = 0; k1 < g.n1; ++k1)
+    for (int k2 = 0; k2 < g.n2; ++k2)
+      for (int k3 = 0; k3 < g.nh3; ++k3) {
+        if (std::max(std::abs(signed_freq(k1, g.n1)), std::max(std::abs(signed_freq(k2, g.n2)),
+                                                              std::abs(signed_freq(k3, g.n3)))) > kc)
+          continue;
+        if (zero_freq(k1, g.n1) && zero_freq(k2, g.n2) && zero_freq(k3, g.n3)) continue;  // null set
+        const long long k = ((long long)k1 * g.n2 + k2) * g.nh3 + k3;
+        const bool plane = k3 == 0 || (g.n3 % 2 == 0 && k3 == g.n3 / 2);
+        long long kp = -1;
+        if (plane) {
+          kp = ((long long)((g.n1 - k1) % g.n1) * g.n2 + (g.n2 - k2) % g.n2) * g.nh3 + k3;
+          if (seen[kp]) continue;
+          seen[k] = 1;
+          if (kp == k) kp = -1;
+        }
+        hidx.push_back(k);
+        hpar.push_back(kp);
+      }
+  cl.npts = (int)hidx.size();
+  cl.m = 6 * cl.npts;
+  if (cl.m == 0) return;
+  if (cl.m > 1200) DB_THROW(DBFFT_EINVAL, "coarse_kc gives more than 1200 coarse unknowns");
+  cl.idx = static_cast<long long*>(dalloc(hidx.size() * sizeof(long long)));
+  cl.partner = static_cast<long long*>(dalloc(hpar.size() * sizeof(long long)));
+  cl.y = static_cast<double*>(dalloc((size_t)cl.m * sizeof(double)));
+  HIPCK(hipMemcpy(cl.idx, hidx.data(), hidx.size() * sizeof(long long), hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(cl.partner, hpar.data(), hpar.size() * sizeof(long long), hipMemcpyHostToDevice));
+  const size_t v64 = 3 * (size_t)g.nh * 2 * sizeof(double);
+  std::vector<double> E((size_t)cl.m * cl.m), unit(cl.m, 0.0);
+  cl.hy.assign(cl.m, 0.0);
+  double zero16[16] = {0};
+  HIPCK(hipMemcpyAsync(c.blk_mac, zero16, sizeof(zero16), hipMemcpyHostToDevice, c.st));
+  for (int j = 0; j < cl.m; ++j) {
+    // e_j, then K e_j and its coarse coordinates: column j of E
+    HIPCK(hipMemsetAsync(tmp_a, 0, v64, c.st));
+    unit[j] = 1.0;
+    HIPCK(hipMemcpyAsync(cl.y, unit.data(), cl.m * sizeof(double), hipMemcpyHostToDevice, c.st));
+    unit[j] = 0.0;
+    launch_coarse_scatter(tmp_a, cl.idx, cl.partner, cl.npts, g.nh, cl.y, c.st);
+    apply_K<double>(c, tmp_a, tmp_q, c.blk_mac, nullptr, tan64, c.partA, c.blk_dc, nullptr);
+    launch_coarse_gather(tmp_q, cl.idx, cl.npts, g.nh, cl.y, c.st);
+    HIPCK(hipMemcpyAsync(cl.hy.data(), cl.y, cl.m * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCK(hipStreamSynchronize(c.st));
+    for (int i = 0; i < cl.m; ++i) E[(size_t)i * cl.m + j] = cl.hy[i];
+  }
+  for (int i = 0; i < cl.m; ++i)
+    for (int j = 0; j < i; ++j) E[(size_t)i * cl.m + j] = E[(size_t)j * cl.m + i] =
+                                    0.5 * (E[(size_t)i * cl.m + j] + E[(size_t)j * cl.m + i]);
+  if (!chol(E, cl.m, cl.L)) DB_THROW(DBFFT_EBREAKDOWN, "coarse block of the operator not positive definite");
+}
+
+// z (= M(xi) r) gets E^-1 r on the coarse unknowns
+static void coarse_apply(Ctx& c, CoarseLevel& cl, const void* r, void* z) {
+  if (cl.m == 0) return;
+  launch_coarse_gather(r, cl.idx, cl.npts, c.g.nh, cl.y, c.st);
+  HIPCK(hipMemcpyAsync(cl.hy.data(), cl.y, cl.m * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCK(hipStreamSynchronize(c.st));
+  cl.hy = chol_solve(cl.L, cl.m, cl.hy, 1);
+  HIPCK(hipMemcpyAsync(cl.y, cl.hy.data(), cl.m * sizeof(double), hipMemcpyHostToDevice, c.st));
+  launch_coarse_scatter(z, cl.idx, cl.partner, cl.npts, c.g.nh, cl.y, c.st);
+}
+
 struct BlockOut {
   int iterations = 0, applies = 0, status = DBFFT_OK;
   std::vector<int> col_iters, col_status;
@@ -1128,6 +1221,8 @@ static BlockOut block_solve(Ctx& c, int s, const double* loads, const int mask[9
     for (int k = 0; k < 6; ++k)
       for (int j = 0; j < s; ++j) (*sets[k])[j].a = base + ((size_t)k * s + j) * v64;
   }
+  CoarseLevel cl;
+  if (o.coarse_kc > 0) coarse_build(c, cl, o.coarse_kc, tan64, P[0].a, Q[0].a);
   // right-hand sides: R_j = -K[0; EU_j], macro rows sbar_j - B : <C : EU_j>
   std::vector<std::array<double, 9>> EU(s), sig(s);
   std::vector<std::array<double, kMaxMacro>> sbar(s);
@@ -1178,6 +1273,7 @@ static BlockOut block_solve(Ctx& c, int s, const double* loads, const int mask[9
     for (size_t jj = 0; jj < active.size(); ++jj) {
       const int j = active[jj];
       launch_precond_init<double>(Z[j].a, R[j].a, pa, c.g, c.partB, nblk, c.st);
+      coarse_apply(c, cl, R[j].a, Z[j].a);
       for (int a = 0; a < nS; ++a) {
         double v = 0.0;
         for (int b = 0; b < nS; ++b) v += pc.Me[a][b] * R[j].e[b];
@@ -2743,6 +2839,7 @@ dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t str
   else dbfft_default_opts(&o);
   c.use_fused = o.fused_cg != 0;
   c.use_graph = o.graph != 0;
+  if (o.coarse_kc != 0) DB_THROW(DBFFT_EUNSUPPORTED, "opts.coarse_kc applies to dbfft_solve_block");
   int mask[9];
   for (int i = 0; i < 9; ++i) mask[i] = stress_mask[i] ? 1 : 0;
   if (c.kin == KIN_SMALL) {
@@ -2935,6 +3032,7 @@ dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_
   if (opts) o = *opts;
   else dbfft_default_opts(&o);
   o.checkpoint = 0;  // batches keep no checkpoints
+  if (o.coarse_kc != 0) DB_THROW(DBFFT_EUNSUPPORTED, "opts.coarse_kc applies to dbfft_solve_block");
   for (int r = 0; r < n; ++r) {
     const Ctx& c = *B.cells[r];
     if (c.kin == KIN_SMALL)

@@ -308,6 +308,47 @@ __global__ __launch_bounds__(kVecThreads) void k_block_comb(BlockVecs X, BlockVe
     }
 }
 
+// Coarse unknowns of a two-level preconditioner: for point p (linear
+// half-spectrum index idx[p]) and component c, out[6p + 2c] = sqrt(2) Re v,
+// out[6p + 2c + 1] = sqrt(2) Im v (the coordinates along the orthonormal
+// coarse basis).
+__global__ void k_coarse_gather(const cpx<double>* __restrict__ v, const long long* __restrict__ idx, int npts,
+                                long long nh, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= 3 * npts) return;
+  const int p = j / 3, c = j % 3;
+  const cpx<double> a = v[c * nh + idx[p]];
+  const double s = 1.4142135623730951;
+  out[6 * p + 2 * c] = s * a.x;
+  out[6 * p + 2 * c + 1] = s * a.y;
+}
+
+// v(k) = (y_re + i y_im) / sqrt(2) at every coarse point, and its conjugate at
+// the partner point (-k) on the self-conjugate planes (partner[p] >= 0)
+__global__ void k_coarse_scatter(cpx<double>* __restrict__ v, const long long* __restrict__ idx,
+                                 const long long* __restrict__ partner, int npts, long long nh,
+                                 const double* __restrict__ y) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= 3 * npts) return;
+  const int p = j / 3, c = j % 3;
+  const double s = 0.7071067811865476;
+  const cpx<double> a = mk<double>(s * y[6 * p + 2 * c], s * y[6 * p + 2 * c + 1]);
+  v[c * nh + idx[p]] = a;
+  if (partner[p] >= 0) v[c * nh + partner[p]] = conj(a);
+}
+
+void launch_coarse_gather(const void* v, const long long* idx, int npts, long long nh, double* out, hipStream_t st) {
+  const int n = 3 * npts;
+  DB_LAUNCH(k_coarse_gather, dim3((n + 255) / 256), dim3(256), 0, st, static_cast<const cpx<double>*>(v), idx, npts,
+            nh, out);
+}
+void launch_coarse_scatter(void* v, const long long* idx, const long long* partner, int npts, long long nh,
+                           const double* y, hipStream_t st) {
+  const int n = 3 * npts;
+  DB_LAUNCH(k_coarse_scatter, dim3((n + 255) / 256), dim3(256), 0, st, static_cast<cpx<double>*>(v), idx, partner,
+            npts, nh, y);
+}
+
 void launch_block_dot(const BlockVecs& A, const BlockVecs& B, int na, int nb, const Geom& g, double* partials,
                       int nblocks, hipStream_t st) {
   DB_LAUNCH(k_block_dot, dim3(nblocks), dim3(kVecThreads), 0, st, A, B, na, nb, g, partials);
