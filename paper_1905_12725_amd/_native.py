@@ -76,6 +76,11 @@ class DbfftError(RuntimeError):
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1905_12725_amd.build`")
+    # The library must bind to the HIP runtime torch already carries: torch
+    # asks for libamdhip64.so, the library for libamdhip64.so.7, so loading
+    # the library first would map a second runtime from the system ROCm
+    # into the process, and the two then fight over the device.
+    import torch  # noqa: F401
     lib = ct.CDLL(path)
     P, I32, I64P, D, DP = ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int64), ct.c_double, ct.POINTER(ct.c_double)
     lib.dbfft_default_opts.argtypes = [ct.POINTER(Opts)]

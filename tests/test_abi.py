@@ -119,3 +119,23 @@ def test_apply_noalloc_rejects_null_arguments_without_gpu():
     assert lib.dbfft_apply_noalloc(n, 0, None, params, 2, None, None, None) == 1
     assert lib.dbfft_apply_noalloc(None, 0, None, params, 2, None, None, None) == 1
     assert "null" in lib.dbfft_last_error().decode()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdbfft.so not built")
+def test_binding_maps_one_hip_runtime():
+    """Loading the binding before torch must not bring a second HIP runtime
+    into the process (torch and the library name it differently)."""
+    import subprocess
+    import sys
+    code = ("from paper_1905_12725_amd import _native\n"
+            "_native.lib()\n"
+            "import torch\n"
+            "paths = set()\n"
+            "for line in open('/proc/self/maps'):\n"
+            "    f = line.split()[-1]\n"
+            "    if 'libamdhip64' in f:\n"
+            "        paths.add(f)\n"
+            "print(len(paths))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
