@@ -44,6 +44,7 @@ struct BatchLaunch {
   const int* boff_z;
   const int* boff_v;
   size_t lds_x, lds_y, lds_z;
+  int gen_x, gen_y, gen_z;  // 1: some cell needs the LDS Stockham engine on this axis
 };
 
 // line lengths the batched two-step kernels are compiled for (x/y: n; z: n3/2)

@@ -54,8 +54,11 @@ __device__ __forceinline__ void batch_mixed_tile(const cpx<T>* in, cpx<T>* out, 
                                  threadIdx.x);
 }
 
-// x pass (axis 0) or y pass (axis 1) of every cell
-template <typename T, int MODE>
+// x pass (axis 0) or y pass (axis 1) of every cell.  GEN = false: every
+// cell takes the two-step register transform on this axis, and the LDS
+// Stockham engine (which needs more registers than the two-step tiles of
+// the plain passes) is left out of the kernel.
+template <typename T, int MODE, bool GEN>
 __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>* __restrict__ D,
                                                               const int* __restrict__ boff, int ncell, int axis,
                                                               int src, int dst, int ncomp, T d) {
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>*
       default: return;
     }
   }
-  strided_core<T, MODE>(buf_of(R, src), buf_of(R, dst), sg, g, *plan, tw, d, TZ, dc, tile, o, c, smem_raw);
+  if constexpr (GEN) strided_core<T, MODE>(buf_of(R, src), buf_of(R, dst), sg, g, *plan, tw, d, TZ, dc, tile, o, c, smem_raw);
+  else (void)plan;
 }
 
 // two-step z pass of a cell: four waves per block, one energy partial per block
@@ -143,7 +147,8 @@ __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, u
   }
 }
 
-template <typename T, int KIN, int LAW>
+// GEN = false: every cell takes the two-step z pass (no LDS engine in the kernel)
+template <typename T, int KIN, int LAW, bool GEN>
 __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __restrict__ D, const int* __restrict__ boff,
                                                         int ncell, int ncomp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -162,8 +167,9 @@ __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __res
       default: return;
     }
   }
-  line_core<T, LP_FUSED, KIN, LAW>(R.W, R.W, R.g, R.p3, R.tw3, R.rtw, R.tan, R.sc->pmac, nullptr, R.partA, R.L, ncomp,
-                              (long long)lb, smem_raw);
+  if constexpr (GEN)
+    line_core<T, LP_FUSED, KIN, LAW>(R.W, R.W, R.g, R.p3, R.tw3, R.rtw, R.tan, R.sc->pmac, nullptr, R.partA, R.L,
+                                     ncomp, (long long)lb, smem_raw);
 }
 
 template <typename T>
@@ -204,39 +210,47 @@ __global__ void kb_flags(const CellDesc<T>* __restrict__ D, int ncell, int* __re
   for (int r = threadIdx.x; r < ncell; r += blockDim.x) flags[r] = D[r].sc->converged;
 }
 
+template <typename T, int MODE>
+static void launch_kb_strided(const BatchLaunch& bl, const CellDesc<T>* D, int axis, int src, int dst, T d,
+                              hipStream_t st) {
+  const dim3 ts(kStridedThreads);
+  const int nb = axis == 0 ? bl.nbx_f : bl.nby;
+  const int* boff = axis == 0 ? bl.boff_xf : bl.boff_y;
+  const size_t lds = axis == 0 ? bl.lds_x : bl.lds_y;
+  if (axis == 0 ? bl.gen_x : bl.gen_y)
+    hipLaunchKernelGGL((kb_strided<T, MODE, true>), dim3(nb), ts, lds, st, D, boff, bl.ncell, axis, src, dst, bl.ncomp, d);
+  else
+    hipLaunchKernelGGL((kb_strided<T, MODE, false>), dim3(nb), ts, lds, st, D, boff, bl.ncell, axis, src, dst, bl.ncomp,
+                       d);
+}
+
+template <typename T, int KIN, int LAW>
+static void launch_kb_line(const BatchLaunch& bl, const CellDesc<T>* D, hipStream_t st) {
+  const dim3 ls(kLineThreads);
+  if (bl.gen_z)
+    hipLaunchKernelGGL((kb_line<T, KIN, LAW, true>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+  else
+    hipLaunchKernelGGL((kb_line<T, KIN, LAW, false>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+}
+
 template <typename T>
 void launch_batch_iteration(const BatchLaunch& bl, const void* desc, hipStream_t st) {
   auto D = static_cast<const CellDesc<T>*>(desc);
-  const int gm = bl.kin == KIN_SMALL ? SP_GRAD_SMALL : SP_GRAD_FINITE;
-  const int dm = bl.kin == KIN_SMALL ? SP_DIV_SMALL : SP_DIV_FINITE;
-  const dim3 ts(kStridedThreads), ls(kLineThreads), vs(kVecThreads);
+  const dim3 vs(kVecThreads);
   // x inverse + gradient: a = p -> W
-  if (gm == SP_GRAD_SMALL)
-    hipLaunchKernelGGL((kb_strided<T, SP_GRAD_SMALL>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
-                       BUF_P, BUF_W, bl.ncomp, (T)1);
-  else
-    hipLaunchKernelGGL((kb_strided<T, SP_GRAD_FINITE>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
-                       BUF_P, BUF_W, bl.ncomp, (T)1);
+  if (bl.kin == KIN_SMALL) launch_kb_strided<T, SP_GRAD_SMALL>(bl, D, 0, BUF_P, BUF_W, (T)1, st);
+  else launch_kb_strided<T, SP_GRAD_FINITE>(bl, D, 0, BUF_P, BUF_W, (T)1, st);
   // y inverse, all components
-  hipLaunchKernelGGL((kb_strided<T, SP_PLAIN>), dim3(bl.nby), ts, bl.lds_y, st, D, bl.boff_y, bl.ncell, 1, BUF_W, BUF_W,
-                     bl.ncomp, (T)1);
+  launch_kb_strided<T, SP_PLAIN>(bl, D, 1, BUF_W, BUF_W, (T)1, st);
   // z: C2R, tangent, R2C
-  if (bl.kin == KIN_SMALL)
-    hipLaunchKernelGGL((kb_line<T, KIN_SMALL, 0>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
-  else if (bl.law == 2)
-    hipLaunchKernelGGL((kb_line<T, KIN_FINITE, 2>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
-  else
-    hipLaunchKernelGGL((kb_line<T, KIN_FINITE, 0>), dim3(bl.nbz), ls, bl.lds_z, st, D, bl.boff_z, bl.ncell, bl.ncomp);
+  if (bl.kin == KIN_SMALL) launch_kb_line<T, KIN_SMALL, 0>(bl, D, st);
+  else if (bl.law == 2) launch_kb_line<T, KIN_FINITE, 2>(bl, D, st);
+  else launch_kb_line<T, KIN_FINITE, 0>(bl, D, st);
   // y forward
-  hipLaunchKernelGGL((kb_strided<T, SP_PLAIN>), dim3(bl.nby), ts, bl.lds_y, st, D, bl.boff_y, bl.ncell, 1, BUF_W, BUF_W,
-                     bl.ncomp, (T)-1);
+  launch_kb_strided<T, SP_PLAIN>(bl, D, 1, BUF_W, BUF_W, (T)-1, st);
   // x forward + divergence: W -> q
-  if (dm == SP_DIV_SMALL)
-    hipLaunchKernelGGL((kb_strided<T, SP_DIV_SMALL>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
-                       BUF_W, BUF_Q, bl.ncomp, (T)-1);
-  else
-    hipLaunchKernelGGL((kb_strided<T, SP_DIV_FINITE>), dim3(bl.nbx_f), ts, bl.lds_x, st, D, bl.boff_xf, bl.ncell, 0,
-                       BUF_W, BUF_Q, bl.ncomp, (T)-1);
+  if (bl.kin == KIN_SMALL) launch_kb_strided<T, SP_DIV_SMALL>(bl, D, 0, BUF_W, BUF_Q, (T)-1, st);
+  else launch_kb_strided<T, SP_DIV_FINITE>(bl, D, 0, BUF_W, BUF_Q, (T)-1, st);
   hipLaunchKernelGGL((kb_alpha<T>), dim3(bl.ncell), vs, 0, st, D, bl.boff_z);
   hipLaunchKernelGGL((kb_update<T>), dim3(bl.nbv), vs, 0, st, D, bl.boff_v, bl.ncell);
   hipLaunchKernelGGL((kb_beta<T>), dim3(bl.ncell), vs, 0, st, D, bl.boff_v);

@@ -2165,6 +2165,12 @@ static void batch_build(Batch& B) {
   B.bl.lds_x = lx;
   B.bl.lds_y = ly;
   B.bl.lds_z = lz;
+  B.bl.gen_x = B.bl.gen_y = B.bl.gen_z = 0;
+  for (int r = 0; r < n; ++r) {
+    if (!B.mx[r]) B.bl.gen_x = 1;
+    if (!B.my[r]) B.bl.gen_y = 1;
+    if (!B.mz[r]) B.bl.gen_z = 1;
+  }
   B.desc_dev = dalloc(B.desc_host.size());
   B.flags_dev = static_cast<int*>(dalloc(n * sizeof(int)));
   HIPCK(hipHostMalloc((void**)&B.flags_host, n * sizeof(int), hipHostMallocDefault));
