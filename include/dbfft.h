@@ -234,6 +234,35 @@ dbfft_status dbfft_solve_block(dbfft_ctx* ctx, int32_t nrhs, const double* loads
 dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_bar[9], double* strain_dev,
                               double* stress_dev, double* disp_dev);
 
+/* Error estimates of Sec. 3 for real fields on the context's grid, as the
+ * paper checks a computed state:
+ *  out[0] equilibrium (eq. chedckeq): ||div sigma||_L2 / ||<sigma>||, the L2
+ *         norm the root mean square over the voxels; at finite strains the
+ *         first Piola-Kirchhoff stress and the reference divergence
+ *         (Sec. 3.3);
+ *  out[1] compatibility (eq. chedckcomp): the largest |component| of
+ *         curl curl eps over the grid, divided by ||<eps>||; at finite strains
+ *         (Sec. 3.3) max |curl_0 F| / ||<F> - I||, the curl of every row of F;
+ *  out[2] loading, strain part (eq. chedckimp): ||<eps>_E - load_E|| /
+ *         ||load_E|| over the components whose stress_mask entry is 0 (at
+ *         finite strains I + <H> against the prescribed F, relative to
+ *         ||load_E - I_E||); 0 when every component is stress-controlled;
+ *  out[3] loading, stress part: ||<sigma>_S - load_S|| / ||<sigma>|| over the
+ *         stress-controlled components S (the denominator of opts.tol_load);
+ *         0 when S is empty.
+ * Derivatives are spectral with the frequencies of Sec. 2.1 (Nyquist
+ * zeroed on even axes).  strain_dev, stress_dev: device doubles
+ * [c][n1][n2][n3] in dbfft_homogenize's layout (small strains: 6 components
+ * 11 22 33 23 13 12; finite strains: 9 components of H = F - I and of P,
+ * row-major); NULL takes that field of the context's last solve.  load,
+ * stress_mask: host, as for dbfft_solve; load NULL leaves out[2] and out[3]
+ * NaN (stress_mask NULL: strain control).  out: 4 host doubles.  The fields
+ * are read, not changed; the context's solution is kept.  A zero
+ * denominator gives 0 if the numerator is 0, else infinity.  EINVAL for a
+ * NULL context or out, or a NULL field without a solve. */
+dbfft_status dbfft_residuals(dbfft_ctx* ctx, const double* strain_dev, const double* stress_dev, const double load[9],
+                             const uint8_t stress_mask[9], double out[4]);
+
 /* Fourier unknowns of the last solve: a (device complex doubles
  * [3][n1][n2][n3/2+1]) and the macro strain on the stress-controlled
  * components (host 3x3 row-major); either may be NULL. */

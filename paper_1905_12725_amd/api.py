@@ -181,6 +181,27 @@ class Cell:
             out["displacement"] = fu
         return out
 
+    def residuals(self, strain=None, stress=None, load=None, stress_mask=None):
+        """dbfft_residuals: (equilibrium, compatibility, loading strain part,
+        loading stress part) of the given real fields, or of the last
+        solve's fields where a field is None."""
+        def field(t):
+            if t is None:
+                return None, None
+            t = t.to(device=self.device, dtype=torch.float64).contiguous()
+            if tuple(t.shape) != (self.ncomp,) + tuple(self.n):
+                raise ValueError(f"field of shape {tuple(t.shape)}, expected {(self.ncomp,) + tuple(self.n)}")
+            return t, _ptr(t)
+        fs, ps = field(strain)
+        fp, pp = field(stress)
+        ld = None if load is None else nat.dvec(np.asarray(load, dtype=np.float64).reshape(9))
+        mk = None if stress_mask is None else \
+            (ct.c_uint8 * 9)(*np.asarray(stress_mask, dtype=bool).reshape(9).astype(np.uint8).tolist())
+        out = (ct.c_double * 4)()
+        nat.check(nat.lib().dbfft_residuals(self._h, ps, pp, ld, mk, out))
+        del fs, fp
+        return np.array(out[:])
+
     def solution(self):
         a = torch.empty((3,) + self.half, dtype=torch.complex128, device=self.device)
         e = (ct.c_double * 9)()

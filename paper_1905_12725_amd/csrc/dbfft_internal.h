@@ -290,6 +290,9 @@ void launch_convert(void* out, const void* in, long long n, hipStream_t st);
 void launch_dot_w(const void* u, const void* v, int isf32, const Geom& g, double* partials, int nblocks,
                   hipStream_t st);
 void launch_reduce(const double* partials, int nparts, int nvals, double* out, hipStream_t st);
+// compatibility operator of the error estimate on 6 (small) or 9 (finite)
+// half-spectrum FP64 components, in place
+void launch_incompat(void* w, const Geom& g, int finite, hipStream_t st);
 
 // materials / fields
 template <typename T>

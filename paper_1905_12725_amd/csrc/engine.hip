@@ -2971,6 +2971,102 @@ dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_ba
   API_END
 }
 
+static double ratio_or_inf(double num, double den) {
+  if (den == 0.0) return num == 0.0 ? 0.0 : INFINITY;
+  return num / den;
+}
+
+dbfft_status dbfft_residuals(dbfft_ctx* ctx, const double* strain_dev, const double* stress_dev, const double load[9],
+                             const uint8_t stress_mask[9], double out[4]) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !out) DB_THROW(DBFFT_EINVAL, "null argument");
+  Ctx& c = *C(ctx);
+  if ((!strain_dev || !stress_dev) && !c.solved) DB_THROW(DBFFT_EINVAL, "no solution yet");
+  const int nc = c.ncomp;
+  const bool fin = c.kin == KIN_FINITE;
+  double mt[9];
+  for (int i = 0; i < 9; ++i) mt[i] = c.EU_st[i] + c.e_st[i];
+  // equilibrium: the divergence coefficients of the stress field (the
+  // residual of the Newton loop), whose weighted half-spectrum norm is the
+  // mean square of div sigma over the voxels (Parseval); <sigma> from the DC bins
+  const double* sig = stress_dev;
+  if (!sig) {
+    if (c.linear_material()) {
+      set_macro(c, mt);
+      strain_field(c, c.sol, c.mac_dev, c.fb, 1);
+      sig = c.fb;
+    } else {
+      sig = c.fc;
+    }
+  }
+  stress_residual(c, sig, c.t64, c.dc_dev);
+  const double div2 = dot64(c, c.t64, c.t64);
+  double sig_st[9], sig_rm[9] = {0};
+  read_dc(c, sig_st);
+  stored_to_rm(c.kin, sig_st, sig_rm);
+  // compatibility: forward transform of the strain components, the curl
+  // operator per frequency, back to real space, largest magnitude
+  const double* eps = strain_dev;
+  if (!eps) {
+    set_macro(c, mt);
+    strain_field(c, c.sol, c.mac_dev, c.fa);
+    eps = c.fa;
+  }
+  Tables<double>& tb = c.td;
+  const StridedGeom sx = xgeom(c), sy = ygeom(c);
+  TangentArgs<double> tan = elastic_tangent<double>(c);
+  launch_line<double>(LP_R2C, c.kin, eps, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, nc, c.st,
+                      nullptr, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, nc, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, nc, sx, c.g, c.p1, tb.tw1, -1, nullptr, c.st, nullptr);
+  for (int i = 0; i < nc; ++i)
+    HIPCK(hipMemcpyAsync(c.red_host + i, static_cast<const double*>(c.W) + 2 * (size_t)i * c.g.nh, sizeof(double),
+                         hipMemcpyDeviceToHost, c.st));
+  launch_incompat(c.W, c.g, fin ? 1 : 0, c.st);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, nc, sx, c.g, c.p1, tb.tw1, +1, nullptr, c.st, nullptr);
+  launch_strided<double>(SP_PLAIN, c.W, c.W, nc, sy, c.g, c.p2, tb.tw2, +1, nullptr, c.st, nullptr);
+  launch_line<double>(LP_C2R, c.kin, c.W, c.fb, c.g, c.p3, tb.tw3, tb.rtw, tan, nullptr, nullptr, nullptr, nc, c.st,
+                      nullptr, nullptr);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(c.st));
+  double eps_st[9] = {0}, eps_rm[9] = {0};
+  for (int i = 0; i < nc; ++i) eps_st[i] = c.red_host[i];
+  stored_to_rm(c.kin, eps_st, eps_rm);
+  const double inc_max = max_abs_diff(c, c.fb, nullptr, (long long)nc * c.g.nvox);
+  double sn = 0.0, en = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    sn += sig_rm[i] * sig_rm[i];
+    en += eps_rm[i] * eps_rm[i];
+  }
+  sn = std::sqrt(sn);
+  en = std::sqrt(en);
+  out[0] = ratio_or_inf(std::sqrt(std::max(div2, 0.0)), sn);
+  out[1] = ratio_or_inf(inc_max, en);
+  if (!load) {
+    out[2] = out[3] = NAN;
+  } else {
+    double ne = 0.0, de = 0.0, ns = 0.0;
+    bool anyE = false, anyS = false;
+    for (int i = 0; i < 9; ++i) {
+      const double id = (fin && i % 4 == 0) ? 1.0 : 0.0;
+      if (stress_mask && stress_mask[i]) {
+        anyS = true;
+        ns += (sig_rm[i] - load[i]) * (sig_rm[i] - load[i]);
+      } else {
+        anyE = true;
+        const double m = eps_rm[i] + id;
+        ne += (m - load[i]) * (m - load[i]);
+        de += (load[i] - id) * (load[i] - id);
+      }
+    }
+    out[2] = anyE ? ratio_or_inf(std::sqrt(ne), std::sqrt(de)) : 0.0;
+    out[3] = anyS ? ratio_or_inf(std::sqrt(ns), sn) : 0.0;
+  }
+  return DBFFT_OK;
+  API_END
+}
+
 struct dbfft_batch {
   Batch impl;
 };

@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kMatThreads) void k_max_abs_diff(const double* __re
   __shared__ double red[kMatThreads];
   double m = 0.0;
   for (long long i = (long long)blockIdx.x * kMatThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kMatThreads)
-    m = fmax(m, fabs(a[i] - b[i]));
+    m = fmax(m, fabs(b != nullptr ? a[i] - b[i] : a[i]));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = kMatThreads / 2; s > 0; s >>= 1) {

@@ -349,6 +349,69 @@ void launch_coarse_scatter(void* v, const long long* idx, const long long* partn
             npts, nh, y);
 }
 
+// ------------------------------------------------------------- error estimates
+// Compatibility measure of Sec. 3 (eq. chedckcomp; its finite-strain form in
+// Sec. 3.3) on the normalized coefficients of a strain field, in place.
+// With A v = xi x v (A_il = e_ikl xi_k): small strains (6 stored components
+// 11 22 33 23 13 12) eta = curl curl eps becomes -A eps A^T; finite strains
+// (9 components H_il, row-major) the row-wise curl (curl H)_ij = e_jkl d_k H_il
+// becomes i (H A^T).  xi is that of the gradient (Nyquist zeroed).
+__global__ __launch_bounds__(kVecThreads) void k_incompat(cpx<double>* __restrict__ w, Geom g, int finite) {
+  const long long k = (long long)blockIdx.x * kVecThreads + threadIdx.x;
+  if (k >= g.nh) return;
+  const FreqIdx f = decode(k, g);
+  const double x1 = xi_of(f.k1, g.n1), x2 = xi_of(f.k2, g.n2), x3 = xi_of(f.k3, g.n3);
+  const double A[3][3] = {{0.0, -x3, x2}, {x3, 0.0, -x1}, {-x2, x1, 0.0}};
+  const long long nh = g.nh;
+  if (finite) {
+    cpx<double> H[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) H[i][l] = w[(i * 3 + l) * nh + k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        cpx<double> s = mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) s = add(s, scl(H[i][l], A[j][l]));
+        w[(i * 3 + j) * nh + k] = mk<double>(-s.y, s.x);  // i s
+      }
+    return;
+  }
+  constexpr int ci[6] = {0, 1, 2, 1, 0, 0}, cj[6] = {0, 1, 2, 2, 2, 1};
+  cpx<double> e[3][3];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const cpx<double> v = w[c * nh + k];
+    e[ci[c]][cj[c]] = v;
+    e[cj[c]][ci[c]] = v;
+  }
+  cpx<double> B[3][3];  // eps A^T
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cpx<double> s = mk<double>(0.0, 0.0);
+#pragma unroll
+      for (int n = 0; n < 3; ++n) s = add(s, scl(e[l][n], A[j][n]));
+      B[l][j] = s;
+    }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    cpx<double> s = mk<double>(0.0, 0.0);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) s = add(s, scl(B[l][cj[c]], A[ci[c]][l]));
+    w[c * nh + k] = scl(s, -1.0);
+  }
+}
+
+void launch_incompat(void* w, const Geom& g, int finite, hipStream_t st) {
+  DB_LAUNCH(k_incompat, dim3((unsigned)((g.nh + kVecThreads - 1) / kVecThreads)), dim3(kVecThreads), 0, st,
+            static_cast<cpx<double>*>(w), g, finite);
+}
+
 void launch_block_dot(const BlockVecs& A, const BlockVecs& B, int na, int nb, const Geom& g, double* partials,
                       int nblocks, hipStream_t st) {
   DB_LAUNCH(k_block_dot, dim3(nblocks), dim3(kVecThreads), 0, st, A, B, na, nb, g, partials);
