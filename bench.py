@@ -41,19 +41,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the 128^3 FP64 kernels measured with rocprofv3
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000; the factors make a 1 GiB device
-# copy read and write 1 GiB).  They hold for the kernel sources whose
+# HBM bytes per launch of the 128^3 kernels (FP64, and FP32 for the
+# FP32-mixed inner iteration) measured with rocprofv3 (FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000; the factors make a 1 GiB device copy read and write
+# 1 GiB).  They hold for the kernel sources whose
 # SHA-256 is recorded here and are reported as null once those change.
 TRAFFIC_SOURCES = ("paper_1905_12725_amd/csrc/fft_fast.hip", "paper_1905_12725_amd/csrc/fft_common.h",
                    "paper_1905_12725_amd/csrc/pcg_core.h", "paper_1905_12725_amd/csrc/pcg.hip")
-TRAFFIC_SHA256 = "1d7ccbcc73ea67e48375a6edf09e173afca8249b934d1a594e4f756486429459"
-TRAFFIC_128_FP64 = {"x_inverse_grad": 149476120, "y_inverse": 201679836, "y_forward": 201679836,
-                    "z_fused_tangent": 207418950, "x_forward_div": 221372451, "cg_beta": 27438,
-                    "cg_direction": 247967850}
+TRAFFIC_SHA256 = "020971b320e27fa0d334d0d42b4a477a341c2766c1ef1e4a045b46d0a6703658"
+TRAFFIC_128 = {
+    "fp64": {"x_inverse_grad": 153574298, "y_inverse": 207064377, "y_forward": 207064377,
+             "z_fused_tangent": 213012266, "x_forward_div": 227516045, "cg_beta": 27999,
+             "cg_direction": 255660763},
+    "fp32_mixed": {"x_inverse_grad": 76850956, "y_inverse": 102415516, "y_forward": 102415516,
+                   "z_fused_tangent": 108642613, "x_forward_div": 124221217, "cg_beta": 27999,
+                   "cg_direction": 127865197},
+}
 
 
-def measured_traffic(n, kind):
+def measured_traffic(n, kind, precision="fp64"):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -61,7 +67,9 @@ def measured_traffic(n, kind):
             h.update(fh.read())
     if h.hexdigest() != TRAFFIC_SHA256 or tuple(n) != (128, 128, 128):
         return None
-    return TRAFFIC_128_FP64.get(kind)
+    return TRAFFIC_128[precision].get(kind)
+
+
 METRIC = "DBFFT operator applies/s (Gvoxel-DOF/s, %HBM) + solve time FP32-mixed vs FP64"
 
 
@@ -673,6 +681,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched FP32-mixed solve of the uneven neo-Hookean batch (for profiling)")
     ap.add_argument("--unfused", action="store_true", help="separate CG vector kernels (fused_cg = 0)")
+    ap.add_argument("--precision", choices=("fp64", "fp32_mixed"), default="fp64",
+                    help="precision of the timed leg (fp32_mixed: to profile the FP32 kernels; "
+                         "the FP32-mixed comparison leg needs fp64 here and is skipped otherwise)")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (reference kernel for HBM byte counters)")
@@ -715,8 +726,9 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     log(f"[bench] {n} spheres vf={phase.mean():.4f}, contrast 100, 6 load cases")
 
-    cell = Cell(n, "iso_phase", torch.from_numpy(phase), params)
+    cell = Cell(n, "iso_phase", torch.from_numpy(phase), params, precision=args.precision)
     fo = {"fused_cg": 0 if args.unfused else 1}
+    wb = 8 if args.precision == "fp64" else 4
     for _ in range(args.warmup):
         run_cases(cell, loads, tol=1e-8, **fo)
     log("[bench] warmup done")
@@ -740,7 +752,7 @@ def main():
     for k, (ms_tot, cnt) in ktime.items():
         if cnt > 0:
             avg = ms_tot / cnt * 1e-3
-            b = kernel_bytes(n, k, 8, fused)
+            b = kernel_bytes(n, k, wb, fused)
             per_kernel[k] = {"avg_us": avg * 1e6, "launches": cnt, "total_ms": ms_tot,
                              "bytes_per_launch": b, "GBps": (b / avg / 1e9) if b else None}
     dom = max((k for k in per_kernel if per_kernel[k]["bytes_per_launch"] > 0),
@@ -748,10 +760,10 @@ def main():
     dk = per_kernel[dom]
     apply_kinds = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div")
     apply_us = sum(per_kernel[k]["avg_us"] for k in apply_kinds if k in per_kernel)
-    apply_bytes = sum(kernel_bytes(n, k, 8, fused) for k in apply_kinds)
+    apply_bytes = sum(kernel_bytes(n, k, wb, fused) for k in apply_kinds)
     iter_kinds = apply_kinds + ("cg_alpha", "cg_update", "cg_beta", "cg_direction")
     iter_us = sum(per_kernel[k]["avg_us"] for k in iter_kinds if k in per_kernel)
-    iter_bytes = sum(kernel_bytes(n, k, 8, fused) for k in iter_kinds)
+    iter_bytes = sum(kernel_bytes(n, k, wb, fused) for k in iter_kinds)
 
     out = {
         "metric": METRIC,
@@ -764,11 +776,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"{n[0]}^3 two-phase random spheres (radius 6-10 voxels, 30 % volume fraction, seed 2), "
-                        "stiffness contrast 100, nu 0.3, six Mandel strain load cases, PCG tol 1e-8, FP64",
+                        "stiffness contrast 100, nu 0.3, six Mandel strain load cases, PCG tol 1e-8, "
+                        + ("FP64" if args.precision == "fp64" else "FP32-mixed"),
             "grid": list(n),
             "volume_fraction": float(phase.mean()),
             "load_cases": 6,
@@ -793,12 +806,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dk["GBps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(n, dom),
+            "traffic": measured_traffic(n, dom, args.precision),
         },
     }
 
     # tight FP64 reference for accuracy, then FP32-mixed vs FP64 at equal accuracy
-    if not args.no_mixed:
+    if not args.no_mixed and args.precision == "fp64":
         ref_cols, _, _ = run_cases(cell, loads, tol=1e-10, tol_load=1e-10, **fo)
         Cref = ceff(ref_cols)
 

@@ -25,6 +25,22 @@ __device__ __forceinline__ int find_cell(const int* __restrict__ boff, int ncell
   return lo;
 }
 
+// Blocks are dispatched to the 8 XCDs round robin, and consecutive tiles
+// of a pass share cache lines where rows are not line-aligned.  The blocks
+// [b0, b1) of a cell are renumbered so that the tiles of each XCD are
+// consecutive: the cell's blocks on XCD 0 take the first tiles, then those
+// on XCD 1, and so on (a bijection onto 0 .. b1 - b0 - 1).
+__device__ __forceinline__ int xcd_local(int b, int b0, int b1) {
+  const int x = b & 7;
+  int before = 0;
+  for (int y = 0; y < x; ++y) {
+    const int f = b0 + ((y - b0) & 7);  // first block of XCD y in the range
+    if (f < b1) before += (b1 - 1 - f) / 8 + 1;
+  }
+  const int fx = b0 + ((x - b0) & 7);
+  return before + (b - fx) / 8;
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T>* buf_of(const CellDesc<T>& R, int which) {
   switch (which) {
@@ -66,7 +82,7 @@ __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>*
   const int r = find_cell(boff, ncell, blockIdx.x);
   const CellDesc<T>& R = D[r];
   if (R.sc->converged) return;
-  const int lb = blockIdx.x - boff[r];
+  const int lb = xcd_local(blockIdx.x, boff[r], boff[r + 1]);
   const Geom& g = R.g;
   StridedGeom sg;
   int tile, o, c, TZ;
