@@ -145,7 +145,10 @@ void dbfft_default_opts(dbfft_opts* opts);
  * residuals and outer corrections); hip_stream: hipStream_t the context
  * enqueues on (NULL = default stream).  The material field is copied.
  * EINVAL on null pointers, non-positive sizes, sizes with prime factors
- * other than 2, 3, 5, 7, unknown or mismatched material kind. */
+ * other than 2, 3, 5, 7 or above 4096, unknown or mismatched material kind.
+ * EUNSUPPORTED (before any GPU work) for lines longer than one block's LDS
+ * holds: n1 or n2 above 1365, n3 above 744 (small strains) or 585 (finite
+ * strains). */
 dbfft_status dbfft_setup(dbfft_ctx** out, const int64_t n[3], int32_t kinematics, int32_t precision,
                          int32_t material, const void* field_dev, const double* params, int32_t nparams,
                          void* hip_stream);

@@ -97,6 +97,19 @@ def test_setup_rejects_invalid_arguments(kwargs, needle):
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libdbfft.so not built")
+@pytest.mark.parametrize("kwargs,needle", [
+    (dict(n=(1372, 4, 4)), "n1 and n2"),          # 2^2 7^3, one past the longest x line
+    (dict(n=(4, 1372, 4)), "n1 and n2"),
+    (dict(n=(4, 4, 750)), "n3 too large"),        # 2 3 5^3: M = 375 > 372
+    (dict(n=(4, 4, 600), kin=1, mat=4, params=(1.0, 3.0)), "n3 too large"),  # finite: M = 300 > 292
+])
+def test_setup_rejects_lines_beyond_the_maximum(kwargs, needle):
+    st, msg = _setup(**kwargs)
+    assert st == 6, (st, msg)  # DBFFT_EUNSUPPORTED
+    assert needle in msg, msg
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdbfft.so not built")
 def test_null_handles_are_rejected():
     from paper_1905_12725_amd import _native
     lib = _native.lib()

@@ -27,6 +27,12 @@ SHAPES = ([(4, 6, n3) for n3 in Z_LENGTHS] + [(n, 6, 8) for n in XY_LENGTHS] + [
           + [(72, 4, 54), (8, 6, 80), (96, 6, 8), (6, 90, 8)])
 
 
+# the longest line each pass takes: n1, n2 <= 1365; the z pass holds a line
+# in LDS, n3 <= 744 at small strains and 585 at finite strains
+MAX_SHAPES = {"small": [(1350, 4, 6), (4, 1344, 4), (4, 6, 720), (3, 4, 735)],
+              "finite": [(1350, 4, 6), (4, 1344, 4), (4, 4, 576), (3, 4, 567)]}
+
+
 def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
@@ -181,3 +187,48 @@ def test_batch_neohooke_lengths_vs_oracle(gpu, prec):
         assert err < bar, n
     for c in cells:
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("kin,n", [(k, n) for k in ("small", "finite") for n in MAX_SHAPES[k]])
+def test_real_apply_maximum_lengths(gpu, kin, n, prec):
+    """The longest x, y and z lines the library accepts (odd and even n3):
+    the real-space operator against the oracle."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case real_apply maximum {kin} {prec} n={n}", flush=True)
+    rng = np.random.default_rng(300 + sum(n))
+    phase = (rng.random(n) < 0.35).astype(np.uint8)
+    u = rng.standard_normal((3,) + n)
+    if kin == "small":
+        lam, mu = mt.lame(np.asarray([1.0, 7.0])[phase], 0.3)
+        tan, okin = so.IsoTangent(lam, mu), so.SMALL
+        cell = Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 7.0, 0.3], precision=prec)
+    else:
+        tan, okin = _neo_tangent_at_identity(phase, [1.0, 10.0]), so.FINITE
+        cell = Cell(n, "neohooke", torch.from_numpy(phase), [1.0, 3.0, 10.0, 30.0], kinematics="finite",
+                    precision=prec)
+    with cell:
+        f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = _oracle_real_apply(n, tan, okin, u)
+    assert rel(f, ref) < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("n", [(1350, 4, 6), (4, 6, 720), (3, 4, 735)])
+def test_solve_maximum_lengths(gpu, n):
+    """Random two-phase cell (contrast 5) on the longest lines, strain
+    control, tol 1e-10: iterations and homogenized stress against the
+    oracle's PCG."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print(f"case solve maximum n={n}", flush=True)
+    rng = np.random.default_rng(310 + sum(n))
+    phase = (rng.random(n) < 0.35).astype(np.uint8)
+    lam, mu = mt.lame(np.asarray([1.0, 5.0])[phase], 0.3)
+    L = np.array([[1e-3, 2e-4, 0.0], [2e-4, -4e-4, 1e-4], [0.0, 1e-4, 3e-4]])
+    ref = so.solve_linear(n, so.IsoTangent(lam, mu), L, tol=1e-10, tol_load=1e-10)
+    with Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 5.0, 0.3]) as cell:
+        info = cell.solve(L, tol=1e-10, tol_load=1e-10)
+    assert info["status"] == 0
+    assert abs(info["pcg_iters"] - ref.info.iterations) <= 2
+    assert rel(info["sigma_bar"], ref.sigma_bar) < 1e-8
