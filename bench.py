@@ -92,8 +92,8 @@ def kernel_bytes(n, kind, wbytes, fused=True):
     entries, 2*wbytes each.  Fused CG iteration: the divergence pass also
     reads and writes r (no q vector, alpha and the Hermitian projection of
     r on the self-conjugate planes done there too), the direction kernel
-    reads r, p, x and writes p, x; otherwise the update kernel reads x, r, p, q and writes x, r and the
-    direction kernel reads r, p and writes p."""
+    reads r, p, x and writes p, x; otherwise the update kernel reads r, q and writes r, and the
+    direction kernel is the same as in the fused iteration."""
     n1, n2, n3 = n
     nh = n1 * n2 * (n3 // 2 + 1)
     c = 2 * wbytes
@@ -109,8 +109,8 @@ def kernel_bytes(n, kind, wbytes, fused=True):
     if fused:
         b.update({"x_forward_div": (6 + 3 + 3) * nh * c, "cg_direction": (9 + 6) * nh * c, "cg_update": 0})
     else:
-        b.update({"x_forward_div": (6 + 3) * nh * c, "cg_update": 6 * 3 * nh * c,
-                  "cg_direction": 3 * 3 * nh * c})
+        b.update({"x_forward_div": (6 + 3) * nh * c, "cg_update": 3 * 3 * nh * c,
+                  "cg_direction": (9 + 6) * nh * c})
     return b[kind]
 
 

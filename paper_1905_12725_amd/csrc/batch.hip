@@ -188,22 +188,24 @@ __global__ __launch_bounds__(kLineThreads) void kb_line(const CellDesc<T>* __res
                                      ncomp, (long long)lb, smem_raw);
 }
 
+// r -= alpha q and the partial sums of beta (x is updated by kb_xp)
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void kb_update(const CellDesc<T>* __restrict__ D, const int* __restrict__ boff,
                                                          int ncell) {
   const int r = find_cell(boff, ncell, blockIdx.x);
   const CellDesc<T>& R = D[r];
   const int lb = blockIdx.x - boff[r];
-  update_core<T>(R.x, R.r, R.p, R.q, R.sc, R.pa, R.g, R.partB, lb, boff[r + 1] - boff[r]);
+  update_core<T>(nullptr, R.r, R.p, R.q, R.sc, R.pa, R.g, R.partB, lb, boff[r + 1] - boff[r]);
 }
 
+// x += alpha p (the step alpha_core left pending), then p = M r + beta p
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void kb_pupdate(const CellDesc<T>* __restrict__ D,
-                                                          const int* __restrict__ boff, int ncell) {
+__global__ __launch_bounds__(kVecThreads) void kb_xp(const CellDesc<T>* __restrict__ D, const int* __restrict__ boff,
+                                                     int ncell) {
   const int r = find_cell(boff, ncell, blockIdx.x);
   const CellDesc<T>& R = D[r];
   const int lb = blockIdx.x - boff[r];
-  pupdate_core<T>(R.p, R.r, R.sc, R.pa, R.g, lb, boff[r + 1] - boff[r]);
+  xp_core<T>(R.x, R.p, R.r, R.sc, R.pa, R.g, lb, boff[r + 1] - boff[r]);
 }
 
 // one block per cell
@@ -270,7 +272,7 @@ void launch_batch_iteration(const BatchLaunch& bl, const void* desc, hipStream_t
   hipLaunchKernelGGL((kb_alpha<T>), dim3(bl.ncell), vs, 0, st, D, bl.boff_z);
   hipLaunchKernelGGL((kb_update<T>), dim3(bl.nbv), vs, 0, st, D, bl.boff_v, bl.ncell);
   hipLaunchKernelGGL((kb_beta<T>), dim3(bl.ncell), vs, 0, st, D, bl.boff_v);
-  hipLaunchKernelGGL((kb_pupdate<T>), dim3(bl.nbv), vs, 0, st, D, bl.boff_v, bl.ncell);
+  hipLaunchKernelGGL((kb_xp<T>), dim3(bl.nbv), vs, 0, st, D, bl.boff_v, bl.ncell);
 }
 
 template <typename T>

@@ -780,15 +780,16 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
         launch_pcg_xp<T>(x, p, r, c.sc_dev, pa, c.g, nb, c.st);
         continue;
       }
+      // K p | alpha (+ macroscopic step) | r -= alpha q | beta | x += alpha p, next p
       apply_K<T>(c, p, q, pmac, nullptr, tan, c.partA, c.dc_dev, stop);
       prof_mark(c, PK_ALPHA);
       launch_pcg_alpha(c.sc_dev, c.partA, neb, c.dc_dev, pc, c.st);
       prof_mark(c, PK_UPDATE);
-      launch_pcg_update<T>(x, r, p, q, c.sc_dev, pa, c.g, c.partB, nb, c.st);
+      launch_pcg_update<T>(nullptr, r, p, q, c.sc_dev, pa, c.g, c.partB, nb, c.st);
       prof_mark(c, PK_BETA);
       launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 0, c.st);
       prof_mark(c, PK_PUPDATE);
-      launch_pcg_pupdate<T>(p, r, c.sc_dev, pa, c.g, nb, c.st);
+      launch_pcg_xp<T>(x, p, r, c.sc_dev, pa, c.g, nb, c.st);
     }
     if (sample == check_every - 1) {
       c.prof_tag = sample;

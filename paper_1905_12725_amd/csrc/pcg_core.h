@@ -80,7 +80,8 @@ __device__ __forceinline__ long long partner_index(const FreqIdx& f, const Geom&
 
 __device__ __forceinline__ bool conj_plane(int k3, int n3) { return k3 == 0 || 2 * k3 == n3; }
 
-// x += alpha p; r -= alpha q; partial <r, M r> and <r, r>.
+// x += alpha p (x == nullptr: x is left to the direction kernel, xp_core);
+// r -= alpha q; partial <r, M r> and <r, r>.
 // On the planes k3 = 0 and k3 = n3/2 the coefficients of a real field are
 // Hermitian, a(-k1, -k2) = conj a(k1, k2), and the real inverse transform
 // sees only that part.  Rounding in the transforms leaves a small
@@ -109,20 +110,21 @@ __device__ __forceinline__ void update_core(cpx<T>* __restrict__ x, cpx<T>* __re
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long o = c * nh + k;
-      cpx<double> xc = add(up(x[o]), scl(up(p[o]), alpha));
       cpx<double> rc = sub(up(r[o]), scl(up(q[o]), alpha));
       if (conj_plane(f.k3, g.n3)) {
         const long long op = c * nh + kp;
-        const cpx<double> xp = add(up(x[op]), scl(up(p[op]), alpha));
         const cpx<double> rp = sub(up(r[op]), scl(up(q[op]), alpha));
-        xc = scl(add(xc, conj(xp)), 0.5);
         rc = scl(add(rc, conj(rp)), 0.5);
-        if (kp != k) {
-          x[op] = down<T>(conj(xc));
-          r[op] = down<T>(conj(rc));
+        if (kp != k) r[op] = down<T>(conj(rc));
+        if (x != nullptr) {
+          const cpx<double> xc = scl(add(add(up(x[o]), scl(up(p[o]), alpha)),
+                                         conj(add(up(x[op]), scl(up(p[op]), alpha)))), 0.5);
+          if (kp != k) x[op] = down<T>(conj(xc));
+          x[o] = down<T>(xc);
         }
+      } else if (x != nullptr) {
+        x[o] = down<T>(add(up(x[o]), scl(up(p[o]), alpha)));
       }
-      x[o] = down<T>(xc);
       r[o] = down<T>(rc);
       rv[c] = up(down<T>(rc));
     }
@@ -277,20 +279,27 @@ __device__ __forceinline__ void alpha_only_core(PcgScalars* __restrict__ sc, con
 }
 
 // alpha = <r,z>/<p,Kp>; macro block of x and r; tracked average stress.
-// partials: energy sums of the z pass (one per block) = <p, K p>.
+// partials: energy sums of the z pass (one per block) = <p, K p>.  The
+// field part of x takes alpha p in the direction kernel (`pending`, as in
+// the fused iteration) unless the update kernel is given x.
 __device__ __forceinline__ void alpha_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
                                            int nparts, const double* __restrict__ dc, const PcgConst& pc) {
   __shared__ double red[kVecThreads / 64];
-  if (sc->converged) return;
+  if (sc->converged) {
+    if (threadIdx.x == 0) sc->pending = 0;
+    return;
+  }
   const double pq = reduce_fixed(partials, nparts, 1, 0, red);
   if (threadIdx.x != 0) return;
   sc->pq = pq;
   if (!(pq > 0.0)) {
     sc->converged = 2;
+    sc->pending = 0;
     return;
   }
   const double alpha = sc->rz / pq;
   sc->alpha = alpha;
+  sc->pending = 1;
   macro_step(sc, alpha, dc, pc);
 }
 
