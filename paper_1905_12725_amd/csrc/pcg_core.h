@@ -285,22 +285,36 @@ __device__ __forceinline__ void alpha_only_core(PcgScalars* __restrict__ sc, con
 __device__ __forceinline__ void alpha_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
                                            int nparts, const double* __restrict__ dc, const PcgConst& pc) {
   __shared__ double red[kVecThreads / 64];
-  if (sc->converged) {
-    if (threadIdx.x == 0) sc->pending = 0;
+  // state staged in LDS while the partials are read (as in beta_core)
+  __shared__ PcgScalars s;
+  __shared__ double sdc[9];
+  constexpr int kWords = (int)(sizeof(PcgScalars) / sizeof(int));
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kWords; i += blockDim.x)
+    reinterpret_cast<int*>(&s)[i] = reinterpret_cast<const int*>(sc)[i];
+  if (tid < 9) sdc[tid] = dc[tid];
+  double pv = 0.0;
+  for (int i = tid; i < nparts; i += blockDim.x) pv += partials[i];
+  const double pq = block_sum<kVecThreads>(pv, red);
+  if (s.converged) {
+    if (tid == 0) sc->pending = 0;
     return;
   }
-  const double pq = reduce_fixed(partials, nparts, 1, 0, red);
-  if (threadIdx.x != 0) return;
-  sc->pq = pq;
-  if (!(pq > 0.0)) {
-    sc->converged = 2;
-    sc->pending = 0;
-    return;
+  if (tid == 0) {
+    s.pq = pq;
+    if (!(pq > 0.0)) {
+      s.converged = 2;
+      s.pending = 0;
+    } else {
+      const double alpha = s.rz / pq;
+      s.alpha = alpha;
+      s.pending = 1;
+      macro_step(&s, alpha, sdc, pc);
+    }
   }
-  const double alpha = sc->rz / pq;
-  sc->alpha = alpha;
-  sc->pending = 1;
-  macro_step(sc, alpha, dc, pc);
+  __syncthreads();
+  for (int i = tid; i < kWords; i += blockDim.x)
+    reinterpret_cast<int*>(sc)[i] = reinterpret_cast<const int*>(&s)[i];
 }
 
 // beta, macro block of p, convergence.  first == 1: initial call after
@@ -314,56 +328,79 @@ __device__ __forceinline__ void beta_core(PcgScalars* __restrict__ sc, const dou
                                           int nparts, const PcgConst& pc, int first,
                                           const double* __restrict__ dc = nullptr) {
   __shared__ double red[kVecThreads / 64];
-  if (sc->converged) return;
-  const double rz_a = reduce_fixed(partials, nparts, 2, 0, red);
-  const double rr = reduce_fixed(partials, nparts, 2, 1, red);
-  if (threadIdx.x != 0) return;
-  if (dc != nullptr) macro_step(sc, sc->alpha, dc, pc);
-  double ze[kMaxMacro];
-  double rz = rz_a, re2 = 0.0;
-  for (int a = 0; a < pc.nmacro; ++a) {
-    double z = 0.0;
-    for (int b = 0; b < pc.nmacro; ++b) z += pc.Me[a][b] * sc->re[b];
-    ze[a] = z;
-    rz += sc->re[a] * z;
-    re2 += sc->re[a] * sc->re[a];
+  // The scalar state is copied to LDS by the first threads while every
+  // thread reads its partial sums, so the single thread that finishes the
+  // step reads no global memory; the block writes the state back.
+  __shared__ PcgScalars s;
+  __shared__ double sdc[9];
+  constexpr int kWords = (int)(sizeof(PcgScalars) / sizeof(int));
+  static_assert(sizeof(PcgScalars) % sizeof(int) == 0, "PcgScalars is copied word by word");
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kWords; i += blockDim.x)
+    reinterpret_cast<int*>(&s)[i] = reinterpret_cast<const int*>(sc)[i];
+  if (dc != nullptr && tid < 9) sdc[tid] = dc[tid];
+  // fixed order: thread t sums partials t, t + blockDim, ... (as reduce_fixed)
+  double pa_ = 0.0, pb_ = 0.0;
+  for (int i = tid; i < nparts; i += blockDim.x) {
+    pa_ += partials[2 * (long long)i];
+    pb_ += partials[2 * (long long)i + 1];
   }
-  double beta = 0.0;
-  if (first == 1) {
-    sc->iter = 0;
-  } else {
-    beta = rz / sc->rz;
-    if (first == 0) sc->iter += 1;
+  const double rz_a = block_sum<kVecThreads>(pa_, red);
+  const double rr = block_sum<kVecThreads>(pb_, red);
+  if (s.converged) return;
+  if (tid == 0) {
+    if (dc != nullptr) macro_step(&s, s.alpha, sdc, pc);
+    double ze[kMaxMacro];
+    double rz = rz_a, re2 = 0.0;
+    for (int a = 0; a < pc.nmacro; ++a) {
+      double z = 0.0;
+      for (int b = 0; b < pc.nmacro; ++b) z += pc.Me[a][b] * s.re[b];
+      ze[a] = z;
+      rz += s.re[a] * z;
+      re2 += s.re[a] * s.re[a];
+    }
+    double beta = 0.0;
+    if (first == 1) {
+      s.iter = 0;
+    } else {
+      beta = rz / s.rz;
+      if (first == 0) s.iter += 1;
+    }
+    s.beta = beta;
+    s.rz = rz;
+    s.rr = rr;
+    s.re2 = re2;
+    const double nrm = pc.scale > 0.0 ? pc.scale : frob_stored(s.sig, pc.ncomp);
+    const double ra = sqrt(rr > 0.0 ? rr : 0.0), rl = sqrt(re2);
+    double eq, ld;
+    if (nrm == 0.0) {
+      eq = (ra == 0.0) ? 0.0 : INFINITY;
+      ld = (rl == 0.0) ? 0.0 : INFINITY;
+    } else {
+      eq = ra / nrm;
+      ld = rl / nrm;
+    }
+    s.eq_res = eq;
+    s.load_res = ld;
+    if (eq < pc.tol && ld < pc.tol_load) s.converged = 1;
+    else if (s.iter >= pc.max_iter) s.converged = 3;
+    // Macro block of the next direction, p_e = z_e + beta p_e, and its
+    // tensor for the next operator application.  Once stopped, p_e (like the
+    // field part of p, which the direction kernels leave alone then) keeps
+    // the last direction, from which an iteration with a replaced residual
+    // goes on.
+    if (!s.converged || first == 1) {
+      for (int a = 0; a < pc.nmacro; ++a) s.pe[a] = ze[a] + beta * s.pe[a];
+      for (int c = 0; c < 9; ++c) {
+        double m = 0.0;
+        for (int a = 0; a < pc.nmacro; ++a) m += s.pe[a] * pc.basis[a][c];
+        s.pmac[c] = m;
+      }
+    }
   }
-  sc->beta = beta;
-  sc->rz = rz;
-  sc->rr = rr;
-  sc->re2 = re2;
-  const double nrm = pc.scale > 0.0 ? pc.scale : frob_stored(sc->sig, pc.ncomp);
-  const double ra = sqrt(rr > 0.0 ? rr : 0.0), rl = sqrt(re2);
-  double eq, ld;
-  if (nrm == 0.0) {
-    eq = (ra == 0.0) ? 0.0 : INFINITY;
-    ld = (rl == 0.0) ? 0.0 : INFINITY;
-  } else {
-    eq = ra / nrm;
-    ld = rl / nrm;
-  }
-  sc->eq_res = eq;
-  sc->load_res = ld;
-  if (eq < pc.tol && ld < pc.tol_load) sc->converged = 1;
-  else if (sc->iter >= pc.max_iter) sc->converged = 3;
-  // Macro block of the next direction, p_e = z_e + beta p_e, and its tensor
-  // for the next operator application.  Once stopped, p_e (like the field
-  // part of p, which the direction kernels leave alone then) keeps the last
-  // direction, from which an iteration with a replaced residual goes on.
-  if (sc->converged && first != 1) return;
-  for (int a = 0; a < pc.nmacro; ++a) sc->pe[a] = ze[a] + beta * sc->pe[a];
-  for (int c = 0; c < 9; ++c) {
-    double m = 0.0;
-    for (int a = 0; a < pc.nmacro; ++a) m += sc->pe[a] * pc.basis[a][c];
-    sc->pmac[c] = m;
-  }
+  __syncthreads();
+  for (int i = tid; i < kWords; i += blockDim.x)
+    reinterpret_cast<int*>(sc)[i] = reinterpret_cast<const int*>(&s)[i];
 }
 
 // fused CG: x += alpha p (if this iteration's step is pending), then
