@@ -153,6 +153,17 @@ dbfft_status dbfft_setup(dbfft_ctx** out, const int64_t n[3], int32_t kinematics
                          int32_t material, const void* field_dev, const double* params, int32_t nparams,
                          void* hip_stream);
 
+/* Side lengths L_1, L_2, L_3 of the cell (Sec. 2.1: the frequencies are
+ * xi_i = 2 pi m_i / L_i); a new context has 1, 1, 1, i.e. the unit cube,
+ * whose voxels are cubic only when n1 = n2 = n3.  len: 3 host doubles,
+ * positive and finite (EINVAL otherwise).  Takes effect for the calls that
+ * follow: the last solution (and any J2 checkpoints) is dropped, since its
+ * coefficients refer to the old frequencies.  Cells of a batch take the
+ * lengths they have when dbfft_batch_create is called.  Homogenized
+ * averages do not depend on a common scale of the three lengths, only on
+ * their ratios. */
+dbfft_status dbfft_set_lengths(dbfft_ctx* ctx, const double len[3]);
+
 /* Real-space operator application of Sec. 2.2 eq. lineqf (sign flipped so
  * that it is positive semi-definite): f = -div(C : sym grad u) for small
  * strains, f = -div(K : grad u) for finite strains, with the tangent of the

@@ -25,8 +25,8 @@ import numpy as np
 from .spectral import mandel_basis, MANDEL_PAIRS
 
 
-def diff_matrix(n):
-    """Periodic spectral differentiation matrix on [0, 1) with n points."""
+def diff_matrix(n, length=1.0):
+    """Periodic spectral differentiation matrix on [0, L) with n points."""
     D = np.zeros((n, n))
     for i in range(n):
         for j in range(n):
@@ -37,23 +37,25 @@ def diff_matrix(n):
                 D[i, j] = np.pi * (-1.0) ** k / np.tan(np.pi * k / n)
             else:
                 D[i, j] = np.pi * (-1.0) ** k / np.sin(np.pi * k / n)
-    return D
+    return D / float(length)
 
 
-def partial_matrices(shape):
-    """Dense d/dx_a acting on C-ordered flattened grid functions."""
+def partial_matrices(shape, lengths=None):
+    """Dense d/dx_a acting on C-ordered flattened grid functions of a cell
+    of side lengths L1, L2, L3 (default 1, 1, 1)."""
     n1, n2, n3 = shape
+    L1, L2, L3 = (1.0, 1.0, 1.0) if lengths is None else lengths
     I1, I2, I3 = np.eye(n1), np.eye(n2), np.eye(n3)
-    return [np.kron(np.kron(diff_matrix(n1), I2), I3),
-            np.kron(np.kron(I1, diff_matrix(n2)), I3),
-            np.kron(np.kron(I1, I2), diff_matrix(n3))]
+    return [np.kron(np.kron(diff_matrix(n1, L1), I2), I3),
+            np.kron(np.kron(I1, diff_matrix(n2, L2)), I3),
+            np.kron(np.kron(I1, I2), diff_matrix(n3, L3))]
 
 
-def strain_map(shape):
+def strain_map(shape, lengths=None):
     """Dense map u (3N, component-major) -> Mandel strains (6, N) as a
     (6N, 3N) matrix: eps_ij = (D_j u_i + D_i u_j)/2."""
     N = int(np.prod(shape))
-    D = partial_matrices(shape)
+    D = partial_matrices(shape, lengths)
     B = np.zeros((6 * N, 3 * N))
     Bm = mandel_basis()
     for a, (i, j) in enumerate(MANDEL_PAIRS):
@@ -66,7 +68,7 @@ def strain_map(shape):
     return B
 
 
-def assemble(shape, C_mandel, stress_mask=None):
+def assemble(shape, C_mandel, stress_mask=None, lengths=None):
     """Dense Hessian of the average energy in the unknowns (u (3N), e (|S|)).
     C_mandel: (N, 6, 6) per-voxel Mandel stiffness (C-order voxels).
     Returns (K, Bu, S) with Bu the strain map and S the Mandel indices."""
@@ -74,7 +76,7 @@ def assemble(shape, C_mandel, stress_mask=None):
     if stress_mask is None:
         stress_mask = np.zeros((3, 3), dtype=bool)
     S = [a for a, (i, j) in enumerate(MANDEL_PAIRS) if stress_mask[i, j]]
-    Bu = strain_map(shape)
+    Bu = strain_map(shape, lengths)
     # block-diagonal per-voxel stiffness acting on Mandel fields (6, N)
     Cb = np.zeros((6 * N, 6 * N))
     for a in range(6):
@@ -89,14 +91,14 @@ def assemble(shape, C_mandel, stress_mask=None):
     return K, Bfull, Cb, S
 
 
-def solve(shape, C_mandel, load, stress_mask=None):
+def solve(shape, C_mandel, load, stress_mask=None, lengths=None):
     """Direct solve of the linear problem.  Returns (u (3, n1, n2, n3),
     e (|S|), <sigma> (3x3))."""
     N = int(np.prod(shape))
     if stress_mask is None:
         stress_mask = np.zeros((3, 3), dtype=bool)
     mask = np.asarray(stress_mask, dtype=bool)
-    K, Bfull, Cb, S = assemble(shape, C_mandel, mask)
+    K, Bfull, Cb, S = assemble(shape, C_mandel, mask, lengths)
     Bm = mandel_basis()
     load = np.asarray(load, dtype=np.float64)
     E_U = load * (~mask)

@@ -79,11 +79,11 @@ class Space:
     """Discrete setting of one RVE: grid, frequencies, null set, weights and
     the macroscopic basis restricted to the stress-controlled set S."""
 
-    def __init__(self, shape, kin=SMALL, stress_mask=None):
+    def __init__(self, shape, kin=SMALL, stress_mask=None, lengths=None):
         self.shape = tuple(int(v) for v in shape)
         self.N = float(np.prod(self.shape))
         self.kin = kin
-        self.xi = sp.xi_half(self.shape)
+        self.xi = sp.xi_half(self.shape, lengths)
         self.Z = sp.null_set(self.shape)
         self.w = sp.half_weights(self.shape)
         if stress_mask is None:
@@ -487,14 +487,15 @@ class LinearResult:
 
 
 def solve_linear(shape, tangent, load, stress_mask=None, tol=1e-8, tol_load=1e-10,
-                 max_iter=10000, x0=None, keep_history=False, kin=SMALL, coarse_kc=None):
+                 max_iter=10000, x0=None, keep_history=False, kin=SMALL, coarse_kc=None, lengths=None):
     """Linear DBFFT solve (Sec. 2.2 strain control, Sec. 2.3 stress/mixed
     control): small-strain elasticity, or (kin=FINITE) the linearized
     finite-strain problem with a fixed tangent K (the system of one Newton
     step, Sec. 2.4).  `load` holds the prescribed strain (displacement
     gradient) on strain-controlled components and the prescribed stress on
-    the components where stress_mask is true."""
-    space = Space(shape, kin, stress_mask)
+    the components where stress_mask is true.  `lengths`: the cell's side
+    lengths (Sec. 2.1), default 1, 1, 1."""
+    space = Space(shape, kin, stress_mask, lengths)
     E_U, sbar = split_load(space, load)
     (ka, _), dc0 = space.apply(space.zeros(), tangent, E_U)
     b = (-ka, sbar - space.macro_row(dc0))
@@ -534,7 +535,7 @@ class NewtonInfo:
 
 def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
            newton_tol=1e-6, max_newton=25, max_iter=10000, refresh="increment",
-           state=None, checkpoints=None):
+           state=None, checkpoints=None, lengths=None):
     """Incremental Newton-DBFFT driver.
 
     law.update(field, state) -> (stress, tangent_obj, new_state) where field
@@ -546,7 +547,7 @@ def newton(shape, law, loads, stress_mask, kin=SMALL, tol=1e-8, tol_load=1e-10,
     checkpoints: a list that receives, per increment, the converged (a, e,
     E_U) and the law state the increment started from.
     Returns (a, e, state, info)."""
-    space = Space(shape, kin, stress_mask)
+    space = Space(shape, kin, stress_mask, lengths)
     a, e = space.zeros()
     info = NewtonInfo()
     Cbar = None

@@ -1,8 +1,8 @@
 """Fourier-space building blocks of DBFFT (oracle; test infrastructure only).
 
 Conventions (readings of the paper where it leaves a choice open):
-  * unit cell, L_a = 1; voxel-centre sampling (Sec. 2.1);
-  * xi_a = 2 pi m_a with m_a the signed DFT frequency of index k_a; on even
+  * cell of side lengths L_a (default 1); voxel-centre sampling (Sec. 2.1);
+  * xi_a = 2 pi m_a / L_a with m_a the signed DFT frequency of index k_a; on even
     grids the Nyquist index k_a = n_a/2 gets xi_a = 0 (Sec. 2.1 leaves even
     grids open and mentions neglecting the Nyquist frequencies);
   * the unknown is the normalized Fourier coefficient a = F[u]/N, so that
@@ -18,14 +18,15 @@ from __future__ import annotations
 import numpy as np
 
 
-def axis_xi(n):
-    """Frequencies xi = 2 pi m of one axis of n points, in DFT index order
-    (Sec. 2.1, frequency vector; Nyquist zeroed on even n)."""
+def axis_xi(n, length=1.0):
+    """Frequencies xi = 2 pi m / L of one axis of n points over a length L,
+    in DFT index order (Sec. 2.1, frequency vector; Nyquist zeroed on even
+    n)."""
     k = np.arange(n)
     m = np.where(k < (n + 1) // 2, k, k - n).astype(np.float64)
     if n % 2 == 0:
         m[n // 2] = 0.0
-    return 2.0 * np.pi * m
+    return 2.0 * np.pi * m / float(length)
 
 
 def half_shape(shape):
@@ -33,13 +34,15 @@ def half_shape(shape):
     return (n1, n2, n3 // 2 + 1)
 
 
-def xi_half(shape):
-    """Frequency vector field on the half spectrum, shape (3, n1, n2, n3//2+1)."""
+def xi_half(shape, lengths=None):
+    """Frequency vector field on the half spectrum, shape (3, n1, n2, n3//2+1),
+    for a cell of side lengths L1, L2, L3 (default 1, 1, 1)."""
     n1, n2, n3 = shape
+    L1, L2, L3 = (1.0, 1.0, 1.0) if lengths is None else lengths
     h = half_shape(shape)
-    x1 = axis_xi(n1)[:, None, None]
-    x2 = axis_xi(n2)[None, :, None]
-    x3 = axis_xi(n3)[: n3 // 2 + 1][None, None, :]
+    x1 = axis_xi(n1, L1)[:, None, None]
+    x2 = axis_xi(n2, L2)[None, :, None]
+    x3 = axis_xi(n3, L3)[: n3 // 2 + 1][None, None, :]
     xi = np.zeros((3,) + h)
     xi[0] = np.broadcast_to(x1, h)
     xi[1] = np.broadcast_to(x2, h)

@@ -73,7 +73,7 @@ class Cell:
     """One periodic cell (grid + material) bound to a HIP stream."""
 
     def __init__(self, n, material, field, params, kinematics="small", precision="fp64", stream=None,
-                 device="cuda"):
+                 device="cuda", lengths=None):
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
         self.kin = kinematics
@@ -97,6 +97,17 @@ class Cell:
         self._h = h
         self.ncomp = 6 if kinematics == "small" else 9
         self.half = (self.n[0], self.n[1], self.n[2] // 2 + 1)
+        self.lengths = (1.0, 1.0, 1.0)
+        if lengths is not None:
+            self.set_lengths(lengths)
+
+    def set_lengths(self, lengths):
+        """dbfft_set_lengths: side lengths L1, L2, L3 of the cell."""
+        L = [float(v) for v in lengths]
+        if len(L) != 3:
+            raise ValueError("three cell lengths expected")
+        nat.check(nat.lib().dbfft_set_lengths(self._h, nat.dvec(L, 3)))
+        self.lengths = tuple(L)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -56,6 +56,7 @@ struct Geom {
   long long nh;         // n1*n2*nh3
   long long nvox;       // n1*n2*n3
   double inv_nvox;
+  double il1, il2, il3;  // 1 / cell side length per axis (frequencies 2 pi m / L)
 };
 
 enum Kin : int { KIN_SMALL = 0, KIN_FINITE = 1 };

@@ -1772,6 +1772,7 @@ static void init_grid(Ctx* c, const int64_t n[3], int kin, int prec, int mat, vo
   g.nh = (long long)g.n1 * g.n2 * g.nh3;
   g.nvox = (long long)g.n1 * g.n2 * g.n3;
   g.inv_nvox = 1.0 / (double)g.nvox;
+  g.il1 = g.il2 = g.il3 = 1.0;
   if (!make_plan(g.n1, c->p1) || !make_plan(g.n2, c->p2) || !make_plan(z_length(g.n3), c->p3))
     DB_THROW(DBFFT_EINVAL, "cannot plan the transform lengths");
 }
@@ -2968,6 +2969,29 @@ dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_ba
   }
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(c.st));
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_set_lengths(dbfft_ctx* ctx, const double len[3]) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !len) DB_THROW(DBFFT_EINVAL, "null argument");
+  for (int a = 0; a < 3; ++a)
+    if (!(len[a] > 0.0) || !std::isfinite(len[a])) DB_THROW(DBFFT_EINVAL, "cell lengths must be positive and finite");
+  Ctx& c = *C(ctx);
+  HIPCK(hipStreamSynchronize(c.st));
+  c.g.il1 = 1.0 / len[0];
+  c.g.il2 = 1.0 / len[1];
+  c.g.il3 = 1.0 / len[2];
+  // the captured PCG chunk holds the old geometry; the last solution refers to the old frequencies
+  if (c.chunk_exec) HIPCK(hipGraphExecDestroy(c.chunk_exec));
+  if (c.chunk_graph) HIPCK(hipGraphDestroy(c.chunk_graph));
+  c.chunk_exec = nullptr;
+  c.chunk_graph = nullptr;
+  c.chunk_key.clear();
+  c.solved = false;
+  c.ck_n = 0;
   return DBFFT_OK;
   API_END
 }

@@ -39,12 +39,13 @@ __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T>
 __device__ __forceinline__ cpx<T> muli(cpx<T> a, T d) { return mk<T>(-d * a.y, d * a.x); }
 
-// signed frequency 2*pi*m of DFT index k on an axis of n points; the even-grid
-// Nyquist index gets 0.
-__device__ __forceinline__ double xi_of(int k, int n) {
+// frequency 2 pi m / L of DFT index k on an axis of n points and length L
+// (Sec. 2.1; inv_len = 1/L), m the signed index; the even-grid Nyquist index
+// gets 0.
+__device__ __forceinline__ double xi_of(int k, int n, double inv_len) {
   int m = (2 * k < n) ? k : k - n;
   if (2 * k == n) m = 0;
-  return kTwoPi * (double)m;
+  return kTwoPi * (double)m * inv_len;
 }
 
 // radix-R DFT in registers, exponent sign d (-1 forward, +1 inverse)

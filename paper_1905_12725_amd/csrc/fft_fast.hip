@@ -222,8 +222,8 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
     // eps_ij = i/2 (xi_j a_i + xi_i a_j) is formed on the coefficients (xi1
     // varies along the line) and transformed on its own; the three
     // displacement components are loaded once, up front.
-    const T xi2 = (T)xi_of(o, g.n2);
-    const T xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2);
+    const T xi3 = (T)xi_of(col, g.n3, g.il3);
     const long long co = sg.cstride_out;
     cpx<T> A0[E], A1[E], A2[E];
     loadv(in, A0);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
     auto emit = [&](int c, auto&& form) {
       cpx<T> v[E];
 #pragma unroll
-      for (int r = 0; r < E; ++r) v[r] = form(r, (T)xi_of(t + TL * r, g.n1));
+      for (int r = 0; r < E; ++r) v[r] = form(r, (T)xi_of(t + TL * r, g.n1, g.il1));
       fast_fft<T, N, E>(v, t, lds, PITCH, s, tw, d);
       storev(out + c * co, v);
     };
@@ -246,11 +246,11 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
   } else if constexpr (MODE == SP_GRAD_FINITE) {
     // With T_i = FFT(a_i) and U_i = FFT(xi1 a_i): H_i1 = i U_i,
     // H_i2 = i xi2 T_i, H_i3 = i xi3 T_i (six transforms for nine outputs).
-    const T xi2 = (T)xi_of(o, g.n2);
-    const T xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2);
+    const T xi3 = (T)xi_of(col, g.n3, g.il3);
     T xi1[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) xi1[r] = (T)xi_of(t + TL * r, g.n1);
+    for (int r = 0; r < E; ++r) xi1[r] = (T)xi_of(t + TL * r, g.n1, g.il1);
     const long long co = sg.cstride_out;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -275,8 +275,8 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
     // r_i = -i sum_j xi_j s_ij after the forward x transform; three row
     // accumulators, the next stress component loaded while the current one
     // is transformed.
-    const T xi2 = (T)xi_of(o, g.n2);
-    const T xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2);
+    const T xi3 = (T)xi_of(col, g.n3, g.il3);
     cpx<T> a0[E], a1[E], a2[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) a0[r] = a1[r] = a2[r] = mk<T>(0, 0);
@@ -295,7 +295,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
       const int jj = (c < 3) ? c : (c == 5 ? 1 : 2);
 #pragma unroll
       for (int gq = 0; gq < E; ++gq) {
-        const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
+        const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1, g.il1);
         const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
         const T xi_ = (ii == 0) ? x1 : (ii == 1 ? xi2 : xi3);
         const cpx<T> t1 = scl(v[gq], xj);
@@ -324,8 +324,8 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
     // (xi2, xi3 are constant along the line, so they are applied before the
     // transform): six transforms for the nine components, one row live, the
     // next row's components loaded while the current row is transformed.
-    const T xi2 = (T)xi_of(o, g.n2);
-    const T xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2);
+    const T xi3 = (T)xi_of(col, g.n3, g.il3);
     const bool dcl = dc_out != nullptr && valid && o == 0 && col == 0;
     cpx<T> P1[E], P2[E], P3[E];
     loadv(in, P1);
@@ -372,7 +372,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, MODE>()>::NT)) voi
       fast_fft<T, N, E>(A, t, lds, PITCH, s, tw, d);
 #pragma unroll
       for (int gq = 0; gq < E; ++gq) {
-        const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
+        const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1, g.il1);
         A[gq] = muli(add(scl(A[gq], x1), C[gq]), (T)-1);
       }
       storev(out + i * sg.cstride_out, A);
@@ -465,8 +465,8 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = valid ? src[base + (long long)(t + TL * q) * ls] : mk<T>(0, 0);
   };
-  const T xi2 = (T)xi_of(o, g.n2);
-  const T xi3 = (T)xi_of(col, g.n3);
+  const T xi2 = (T)xi_of(o, g.n2, g.il2);
+  const T xi3 = (T)xi_of(col, g.n3, g.il3);
   // a_i = sum_j xi_j s_ij on the output distribution of the transform
   cpx<T> acc[3][E];
 #pragma unroll
@@ -490,7 +490,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
     const int ii = div_row_i(c), jj = div_row_j(c);
 #pragma unroll
     for (int gq = 0; gq < E; ++gq) {
-      const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1);
+      const T x1 = (T)xi_of(t + TL * fast_out_pos<N, E>(gq), g.n1, g.il1);
       const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
       const T xi_ = (ii == 0) ? x1 : (ii == 1 ? xi2 : xi3);
 #pragma unroll
@@ -545,7 +545,7 @@ __global__ __launch_bounds__((StridedShape<N, strided_E<T, N, SP_DIV_SMALL>()>::
       r[off + c * cs] = rn[c][gq];
       rv[c] = up(rn[c][gq]);
     }
-    precond(pa, xi_of(k1, g.n1), xi_of(o, g.n2), xi_of(col, g.n3), rv, zv);
+    precond(pa, xi_of(k1, g.n1, g.il1), xi_of(o, g.n2, g.il2), xi_of(col, g.n3, g.il3), rv, zv);
     double a = 0.0, bb = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

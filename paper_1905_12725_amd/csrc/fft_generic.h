@@ -43,7 +43,7 @@ __device__ __forceinline__ void strided_core(const cpx<T>* in, cpx<T>* out, cons
     }
   } else {
     // x pass with a fused pointwise operator: line index = k1, other = k2, column = k3
-    const T xi2 = (T)xi_of(o, g.n2);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2);
     if constexpr (MODE == SP_GRAD_SMALL || MODE == SP_GRAD_FINITE) {
       cpx<T> a0[kStridedQ], a1[kStridedQ], a2[kStridedQ];
 #pragma unroll
@@ -67,8 +67,8 @@ __device__ __forceinline__ void strided_core(const cpx<T>* in, cpx<T>* out, cons
           const int e = tid + q * NT;
           if (e < total) {
             const int ln = e / TZ, s = e - ln * TZ;
-            const T x1 = (T)xi_of(ln, g.n1);
-            const T x3 = (T)xi_of(col0 + s, g.n3);
+            const T x1 = (T)xi_of(ln, g.n1, g.il1);
+            const T x3 = (T)xi_of(col0 + s, g.n3, g.il3);
             const T xi[3] = {x1, xi2, x3};
             const cpx<T> a[3] = {a0[q], a1[q], a2[q]};
             cpx<T> v;
@@ -116,8 +116,8 @@ __device__ __forceinline__ void strided_core(const cpx<T>* in, cpx<T>* out, cons
           const int e = tid + q * NT;
           if (e < total) {
             const int ln = e / TZ, s = e - ln * TZ;
-            const T x1 = (T)xi_of(ln, g.n1);
-            const T x3 = (T)xi_of(col0 + s, g.n3);
+            const T x1 = (T)xi_of(ln, g.n1, g.il1);
+            const T x3 = (T)xi_of(col0 + s, g.n3, g.il3);
             const T xi[3] = {x1, xi2, x3};
             const cpx<T> v = res[e];
             int ii, jj;

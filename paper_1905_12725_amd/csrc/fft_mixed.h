@@ -77,7 +77,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     fft(v);
     storev(out, v);
   } else if constexpr (MODE == SP_GRAD_SMALL) {
-    const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2), xi3 = (T)xi_of(col, g.n3, g.il3);
     const long long co = sg.cstride_out;
     if constexpr (PARTS) {
       // components (i, i) and (i, j), j = i + 1 mod 3: stored 11 22 33 23 13 12
@@ -90,7 +90,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
       {
         cpx<T> v[EM];
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) v[n1] = muli(scl(Ai[n1], xa(i, (T)xi_of(N2 * n1 + t, g.n1))), (T)1);
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = muli(scl(Ai[n1], xa(i, (T)xi_of(N2 * n1 + t, g.n1, g.il1))), (T)1);
         fft(v);
         storev(out + i * co, v);
       }
@@ -98,7 +98,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
         cpx<T> v[EM];
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
-          const T x1 = (T)xi_of(N2 * n1 + t, g.n1);
+          const T x1 = (T)xi_of(N2 * n1 + t, g.n1, g.il1);
           v[n1] = muli(scl(add(scl(Ai[n1], xa(j, x1)), scl(Aj[n1], xa(i, x1))), (T)0.5), (T)1);
         }
         fft(v);
@@ -112,7 +112,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     auto emit = [&](int c, auto&& form) {
       cpx<T> v[EM];
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) v[n1] = form(n1, (T)xi_of(N2 * n1 + t, g.n1));
+      for (int n1 = 0; n1 < N1; ++n1) v[n1] = form(n1, (T)xi_of(N2 * n1 + t, g.n1, g.il1));
       fft(v);
       storev(out + c * co, v);
     };
@@ -126,14 +126,14 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     }
   } else if constexpr (MODE == SP_GRAD_FINITE) {
     // T_i = FFT(a_i), U_i = FFT(xi1 a_i): H_i1 = i U_i, H_i2 = i xi2 T_i, H_i3 = i xi3 T_i
-    const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2), xi3 = (T)xi_of(col, g.n3, g.il3);
     const long long co = sg.cstride_out;
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
       cpx<T> Ti[EM], U[EM];
       loadv(in + i * sg.cstride_in, Ti);
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) U[n1] = scl(Ti[n1], (T)xi_of(N2 * n1 + t, g.n1));
+      for (int n1 = 0; n1 < N1; ++n1) U[n1] = scl(Ti[n1], (T)xi_of(N2 * n1 + t, g.n1, g.il1));
       fft(Ti);
       fft(U);
       cpx<T> w[EM];
@@ -149,7 +149,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     }
   } else if constexpr (MODE == SP_DIV_SMALL) {
     // r_i = -i sum_j xi_j s_ij after the forward x transform
-    const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2), xi3 = (T)xi_of(col, g.n3, g.il3);
     if constexpr (PARTS) {
       // row i: s_i1, s_i2, s_i3 as stored components
       const int i = part;
@@ -173,7 +173,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
         if (dc_out != nullptr && first == i && lout && o == 0 && col == 0 && t == 0) dc_out[c] = (double)v[0].x;
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-          const T x1 = (T)xi_of(t + N1 * k2, g.n1);
+          const T x1 = (T)xi_of(t + N1 * k2, g.n1, g.il1);
           const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
           a[k2] = add(a[k2], scl(v[k2], xj));
         }
@@ -200,7 +200,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
       const int jj = (c < 3) ? c : (c == 5 ? 1 : 2);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
-        const T x1 = (T)xi_of(t + N1 * k2, g.n1);
+        const T x1 = (T)xi_of(t + N1 * k2, g.n1, g.il1);
         const T xj = (jj == 0) ? x1 : (jj == 1 ? xi2 : xi3);
         const T xi_ = (ii == 0) ? x1 : (ii == 1 ? xi2 : xi3);
         const cpx<T> t1 = scl(v[k2], xj);
@@ -227,7 +227,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
     }
   } else {
     // SP_DIV_FINITE, row by row: r_i = -i (xi1 F[P_i1] + F[xi2 P_i2 + xi3 P_i3])
-    const T xi2 = (T)xi_of(o, g.n2), xi3 = (T)xi_of(col, g.n3);
+    const T xi2 = (T)xi_of(o, g.n2, g.il2), xi3 = (T)xi_of(col, g.n3, g.il3);
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
       cpx<T> P1[N1], P2[N1], P3[N1];
@@ -271,7 +271,7 @@ __device__ __forceinline__ void mixed_strided_tile(const cpx<T>* in, cpx<T>* out
       fft(A);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
-        const T x1 = (T)xi_of(t + N1 * k2, g.n1);
+        const T x1 = (T)xi_of(t + N1 * k2, g.n1, g.il1);
         A[k2] = muli(add(scl(A[k2], x1), C[k2]), (T)-1);
       }
       storev(out + i * sg.cstride_out, A);

@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kVecThreads) void k_incompat(cpx<double>* __restric
   const long long k = (long long)blockIdx.x * kVecThreads + threadIdx.x;
   if (k >= g.nh) return;
   const FreqIdx f = decode(k, g);
-  const double x1 = xi_of(f.k1, g.n1), x2 = xi_of(f.k2, g.n2), x3 = xi_of(f.k3, g.n3);
+  const double x1 = xi_of(f.k1, g.n1, g.il1), x2 = xi_of(f.k2, g.n2, g.il2), x3 = xi_of(f.k3, g.n3, g.il3);
   const double A[3][3] = {{0.0, -x3, x2}, {x3, 0.0, -x1}, {-x2, x1, 0.0}};
   const long long nh = g.nh;
   if (finite) {

@@ -128,7 +128,7 @@ __device__ __forceinline__ void update_core(cpx<T>* __restrict__ x, cpx<T>* __re
       r[o] = down<T>(rc);
       rv[c] = up(down<T>(rc));
     }
-    precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
+    precond(pa, xi_of(f.k1, g.n1, g.il1), xi_of(f.k2, g.n2, g.il2), xi_of(f.k3, g.n3, g.il3), rv, zv);
     // a pair counts twice (weight 1 per entry), other points with the
     // half-spectrum weight
     const double w = (kp != k) ? 2.0 : half_weight(f.k3, g.n3);
@@ -163,7 +163,7 @@ __device__ __forceinline__ void pupdate_core(cpx<T>* __restrict__ p, const cpx<T
     cpx<double> rv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) rv[c] = up(r[c * nh + k]);
-    precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
+    precond(pa, xi_of(f.k1, g.n1, g.il1), xi_of(f.k2, g.n2, g.il2), xi_of(f.k3, g.n3, g.il3), rv, zv);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long o = c * nh + k;
@@ -202,7 +202,7 @@ __device__ __forceinline__ void pinit_core(cpx<T>* __restrict__ p, cpx<T>* __res
       }
       rv[c] = up(down<T>(rc));
     }
-    precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
+    precond(pa, xi_of(f.k1, g.n1, g.il1), xi_of(f.k2, g.n2, g.il2), xi_of(f.k3, g.n3, g.il3), rv, zv);
     const double w = (kp != k) ? 2.0 : half_weight(f.k3, g.n3);
     double a = 0.0, b = 0.0;
 #pragma unroll
@@ -428,7 +428,7 @@ __device__ __forceinline__ void xp_core(cpx<T>* __restrict__ x, cpx<T>* __restri
       cpx<double> rv[3], zv[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) rv[c] = up(r[c * nh + k]);
-      precond(pa, xi_of(f.k1, g.n1), xi_of(f.k2, g.n2), xi_of(f.k3, g.n3), rv, zv);
+      precond(pa, xi_of(f.k1, g.n1, g.il1), xi_of(f.k2, g.n2, g.il2), xi_of(f.k3, g.n3, g.il3), rv, zv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[c * nh + k] = down<T>(add(zv[c], scl(pv[c], beta)));
     }
