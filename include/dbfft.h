@@ -264,8 +264,8 @@ dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_ba
  *  out[3] loading, stress part: ||<sigma>_S - load_S|| / ||<sigma>|| over the
  *         stress-controlled components S (the denominator of opts.tol_load);
  *         0 when S is empty.
- * Derivatives are spectral with the frequencies of Sec. 2.1 (Nyquist
- * zeroed on even axes).  strain_dev, stress_dev: device doubles
+ * Derivatives are spectral with the frequencies of Sec. 2.1 for the
+ * context's cell lengths (Nyquist zeroed on even axes).  strain_dev, stress_dev: device doubles
  * [c][n1][n2][n3] in dbfft_homogenize's layout (small strains: 6 components
  * 11 22 33 23 13 12; finite strains: 9 components of H = F - I and of P,
  * row-major); NULL takes that field of the context's last solve.  load,

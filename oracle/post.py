@@ -15,9 +15,9 @@ only, imported by nothing in the product).
     one over the stress-prescribed components of a mixed load.
 
 Derivatives are spectral: multiplication of the normalized Fourier
-coefficients by i xi, with the frequencies of Sec. 2.1 (xi = 2 pi m on the
-unit cell; the Nyquist index of an even axis gets xi = 0).  Fields are full
-tensors of shape (3, 3) + grid.
+coefficients by i xi, with the frequencies of Sec. 2.1 (xi = 2 pi m / L for
+cell side lengths L, default 1; the Nyquist index of an even axis gets
+xi = 0).  Fields are full tensors of shape (3, 3) + grid.
 """
 from __future__ import annotations
 
@@ -34,21 +34,21 @@ def levi_civita():
     return e
 
 
-def spectral_derivative(f, shape, axes):
+def spectral_derivative(f, shape, axes, lengths=None):
     """d_{a1} d_{a2} ... f of a real field over its last three axes."""
     c = sp.fourier(f, shape)
-    xi = sp.xi_half(shape)
+    xi = sp.xi_half(shape, lengths)
     for a in axes:
         c = 1j * xi[a] * c
     return sp.real_field(c, shape)
 
 
-def divergence(s, shape):
+def divergence(s, shape, lengths=None):
     """(div s)_i = d_j s_ij of a tensor field (3, 3) + grid."""
-    return np.stack([sum(spectral_derivative(s[i, j], shape, (j,)) for j in range(3)) for i in range(3)])
+    return np.stack([sum(spectral_derivative(s[i, j], shape, (j,), lengths) for j in range(3)) for i in range(3)])
 
 
-def incompatibility(eps, shape):
+def incompatibility(eps, shape, lengths=None):
     """curl curl eps (symmetric) of a small-strain field."""
     e = levi_civita()
     second = {}
@@ -56,7 +56,7 @@ def incompatibility(eps, shape):
         for m in range(k, 3):
             for l in range(3):
                 for n in range(3):
-                    second[(k, m, l, n)] = spectral_derivative(eps[l, n], shape, (k, m))
+                    second[(k, m, l, n)] = spectral_derivative(eps[l, n], shape, (k, m), lengths)
     out = np.zeros((3, 3) + tuple(shape))
     for i in range(3):
         for j in range(3):
@@ -70,7 +70,7 @@ def incompatibility(eps, shape):
     return out
 
 
-def row_curl(F, shape):
+def row_curl(F, shape, lengths=None):
     """(curl_0 F)_ij = e_jkl d_k F_il, the curl of every row of F."""
     e = levi_civita()
     out = np.zeros((3, 3) + tuple(shape))
@@ -79,7 +79,7 @@ def row_curl(F, shape):
             for k in range(3):
                 for l in range(3):
                     if e[j, k, l] != 0.0:
-                        out[i, j] += e[j, k, l] * spectral_derivative(F[i, l], shape, (k,))
+                        out[i, j] += e[j, k, l] * spectral_derivative(F[i, l], shape, (k,), lengths)
     return out
 
 
@@ -93,17 +93,17 @@ def _ratio(num, den):
     return num / den
 
 
-def equilibrium_residual(sig, shape):
+def equilibrium_residual(sig, shape, lengths=None):
     """Eq. chedckeq (P and the reference divergence at finite strains)."""
-    d = divergence(sig, shape)
+    d = divergence(sig, shape, lengths)
     l2 = np.sqrt(np.mean(np.sum(d * d, axis=0)))
     return _ratio(float(l2), float(np.linalg.norm(_mean(sig))))
 
 
-def compatibility_residual(field, shape, finite=False):
+def compatibility_residual(field, shape, finite=False, lengths=None):
     """Eq. chedckcomp; `field` is eps, or at finite strains the displacement
     gradient H = F - I (curl_0 F = curl_0 H, <F> - I = <H>)."""
-    inc = row_curl(field, shape) if finite else incompatibility(field, shape)
+    inc = row_curl(field, shape, lengths) if finite else incompatibility(field, shape, lengths)
     return _ratio(float(np.max(np.abs(inc))), float(np.linalg.norm(_mean(field))))
 
 
