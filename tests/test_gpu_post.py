@@ -276,7 +276,7 @@ def test_residuals_with_cell_lengths(gpu, kin):
         got = cell.residuals(torch.from_numpy(eps), torch.from_numpy(sig), load, mask)
     ref = _oracle_residuals(eps, sig, n, load, mask, finite, Lc)
     unit = _oracle_residuals(eps, sig, n, load, mask, finite)
-    assert np.max(np.abs(got - ref) / ref) < 1e-10, (got, ref)
+    assert np.allclose(got, ref, rtol=1e-10, atol=0.0), (got, ref)
     assert abs(got[0] - unit[0]) > 1e-3 * unit[0]
 
 
