@@ -45,7 +45,7 @@ __device__ __forceinline__ cpx<T> muli(cpx<T> a, T d) { return mk<T>(-d * a.y, d
 __device__ __forceinline__ double xi_of(int k, int n, double inv_len) {
   int m = (2 * k < n) ? k : k - n;
   if (2 * k == n) m = 0;
-  return kTwoPi * (double)m * inv_len;
+  return (double)m * (kTwoPi * inv_len);  // 2 pi / L is the same for every call of a pass
 }
 
 // radix-R DFT in registers, exponent sign d (-1 forward, +1 inverse)
