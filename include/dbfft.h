@@ -183,7 +183,8 @@ dbfft_status dbfft_apply_fourier(dbfft_ctx* ctx, const void* a_dev, const double
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the operator of
- * dbfft_apply (FP64, small strains, elastic tangent) without a context.
+ * dbfft_apply (FP64, small strains, elastic tangent, unit cell lengths)
+ * without a context.
  * It calls no hipMalloc, hipFree or other allocating routine; its workspace
  * (twiddle tables, 12 half-spectrum components, partial sums, a checked copy
  * of the phase map) lives in a static device array of 64 MiB that every
