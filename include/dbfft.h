@@ -241,6 +241,24 @@ dbfft_status dbfft_solve(dbfft_ctx* ctx, const double load[9], const uint8_t str
 dbfft_status dbfft_solve_block(dbfft_ctx* ctx, int32_t nrhs, const double* loads, const uint8_t stress_mask[9],
                                const dbfft_opts* opts, dbfft_info* infos, int32_t* applies);
 
+/* Several loads of one linear cell solved as independent PCG solves
+ * (Sec. 2.2-2.5, each load exactly as dbfft_solve solves it: the same
+ * kernels in the same order, so the same results) running concurrently on
+ * nstreams helper contexts, each with a HIP stream and a host thread of its
+ * own, so that the kernels of one solve fill the launch gaps and partly
+ * idle rounds of another.  loads: nrhs x 9 host doubles (row-major 3x3
+ * each, strain or stress per stress_mask as for dbfft_solve, one mask for
+ * all loads); infos: nrhs entries; nstreams 1 .. 8 (at most nrhs are used);
+ * load j runs on helper j mod nstreams.  The helpers (a copy of the
+ * material and of the workspaces per stream, on the context's device and
+ * with its cell lengths) are created on the first call that needs them and
+ * kept until dbfft_destroy.  The context's own solution is not changed and
+ * its stream is synchronized first.  Linear materials (EUNSUPPORTED
+ * otherwise).  Returns the status of the first load that failed (its info
+ * is filled), after every load has run. */
+dbfft_status dbfft_solve_many(dbfft_ctx* ctx, int32_t nrhs, const double* loads, const uint8_t stress_mask[9],
+                              const dbfft_opts* opts, dbfft_info* infos, int32_t nstreams);
+
 /* Homogenized response of the last solve (Sec. 3 post-processing):
  * <sigma> and <eps> (row-major, host, either may be NULL) and, when the
  * pointers are not NULL, the real fields of strain (6 or 9 comps), stress

@@ -29,6 +29,7 @@ EXPORTED = (
     "dbfft_homogenize", "dbfft_get_solution", "dbfft_adjoint", "dbfft_destroy", "dbfft_last_error",
     "dbfft_kernel_timing", "dbfft_batch_create", "dbfft_batch_solve", "dbfft_batch_tiles",
     "dbfft_batch_destroy", "dbfft_apply_noalloc", "dbfft_solve_block", "dbfft_residuals", "dbfft_set_lengths",
+    "dbfft_solve_many",
 )
 KERNEL_KINDS = ("x_inverse_grad", "y_inverse", "z_fused_tangent", "y_forward", "x_forward_div",
                 "cg_alpha", "cg_update", "cg_beta", "cg_direction")
@@ -100,6 +101,8 @@ def load_library(path=LIB_PATH):
     lib.dbfft_solve_block.restype = ct.c_int
     lib.dbfft_homogenize.argtypes = [P, DP, DP, P, P, P]
     lib.dbfft_homogenize.restype = ct.c_int
+    lib.dbfft_solve_many.argtypes = [P, I32, DP, ct.POINTER(ct.c_uint8), ct.POINTER(Opts), ct.POINTER(Info), I32]
+    lib.dbfft_solve_many.restype = ct.c_int
     lib.dbfft_set_lengths.argtypes = [P, DP]
     lib.dbfft_set_lengths.restype = ct.c_int
     lib.dbfft_residuals.argtypes = [P, P, P, DP, ct.POINTER(ct.c_uint8), DP]

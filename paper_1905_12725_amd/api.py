@@ -155,6 +155,25 @@ class Cell:
         nat.check(nat.lib().dbfft_apply_fourier(self._h, _ptr(a), em, _ptr(f), sig))
         return f, np.array(sig[:]).reshape(3, 3)
 
+    def solve_many(self, loads, stress_mask=None, nstreams=2, raise_on_fail=True, **opts):
+        """dbfft_solve_many: the loads (a list of 3x3) solved as independent
+        PCG solves on `nstreams` concurrent streams.  Returns the list of
+        info dicts (one per load)."""
+        L = np.ascontiguousarray(np.asarray(loads, dtype=np.float64).reshape(-1, 9))
+        s = L.shape[0]
+        mask = np.zeros(9, dtype=np.uint8) if stress_mask is None else \
+            np.asarray(stress_mask, dtype=bool).reshape(9).astype(np.uint8)
+        o = nat.default_opts(**opts)
+        infos = (nat.Info * s)()
+        st = nat.lib().dbfft_solve_many(self._h, s, L.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                        (ct.c_uint8 * 9)(*mask.tolist()), ct.byref(o), infos, int(nstreams))
+        if st != nat.DBFFT_OK and raise_on_fail:
+            nat.check(st)
+        out = [_info_dict(infos[j]) for j in range(s)]
+        for d, inf in zip(out, infos):
+            d["status"] = inf.status
+        return out
+
     def solve_block(self, loads, stress_mask=None, raise_on_fail=True, **opts):
         """dbfft_solve_block: the loads (a list of 3x3) solved together by
         block PCG.  Returns (list of info dicts, operator applications)."""

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dbfft.h"
@@ -24,6 +25,7 @@
 namespace dbfft {
 
 static thread_local std::string g_err;
+constexpr int kMaxSolveStreams = 8;  // helper contexts of dbfft_solve_many
 static const bool g_verbose = [] {
   const char* v = std::getenv("DBFFT_VERBOSE");
   return v != nullptr && v[0] != '0';
@@ -216,6 +218,13 @@ struct Ctx {
   double* blk_mac = nullptr;
   double* blk_dc = nullptr;
   double* blk_part = nullptr;
+
+  // dbfft_solve_many: the setup arguments a helper context is made from,
+  // the device, and the helpers (one per stream, created on first use)
+  std::vector<double> setup_params;
+  int dev = 0;
+  std::vector<dbfft_ctx*> helpers;
+  std::vector<hipStream_t> helper_streams;
 
   // solution state
   bool solved = false;
@@ -1724,6 +1733,10 @@ static bool smooth(long long n) {
 }
 
 static void release(Ctx* c) {
+  for (dbfft_ctx* h : c->helpers) dbfft_destroy(h);
+  for (hipStream_t s : c->helper_streams) (void)hipStreamDestroy(s);
+  c->helpers.clear();
+  c->helper_streams.clear();
   (void)hipStreamSynchronize(c->st);
   void* dev[] = {c->td.tw1, c->td.tw2, c->td.tw3, c->td.rtw, c->tf.tw1, c->tf.tw2, c->tf.tw3, c->tf.rtw,
                  c->phase, c->E64, c->E32, c->grain, c->grain21, c->grainC, c->grainS, c->W, c->x, c->r, c->p,
@@ -1808,6 +1821,8 @@ static void setup(Ctx* c, const int64_t n[3], int kin, int prec, int mat, const 
     DB_THROW(DBFFT_EINVAL, "NEOHOOKE and SVK need FINITE kinematics and every other material SMALL");
   if (!field) DB_THROW(DBFFT_EINVAL, "null material field");
   if (!params || nparams < 1) DB_THROW(DBFFT_EINVAL, "null material parameters");
+  c->setup_params.assign(params, params + nparams);
+  HIPCK(hipGetDevice(&c->dev));
 
   {
     init_grid(c, n, kin, prec, mat, stream);
@@ -2969,6 +2984,74 @@ dbfft_status dbfft_homogenize(dbfft_ctx* ctx, double sigma_bar[9], double eps_ba
   }
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(c.st));
+  return DBFFT_OK;
+  API_END
+}
+
+dbfft_status dbfft_solve_many(dbfft_ctx* ctx, int32_t nrhs, const double* loads, const uint8_t stress_mask[9],
+                              const dbfft_opts* opts, dbfft_info* infos, int32_t nstreams) {
+  g_err.clear();
+  API_BEGIN
+  if (!ctx || !loads || !stress_mask || !infos) DB_THROW(DBFFT_EINVAL, "null argument");
+  if (nrhs < 1) DB_THROW(DBFFT_EINVAL, "nrhs must be at least 1");
+  if (nstreams < 1 || nstreams > kMaxSolveStreams) DB_THROW(DBFFT_EINVAL, "nstreams must be 1 .. 8");
+  Ctx& c = *C(ctx);
+  if (!c.linear_material()) DB_THROW(DBFFT_EUNSUPPORTED, "dbfft_solve_many takes linear materials");
+  if (opts && opts->coarse_kc != 0) DB_THROW(DBFFT_EUNSUPPORTED, "opts.coarse_kc applies to dbfft_solve_block");
+  HIPCK(hipStreamSynchronize(c.st));
+  const int ns = std::min<int>(nstreams, nrhs);
+  // helper contexts: the same grid, precision and material (the field is
+  // copied from this context's device copy), each on a stream of its own
+  while ((int)c.helpers.size() < ns) {
+    const void* field = (c.mat == DBFFT_MAT_ISO_PHASE) ? static_cast<const void*>(c.phase)
+                        : (c.mat == DBFFT_MAT_ISO_FIELD) ? static_cast<const void*>(c.E64)
+                                                         : static_cast<const void*>(c.grain);
+    const int64_t n64[3] = {c.n[0], c.n[1], c.n[2]};
+    hipStream_t s = nullptr;
+    HIPCK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    dbfft_ctx* h = nullptr;
+    const dbfft_status st = dbfft_setup(&h, n64, c.kin, c.prec, c.mat, field, c.setup_params.data(),
+                                        (int32_t)c.setup_params.size(), s);
+    if (st != DBFFT_OK) {
+      const std::string m = dbfft_last_error();
+      (void)hipStreamDestroy(s);
+      DB_THROW(st, "helper context: " + m);
+    }
+    c.helpers.push_back(h);
+    c.helper_streams.push_back(s);
+  }
+  const double len[3] = {1.0 / c.g.il1, 1.0 / c.g.il2, 1.0 / c.g.il3};
+  for (int t = 0; t < ns; ++t) {
+    const Geom& hg = C(c.helpers[t])->g;
+    if (hg.il1 != c.g.il1 || hg.il2 != c.g.il2 || hg.il3 != c.g.il3) {
+      const dbfft_status st = dbfft_set_lengths(c.helpers[t], len);
+      if (st != DBFFT_OK) DB_THROW(st, std::string("helper context: ") + dbfft_last_error());
+    }
+  }
+  // load j runs on helper j mod ns, each helper's loads in order on its own
+  // host thread (contexts may be driven from different threads at once)
+  std::vector<int> status(nrhs, DBFFT_OK);
+  std::vector<std::string> msg(nrhs);
+  std::vector<std::thread> th;
+  th.reserve(ns);
+  for (int t = 0; t < ns; ++t) {
+    th.emplace_back([&, t]() {
+      if (hipSetDevice(c.dev) != hipSuccess) {
+        for (int j = t; j < nrhs; j += ns) {
+          status[j] = DBFFT_EHIP;
+          msg[j] = "hipSetDevice failed in a solve thread";
+        }
+        return;
+      }
+      for (int j = t; j < nrhs; j += ns) {
+        status[j] = dbfft_solve(c.helpers[t], loads + 9 * (size_t)j, stress_mask, 1, 1.0, opts, &infos[j]);
+        if (status[j] != DBFFT_OK) msg[j] = dbfft_last_error();
+      }
+    });
+  }
+  for (std::thread& x : th) x.join();
+  for (int j = 0; j < nrhs; ++j)
+    if (status[j] != DBFFT_OK) DB_THROW(status[j], "load " + std::to_string(j) + ": " + msg[j]);
   return DBFFT_OK;
   API_END
 }

@@ -120,6 +120,7 @@ def test_null_handles_are_rejected():
     assert lib.dbfft_batch_create(None, None, 0, 1) == 1
     assert lib.dbfft_batch_solve(None, load, mask, 1, 1.0, None, ctypes.byref(info)) == 1
     assert lib.dbfft_set_lengths(None, (ctypes.c_double * 3)(1.0, 1.0, 1.0)) == 1
+    assert lib.dbfft_solve_many(None, 1, load, mask, None, ctypes.byref(info), 2) == 1
     assert lib.dbfft_residuals(None, None, None, None, None, (ctypes.c_double * 4)()) == 1
     lib.dbfft_destroy(None)
 
