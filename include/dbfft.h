@@ -387,11 +387,15 @@ dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int3
  * dt are shared by all cells.  Afterwards dbfft_homogenize and
  * dbfft_get_solution read each context's result as after dbfft_solve.
  * Each pass runs as one launch over all cells, except when every cell is a
- * small-strain cell of at least 96^3 voxels: such cells are solved one
- * after another by dbfft_solve, whose passes already fill the GPU (and,
- * for power-of-two n1 with even n2 and opts.fused_cg, take the fused
- * iteration).  Returns OK when every cell converged, else the status of
- * the last cell that did not (each info.status holds its own). */
+ * small-strain cell of at least 96^3 voxels: such cells are solved by
+ * dbfft_solve, whose passes already fill the GPU (and, for power-of-two n1
+ * with even n2 and opts.fused_cg, take the fused iteration), two cells at a
+ * time, each pair on two non-blocking streams of the batch driven by two
+ * host threads (a context listed twice: one at a time); each cell's own
+ * stream is synchronized before its solve.  Returns OK when every cell
+ * converged, else the status of the last cell that did not (each
+ * info.status holds its own); another error of a cell is returned with
+ * that cell's message. */
 dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_t* stress_masks,
                                int32_t n_increments, double dt, const dbfft_opts* opts, dbfft_info* infos);
 

@@ -169,10 +169,7 @@ class Cell:
                                         (ct.c_uint8 * 9)(*mask.tolist()), ct.byref(o), infos, int(nstreams))
         if st != nat.DBFFT_OK and raise_on_fail:
             nat.check(st)
-        out = [_info_dict(infos[j]) for j in range(s)]
-        for d, inf in zip(out, infos):
-            d["status"] = inf.status
-        return out
+        return [_info_dict(infos[j]) for j in range(s)]
 
     def solve_block(self, loads, stress_mask=None, raise_on_fail=True, **opts):
         """dbfft_solve_block: the loads (a list of 3x3) solved together by

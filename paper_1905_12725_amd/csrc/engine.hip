@@ -2024,6 +2024,7 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int> tzx, tzy, L, mx, my, mz;
+  std::vector<hipStream_t> lane_st;  // streams of the cell-by-cell lanes (created on first use)
 };
 
 template <typename T>
@@ -2514,6 +2515,7 @@ static void batch_release(Batch* B) {
   if (B->flags_dev) (void)hipFree(B->flags_dev);
   if (B->flags_host) (void)hipHostFree(B->flags_host);
   if (B->st) (void)hipStreamDestroy(B->st);
+  for (hipStream_t s : B->lane_st) (void)hipStreamDestroy(s);
 }
 
 // ------------------------------------------------------------------ allocation-free apply
@@ -3218,17 +3220,67 @@ dbfft_status dbfft_batch_create(dbfft_batch** out, dbfft_ctx* const* cells, int3
   API_END
 }
 
-// A batch whose every cell takes the fused single-cell iteration with at
-// least 128^3 voxels solves the cells one after another with it: each pass
-// then already has a thousand or more blocks, and the batched passes (LDS
-// Stockham transforms, separate CG vector kernels) are slower there.
-// small-strain cells of 96^3 voxels and more: one after another with the
-// single-cell passes (measured faster than the batched ones from 96^3 up)
-static bool solve_cellwise(const Batch& B, const dbfft_opts& o) {
-  (void)o;
+// Small-strain cells of 96^3 voxels and more are solved cell by cell with
+// the single-cell passes, whose launches already have a thousand or more
+// blocks there (measured faster than the batched passes from 96^3 up).
+static bool solve_cellwise(const Batch& B) {
   for (const Ctx* c : B.cells)
     if (!(c->kin == KIN_SMALL && c->g.nvox >= 96LL * 96 * 96)) return false;
   return true;
+}
+
+constexpr int kCellLanes = 2;  // cells solved at once by the cell-by-cell path
+
+// dbfft_solve on every cell, kCellLanes cells at a time: each lane is a
+// host thread (the calling one for the first lane) and a non-blocking
+// stream of the batch, on which the cell's context enqueues for the call
+// (its own stream is synchronized first and given back afterwards).  Two solves at once fill each other's launch
+// gaps.  A context listed twice keeps every solve in one lane.  Returns the
+// worst status as dbfft_batch_solve does.
+static dbfft_status batch_solve_cellwise(Batch& B, const double* loads, const uint8_t* masks, int ninc, double dt,
+                                         const dbfft_opts& o, dbfft_info* infos) {
+  const int n = (int)B.cells.size();
+  bool dup = false;
+  for (int a = 0; a < n && !dup; ++a)
+    for (int b = a + 1; b < n; ++b)
+      if (B.cells[a] == B.cells[b]) dup = true;
+  const int nl = dup ? 1 : std::min(kCellLanes, n);
+  while ((int)B.lane_st.size() < nl) {
+    hipStream_t s = nullptr;
+    HIPCK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    B.lane_st.push_back(s);
+  }
+  std::vector<int> status(n, DBFFT_OK);
+  std::vector<std::string> msg(n);
+  auto lane = [&](int t) {
+    for (int r = t; r < n; r += nl) {
+      Ctx& c = *B.cells[r];
+      if ((t > 0 && hipSetDevice(c.dev) != hipSuccess) || hipStreamSynchronize(c.st) != hipSuccess) {
+        status[r] = DBFFT_EHIP;
+        msg[r] = "cannot select the cell's device or synchronize its stream";
+        continue;
+      }
+      const hipStream_t own = c.st;
+      c.st = B.lane_st[t];
+      status[r] = dbfft_solve(B.handles[r], loads + 9 * (size_t)r, masks + 9 * (size_t)r, ninc, dt, &o, &infos[r]);
+      if (status[r] != DBFFT_OK) msg[r] = dbfft_last_error();
+      (void)hipStreamSynchronize(c.st);
+      c.st = own;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nl; ++t) th.emplace_back(lane, t);
+  lane(0);
+  for (std::thread& x : th) x.join();
+  int worst = DBFFT_OK;
+  for (int r = 0; r < n; ++r) {
+    if (status[r] == DBFFT_OK) continue;
+    if (status[r] != DBFFT_ENOTCONV && status[r] != DBFFT_EBREAKDOWN)
+      DB_THROW(status[r], "cell " + std::to_string(r) + ": " + msg[r]);
+    worst = status[r];
+    g_err = "cell " + std::to_string(r) + ": " + msg[r];
+  }
+  return (dbfft_status)worst;
 }
 
 dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_t* stress_masks, int32_t n_increments,
@@ -3257,19 +3309,7 @@ dbfft_status dbfft_batch_solve(dbfft_batch* b, const double* loads, const uint8_
     if (n_increments < 1) DB_THROW(DBFFT_EINVAL, "n_increments must be >= 1");
     if (B.cells[0]->mat == DBFFT_MAT_J2VP_CUBIC && !(dt > 0.0)) DB_THROW(DBFFT_EINVAL, "dt must be > 0");
   }
-  if (solve_cellwise(B, o)) {
-    // cells that each fill the GPU with the fused single-cell iteration
-    int worst = DBFFT_OK;
-    for (int r = 0; r < n; ++r) {
-      const dbfft_status s = dbfft_solve(B.handles[r], loads + 9 * r, stress_masks + 9 * r, n_increments, dt, &o,
-                                         &infos[r]);
-      if (s != DBFFT_OK) {
-        if (s != DBFFT_ENOTCONV && s != DBFFT_EBREAKDOWN) return s;
-        worst = s;
-      }
-    }
-    return (dbfft_status)worst;
-  }
+  if (solve_cellwise(B)) return batch_solve_cellwise(B, loads, stress_masks, n_increments, dt, o, infos);
   std::vector<int> st = (B.prec == DBFFT_FP64) ? batch_solve_t<double>(B, loads, stress_masks, n_increments, dt, o, infos)
                                                : batch_solve_t<float>(B, loads, stress_masks, n_increments, dt, o, infos);
   int worst = DBFFT_OK;

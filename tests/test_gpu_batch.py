@@ -291,8 +291,8 @@ def test_batch_neohooke_smooth_sizes_fp32_vs_fp64_single(gpu):
 def test_batch_of_large_cells_solves_cell_by_cell(gpu, n):
     """Two small-strain cells of at least 96^3 voxels (128^3: the fused
     single-cell iteration; 96^3: the two-step single-cell passes): the batch
-    solves them one after another, so each result equals the cell's own
-    solve bit for bit."""
+    solves them with the single-cell passes (on two streams at once), so
+    each result equals the cell's own solve bit for bit."""
     import torch
     from paper_1905_12725_amd.api import Batch, Cell
     print(f"case batch of two {n} cells", flush=True)
@@ -307,4 +307,38 @@ def test_batch_of_large_cells_solves_cell_by_cell(gpu, n):
         one = c.solve(L, tol=1e-8)
         assert info["pcg_iters"] == one["pcg_iters"]
         assert np.array_equal(a, c.solution()[0].cpu().numpy())
+        c.close()
+
+
+def test_cell_by_cell_lanes_statuses_and_repeated_context(gpu):
+    """The cell-by-cell path runs two cells at a time on streams of the
+    batch: five 96^3 cells (three microstructures, one context listed twice,
+    so all its solves stay in one lane) give the one-by-one results bit for
+    bit, in the listed order for the repeated context; an iteration cap
+    comes back per cell."""
+    import torch
+    from paper_1905_12725_amd.api import Batch, Cell
+    print("case batch cell-by-cell lanes", flush=True)
+    n = (96, 96, 96)
+    params = [1.0, 0.3, 30.0, 0.3]
+    phases = [ms.random_spheres(n, s, 4.5, 7.5, 0.3)[0] for s in (2, 3, 4)]
+    cells = [Cell(n, "iso_phase", torch.from_numpy(p), params) for p in phases]
+    order = [0, 1, 2, 0, 1]
+    loads = [np.diag([1e-3 * (k + 1), 0.0, 0.0]) for k in range(len(order))]
+    with Batch([cells[i] for i in order]) as b:
+        infos = b.solve(loads, None, tol=1e-9)
+        last = {i: cells[i].solution()[0].cpu().numpy() for i in range(3)}
+        capped = b.solve(loads, None, raise_on_fail=False, max_iter=3, tol=1e-12, tol_load=1e-12)
+    for k, (i, L) in enumerate(zip(order, loads)):
+        one = cells[i].solve(L, tol=1e-9)
+        assert infos[k]["status"] == 0 and infos[k]["pcg_iters"] == one["pcg_iters"], k
+        assert np.array_equal(infos[k]["sigma_bar"], one["sigma_bar"]), k
+    # each context's last solve in the batch is the last entry that lists it
+    for i in range(3):
+        k = max(j for j, o in enumerate(order) if o == i)
+        cells[i].solve(loads[k], tol=1e-9)
+        assert np.array_equal(last[i], cells[i].solution()[0].cpu().numpy()), i
+    assert [c["status"] for c in capped] == [4] * len(order)
+    assert all(c["pcg_iters"] == 3 for c in capped)
+    for c in cells:
         c.close()
