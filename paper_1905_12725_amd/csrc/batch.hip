@@ -133,7 +133,9 @@ __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>*
   else (void)plan;
 }
 
-// two-step z pass of a cell: four waves per block, one energy partial per block
+// two-step z pass of a cell: four waves per block (each a line group of its
+// own, or at finite strains one line group for the block), one energy
+// partial per block
 template <typename T, int M, int KIN, int LAW>
 __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, unsigned char* smem_raw) {
   using L = MixedLine<M>;
@@ -152,7 +154,12 @@ __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, u
     else if constexpr (sizeof(T) == 4)
       e = mixed_line_fused<T, M, KIN_SMALL, 0>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
   } else if constexpr (sizeof(T) == 4) {
-    e = mixed_line_fused<T, M, KIN_FINITE, LAW>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
+    // finite strains: the block's four waves share one line group
+    cpx<T>* X = rtw + M + 1 + (kLineThreads / 64) * L::LB * L::PITCH;
+    e = mixed_line_staged<T, M, LAW, kLineThreads / 64>(R.W, R.W, R.g, tw, rtw, lds, X, R.tan, R.sc->pmac, lb, w,
+                                                         lane);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
   }
   if (lane == 0) ew[w] = e;
   __syncthreads();

@@ -497,4 +497,98 @@ __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out
   return energy * g.inv_nvox;
 }
 
+// z pass of one line group (LB lines) by the NW waves of a block, for
+// tangents that couple every component (finite strains): wave w transforms
+// the components w, w + NW, ... one at a time and stages their real values
+// in LDS (X: [c][line][n], packed pairs n = 0..M-1), the block applies the
+// tangent voxel by voxel from there, and every wave transforms its
+// components back.  Only one component is in registers at a time, so the
+// pass does not hold all nine (the register-resident version needs 256
+// VGPRs and spills).  `lds` is the wave's own exchange buffer.  Returns
+// this thread's share of the energy (1/N of sum eps : sigma); the caller
+// sums over the block.  Every thread of the block must call it: the
+// transforms and the staging use block barriers.
+template <typename T, int M, int LAW, int NW>
+__device__ __forceinline__ double mixed_line_staged(const cpx<T>* in, cpx<T>* out, const Geom& g,
+                                                    const cpx<T>* tw, const cpx<T>* rtw, cpx<T>* lds,
+                                                    cpx<T>* __restrict__ X, const TangentArgs<T>& tn,
+                                                    const double* __restrict__ macro_dev, long long group,
+                                                    int wave, int lane) {
+  using L = MixedLine<M>;
+  constexpr int N1 = L::N1, N2 = L::N2, EM = L::EM, TL = L::TL, LB = L::LB, PITCH = L::PITCH;
+  constexpr int NC = 9;
+  const int line = lane / TL, t = lane % TL;
+  const long long nlines = (long long)g.n1 * g.n2;
+  const long long gl = group * LB + line;
+  const bool active = line < LB;
+  const bool valid = active && gl < nlines;
+  const int tj = active ? t : TL;  // lanes past the last line take no part
+  const int partner = active ? line * TL + ((t < N2) ? (N2 - t) % N2 : t) : lane;
+  const int off = (active ? line : 0) * PITCH;
+  const int nh3 = g.nh3, n3 = g.n3;
+  const cpx<T>* inl = in + (valid ? gl : 0) * nh3;
+  cpx<T>* outl = out + (valid ? gl : 0) * nh3;
+  const bool lt = valid && t < N1;
+  // The transforms exchange through LDS behind block barriers, so every
+  // wave runs the same number of rounds; a wave with no component left in
+  // the last round transforms zeros and stores nothing.
+  constexpr int NR = (NC + NW - 1) / NW;
+#pragma unroll 1
+  for (int j = 0; j < NR; ++j) {
+    const int c = wave + NW * j;
+    const bool has = c < NC;
+    cpx<T> e[EM];
+    mixed_line_inverse<T, M>(inl + (has ? c : 0) * g.nh, valid && has, t, tj, partner, lds, off, tw, rtw, e);
+    if (lt && has) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) X[(c * LB + line) * M + t + N1 * k2] = e[k2];
+    }
+  }
+  __syncthreads();
+  double mac[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) mac[c] = macro_dev ? macro_dev[c] : 0.0;
+  double energy = 0.0;
+  for (int idx = (int)threadIdx.x; idx < LB * M; idx += NW * 64) {
+    const int ln = idx / M, n = idx - ln * M;
+    const long long gln = group * LB + ln;
+    if (gln >= nlines) continue;
+    cpx<T> v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = X[(c * LB + ln) * M + n];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const long long vox = gln * n3 + 2 * n + h;
+      T ev[NC], sv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ev[c] = (h == 0 ? v[c].x : v[c].y) + (T)mac[c];
+      tangent_finite<T, LAW>(tn, vox, g.nvox, ev, sv);
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc += (double)(ev[c] * sv[c]);
+      energy += acc;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (h == 0) v[c].x = sv[c];
+        else v[c].y = sv[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) X[(c * LB + ln) * M + n] = v[c];
+  }
+  __syncthreads();
+  const T scale = (T)g.inv_nvox;
+#pragma unroll 1
+  for (int j = 0; j < NR; ++j) {
+    const int c = wave + NW * j;
+    const bool has = c < NC;
+    cpx<T> e[EM];
+#pragma unroll
+    for (int k2 = 0; k2 < EM; ++k2)
+      e[k2] = (lt && has && k2 < N2) ? X[(c * LB + line) * M + t + N1 * k2] : mk<T>(0, 0);
+    mixed_line_forward<T, M>(outl + (has ? c : 0) * g.nh, valid && has, t, tj, partner, lds, off, tw, rtw, e, scale);
+  }
+  return energy * g.inv_nvox;
+}
+
 }  // namespace dbfft
