@@ -134,8 +134,8 @@ __global__ __launch_bounds__(kStridedThreads) void kb_strided(const CellDesc<T>*
 }
 
 // two-step z pass of a cell: four waves per block (each a line group of its
-// own, or at finite strains one line group for the block), one energy
-// partial per block
+// own for isotropic tangents, else one line group for the block), one
+// energy partial per block
 template <typename T, int M, int KIN, int LAW>
 __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, unsigned char* smem_raw) {
   using L = MixedLine<M>;
@@ -149,15 +149,14 @@ __device__ __forceinline__ void batch_mixed_line(const CellDesc<T>& R, int lb, u
   __syncthreads();
   const long long blk = (long long)lb * (kLineThreads / 64) + w;
   double e = 0.0;
-  if constexpr (KIN == KIN_SMALL) {
-    if (R.mz == 1) e = mixed_line_fused<T, M, KIN_SMALL, 1>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
-    else if constexpr (sizeof(T) == 4)
-      e = mixed_line_fused<T, M, KIN_SMALL, 0>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
+  if (KIN == KIN_SMALL && R.mz == 1) {
+    e = mixed_line_fused<T, M, KIN_SMALL, 1>(R.W, R.W, R.g, tw, rtw, lds, R.tan, R.sc->pmac, blk, lane);
   } else if constexpr (sizeof(T) == 4) {
-    // finite strains: the block's four waves share one line group
+    // anisotropic or finite-strain tangents: the block's four waves share
+    // one line group
     cpx<T>* X = rtw + M + 1 + (kLineThreads / 64) * L::LB * L::PITCH;
-    e = mixed_line_staged<T, M, LAW, kLineThreads / 64>(R.W, R.W, R.g, tw, rtw, lds, X, R.tan, R.sc->pmac, lb, w,
-                                                         lane);
+    e = mixed_line_staged<T, M, KIN, LAW, kLineThreads / 64>(R.W, R.W, R.g, tw, rtw, lds, X, R.tan, R.sc->pmac, lb,
+                                                              w, lane);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
   }

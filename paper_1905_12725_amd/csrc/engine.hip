@@ -2152,14 +2152,14 @@ static void batch_build(Batch& B) {
     const size_t M = c.g.n3 / 2;
     if (B.mz[r]) {
       const int tl = two_step_threads((int)M), lb = 64 / tl;
-      // finite strains: one line group per block, its nine components
-      // staged in LDS (mixed_line_staged)
-      const bool staged = c.kin == KIN_FINITE;
+      // anisotropic or finite-strain tangents (FP32): one line group per
+      // block, its components staged in LDS (mixed_line_staged)
+      const bool staged = B.mz[r] == 2;
       const long long per_block = staged ? lb : (long long)(kLineThreads / 64) * lb;
       bz[r + 1] = bz[r] + (int)((nlines + per_block - 1) / per_block);
       if ((size_t)(bz[r + 1] - bz[r]) > c.npart) DB_THROW(DBFFT_EUNSUPPORTED, "z pass partials exceed the cell's buffer");
       lz = std::max(lz, (size_t)(2 * M + 1 + (size_t)(kLineThreads / 64) * lb * (M + tl + 1) +
-                                 (staged ? (size_t)9 * lb * M : 0)) * eb);
+                                 (staged ? (size_t)c.ncomp * lb * M : 0)) * eb);
     } else {
       bz[r + 1] = bz[r] + (int)((nlines + B.L[r] - 1) / B.L[r]);
       lz = std::max(lz, line_smem_bytes(c.g, B.L[r], c.ncomp, (int)eb));

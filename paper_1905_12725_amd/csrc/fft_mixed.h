@@ -498,17 +498,19 @@ __device__ __forceinline__ double mixed_line_fused(const cpx<T>* in, cpx<T>* out
 }
 
 // z pass of one line group (LB lines) by the NW waves of a block, for
-// tangents that couple every component (finite strains): wave w transforms
+// tangents that couple every component (anisotropic small-strain tangents,
+// finite strains): wave w transforms
 // the components w, w + NW, ... one at a time and stages their real values
 // in LDS (X: [c][line][n], packed pairs n = 0..M-1), the block applies the
 // tangent voxel by voxel from there, and every wave transforms its
 // components back.  Only one component is in registers at a time, so the
 // pass does not hold all nine (the register-resident version needs 256
-// VGPRs and spills).  `lds` is the wave's own exchange buffer.  Returns
+// VGPRs and spills).  X holds NC = 6 (small strains) or 9 components.
+// `lds` is the wave's own exchange buffer.  Returns
 // this thread's share of the energy (1/N of sum eps : sigma); the caller
 // sums over the block.  Every thread of the block must call it: the
 // transforms and the staging use block barriers.
-template <typename T, int M, int LAW, int NW>
+template <typename T, int M, int KIN, int LAW, int NW>
 __device__ __forceinline__ double mixed_line_staged(const cpx<T>* in, cpx<T>* out, const Geom& g,
                                                     const cpx<T>* tw, const cpx<T>* rtw, cpx<T>* lds,
                                                     cpx<T>* __restrict__ X, const TangentArgs<T>& tn,
@@ -516,7 +518,7 @@ __device__ __forceinline__ double mixed_line_staged(const cpx<T>* in, cpx<T>* ou
                                                     int wave, int lane) {
   using L = MixedLine<M>;
   constexpr int N1 = L::N1, N2 = L::N2, EM = L::EM, TL = L::TL, LB = L::LB, PITCH = L::PITCH;
-  constexpr int NC = 9;
+  constexpr int NC = (KIN == KIN_SMALL) ? 6 : 9;
   const int line = lane / TL, t = lane % TL;
   const long long nlines = (long long)g.n1 * g.n2;
   const long long gl = group * LB + line;
@@ -562,11 +564,18 @@ __device__ __forceinline__ double mixed_line_staged(const cpx<T>* in, cpx<T>* ou
       T ev[NC], sv[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) ev[c] = (h == 0 ? v[c].x : v[c].y) + (T)mac[c];
-      tangent_finite<T, LAW>(tn, vox, g.nvox, ev, sv);
-      double acc = 0.0;
+      if constexpr (KIN == KIN_SMALL) {
+        if (tn.kind == TAN_ANISO_FIELD) tangent_small_field<T>(tn, vox, g.nvox, ev, sv);
+        else tangent_small<T>(tn, vox, ev, sv);
+        energy += (double)(ev[0] * sv[0] + ev[1] * sv[1] + ev[2] * sv[2]) +
+                  2.0 * (double)(ev[3] * sv[3] + ev[4] * sv[4] + ev[5] * sv[5]);
+      } else {
+        tangent_finite<T, LAW>(tn, vox, g.nvox, ev, sv);
+        double acc = 0.0;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc += (double)(ev[c] * sv[c]);
-      energy += acc;
+        for (int c = 0; c < NC; ++c) acc += (double)(ev[c] * sv[c]);
+        energy += acc;
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (h == 0) v[c].x = sv[c];

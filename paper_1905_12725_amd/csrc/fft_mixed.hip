@@ -93,6 +93,35 @@ __global__ __launch_bounds__(64) void k_line_mixed(const cpx<T>* in, cpx<T>* out
   if (partials != nullptr && threadIdx.x == 0) partials[blockIdx.x + (long long)blockIdx.y * gridDim.x] = e;
 }
 
+// z pass of the anisotropic and finite-strain tangents in FP32: the four
+// waves of a block share one line group, whose components are staged in LDS
+// (mixed_line_staged); one energy partial per block.
+template <typename T, int M, int KIN, int LAW>
+__global__ __launch_bounds__(256) void k_line_staged(const cpx<T>* in, cpx<T>* out, Geom g,
+                                                     const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ rtwg,
+                                                     TangentArgs<T> tn, const double* __restrict__ macro_dev,
+                                                     double* __restrict__ partials, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
+  using L = MixedLine<M>;
+  constexpr int NW = 4, NC = (KIN == KIN_SMALL) ? 6 : 9;
+  __shared__ cpx<T> tw[M];
+  __shared__ cpx<T> rtw[M + 1];
+  __shared__ cpx<T> lds[NW * L::LB * L::PITCH];
+  __shared__ cpx<T> X[NC * L::LB * M];
+  __shared__ double ew[NW];
+  for (int i = threadIdx.x; i < M; i += NW * 64) tw[i] = twg[i];
+  for (int i = threadIdx.x; i <= M; i += NW * 64) rtw[i] = rtwg[i];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double e = mixed_line_staged<T, M, KIN, LAW, NW>(in, out, g, tw, rtw, lds + w * L::LB * L::PITCH, X, tn, macro_dev,
+                                                    blockIdx.x, w, lane);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+  if (lane == 0) ew[w] = e;
+  __syncthreads();
+  if (threadIdx.x == 0 && partials != nullptr) partials[blockIdx.x] = (ew[0] + ew[1]) + (ew[2] + ew[3]);
+}
+
 static int mixed_lines_per_wave(int M) {
   const int n1 = mixed_n1(M), n2 = M / n1;
   return 64 / (n1 > n2 ? n1 : n2);
@@ -123,14 +152,16 @@ static void launch_line_mixed_m(int kin, bool iso, const void* in, void* out, co
     DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 1>), dim3(nb, 2), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
                        partials, stop);
   else if constexpr (sizeof(T) == 4) {
+    // one line group per block of four waves (as many blocks as there are
+    // line groups, so the energy partials count as for one wave per group)
     if (kin == KIN_SMALL)
-      DB_LAUNCH((k_line_mixed<T, M, KIN_SMALL, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
-                         partials, stop);
+      DB_LAUNCH((k_line_staged<T, M, KIN_SMALL, 0>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
+                partials, stop);
     else if (finite_law(tan.kind) == 2)
-      DB_LAUNCH((k_line_mixed<T, M, KIN_FINITE, 2>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+      DB_LAUNCH((k_line_staged<T, M, KIN_FINITE, 2>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
                 partials, stop);
     else
-      DB_LAUNCH((k_line_mixed<T, M, KIN_FINITE, 0>), dim3(nb), dim3(64), 0, st, i, o, g, t, r, tan, macro_dev,
+      DB_LAUNCH((k_line_staged<T, M, KIN_FINITE, 0>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
                 partials, stop);
   }
 }

@@ -80,23 +80,25 @@ def test_real_apply_lengths(gpu, n, kin, prec):
     assert rel(f, ref) < (1e-12 if prec == "fp64" else 1e-5)
 
 
-@pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 54), (96, 6, 8), (6, 90, 8), (72, 4, 54)])
-def test_real_apply_aniso_lengths(gpu, n):
-    """Anisotropic grain stiffness (21 coefficients: the z pass that keeps
-    every component live)."""
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 54), (4, 6, 90), (96, 6, 8), (6, 90, 8), (72, 4, 54)])
+def test_real_apply_aniso_lengths(gpu, n, prec):
+    """Anisotropic grain stiffness (21 coefficients: the z pass that couples
+    every component; in FP32 the components of a line group are staged in
+    LDS by four waves)."""
     import torch
     from paper_1905_12725_amd.api import Cell
-    print(f"case real_apply aniso n={n}", flush=True)
+    print(f"case real_apply aniso {prec} n={n}", flush=True)
     rng = np.random.default_rng(210)
     ng = 4
     grain = rng.integers(0, ng, size=n).astype(np.int32)
     A = rng.standard_normal((ng, 6, 6))
     Cm = np.einsum("gab,gcb->gac", A, A) + 6 * np.eye(6)
     u = rng.standard_normal((3,) + n)
-    with Cell(n, "aniso_grain", torch.from_numpy(grain), Cm.reshape(-1)) as cell:
+    with Cell(n, "aniso_grain", torch.from_numpy(grain), Cm.reshape(-1), precision=prec) as cell:
         f = cell.apply(torch.from_numpy(u).cuda()).cpu().numpy()
     ref = _oracle_real_apply(n, so.GeneralTangent(mt.mandel_to_tensor4(Cm[grain])), so.SMALL, u)
-    assert rel(f, ref) < 1e-12
+    assert rel(f, ref) < (1e-12 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 90), (96, 6, 8), (6, 80, 8), (72, 4, 54)])
