@@ -345,7 +345,8 @@ dbfft_status dbfft_adjoint(dbfft_ctx* ctx, const double G[9], const double H[9],
  * milliseconds and launch count of kernel kind k:
  *   0 x pass inverse + gradient      1 y pass inverse
  *   2 z pass C2R + tangent + R2C     3 y pass forward
- *   4 x pass forward + divergence    5 CG step length (scalar)
+ *   4 x pass forward + divergence    5 unused (the step length is taken by
+ *                                      the first block of a pass)
  *   6 CG update x, r, <r, M r>       7 CG direction scalars (scalar)
  *   8 CG direction p = M r + beta p
  * The current totals are returned first; enable = 1 then starts (and, if

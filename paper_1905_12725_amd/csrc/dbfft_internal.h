@@ -139,10 +139,19 @@ enum StridedMode : int {
   SP_DIV_FINITE = 4,  // in: 9 comps, forward FFT along x, out: 3 comps
 };
 
+// alpha of a PCG iteration, computed by the first block of a pass (the
+// fused iteration's y forward pass, the separate iteration's x forward
+// pass) from the energy partials of the z pass before it
+struct AlphaTask {
+  PcgScalars* sc = nullptr;
+  const double* eparts = nullptr;
+  int neparts = 0;
+};
+
 template <typename T>
 void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,
                     const Geom& g, const FftPlan& plan, const void* tw, int dir, double* dc_out,
-                    hipStream_t st, const int* stop);
+                    hipStream_t st, const int* stop, const AlphaTask& at = AlphaTask());
 
 enum LineMode : int {
   LP_FUSED = 0,       // C2R -> (+ macro) -> tangent -> R2C (scaled 1/N); energy partials
@@ -192,12 +201,14 @@ void launch_line_mixed(int kin, bool iso, const void* in, void* out, const Geom&
 bool mixed_strided_supported(int n);
 template <typename T>
 void launch_strided_mixed(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
-                          const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop);
+                          const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                          const AlphaTask& at = AlphaTask());
 bool fast_line_supported(int n3);
 int fast_line_blocks(const Geom& g, int elem_bytes);
 template <typename T>
 void launch_strided_fast(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
-                         const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop);
+                         const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                         const AlphaTask& at = AlphaTask());
 template <typename T>
 void launch_line_fast(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
                       const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
@@ -236,7 +247,6 @@ void launch_precond_dots(void* r, const PrecondArgs& pa, const Geom& g, double* 
 // the self-conjugate planes and emits the partial sums of <r, M r> and
 // <r, r>; beta takes the macroscopic step with the divergence pass's average
 // stress; the direction kernel adds alpha p to x and forms the next p.
-void launch_pcg_alpha_only(PcgScalars* sc, const double* partials, int nparts, hipStream_t st);
 void launch_pcg_beta_step(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                           hipStream_t st);
 template <typename T>
@@ -249,14 +259,7 @@ template <typename T>
 int launch_div_update_fast(const void* W, void* r, const StridedGeom& sg, const Geom& g, const void* tw,
                            const PcgScalars* sc, const PrecondArgs& pa, double* dc_out, double* partials,
                            hipStream_t st);
-// plain register-FFT y pass whose first block also computes alpha
-template <typename T>
-void launch_strided_fast_alpha(const void* in, void* out, int ncomp, const StridedGeom& sg, const Geom& g,
-                               const void* tw, int dir, hipStream_t st, const int* stop, PcgScalars* sc,
-                               const double* eparts, int neparts);
 int fused_cg_partials(const Geom& g);
-void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
-                      hipStream_t st);
 void launch_pcg_beta(PcgScalars* sc, const double* partials, int nparts, const PcgConst& pc, int first,
                      hipStream_t st);
 int pcg_block_count(const Geom& g);

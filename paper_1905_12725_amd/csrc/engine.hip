@@ -416,9 +416,11 @@ static StridedGeom ygeom(const Ctx& c) {
 
 // ------------------------------------------------------------------ operator pieces
 // K a: x inverse + gradient -> y inverse -> z fused tangent -> y forward -> x forward + divergence
+// (whose first block computes alpha when `at` names the PCG state)
 template <typename T>
 static void apply_K(Ctx& c, const void* a, void* out, const double* macro_dev, const double* macro_add,
-                    const TangentArgs<T>& tan, double* energy_partials, double* dc_out, const int* stop) {
+                    const TangentArgs<T>& tan, double* energy_partials, double* dc_out, const int* stop,
+                    const AlphaTask& at = AlphaTask()) {
   Tables<T>& tb = tables<T>(c);
   const StridedGeom sx = xgeom(c), sy = ygeom(c);
   const int gm = (c.kin == KIN_SMALL) ? SP_GRAD_SMALL : SP_GRAD_FINITE;
@@ -434,7 +436,7 @@ static void apply_K(Ctx& c, const void* a, void* out, const double* macro_dev, c
   prof_mark(c, PK_YFWD);
   launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
   prof_mark(c, PK_XFWD);
-  launch_strided<T>(dm, c.W, out, 0, sx, c.g, c.p1, tb.tw1, -1, dc_out, c.st, stop);
+  launch_strided<T>(dm, c.W, out, 0, sx, c.g, c.p1, tb.tw1, -1, dc_out, c.st, stop, at);
 }
 
 template <typename T>
@@ -772,15 +774,12 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
         prof_mark(c, PK_ZFUSED);
         launch_line<T>(LP_FUSED, c.kin, c.W, c.W, c.g, c.p3, tb.tw3, tb.rtw, tan, pmac, nullptr, c.partA, c.ncomp,
                        c.st, nullptr, stop);
-        if (fast_strided_supported(c.n[1])) {
-          prof_mark(c, PK_YFWD);
-          launch_strided_fast_alpha<T>(c.W, c.W, c.ncomp, sy, c.g, tb.tw2, -1, c.st, stop, c.sc_dev, c.partA, neb);
-        } else {
-          prof_mark(c, PK_ALPHA);
-          launch_pcg_alpha_only(c.sc_dev, c.partA, neb, c.st);
-          prof_mark(c, PK_YFWD);
-          launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop);
-        }
+        AlphaTask at;
+        at.sc = c.sc_dev;
+        at.eparts = c.partA;
+        at.neparts = neb;
+        prof_mark(c, PK_YFWD);
+        launch_strided<T>(SP_PLAIN, c.W, c.W, c.ncomp, sy, c.g, c.p2, tb.tw2, -1, nullptr, c.st, stop, at);
         prof_mark(c, PK_XFWD);
         const int nd = launch_div_update_fast<T>(c.W, r, sx, c.g, tb.tw1, c.sc_dev, pa, c.dc_dev, c.partB, c.st);
         prof_mark(c, PK_BETA);
@@ -789,14 +788,17 @@ static PcgOut run_pcg(Ctx& c, const TangentArgs<T>& tan, const PrecondArgs& pa, 
         launch_pcg_xp<T>(x, p, r, c.sc_dev, pa, c.g, nb, c.st);
         continue;
       }
-      // K p | alpha (+ macroscopic step) | r -= alpha q | beta | x += alpha p, next p
-      apply_K<T>(c, p, q, pmac, nullptr, tan, c.partA, c.dc_dev, stop);
-      prof_mark(c, PK_ALPHA);
-      launch_pcg_alpha(c.sc_dev, c.partA, neb, c.dc_dev, pc, c.st);
+      // K p (the first block of its x forward pass: alpha) | r -= alpha q |
+      // beta (+ macroscopic step) | x += alpha p, next p
+      AlphaTask at;
+      at.sc = c.sc_dev;
+      at.eparts = c.partA;
+      at.neparts = neb;
+      apply_K<T>(c, p, q, pmac, nullptr, tan, c.partA, c.dc_dev, stop, at);
       prof_mark(c, PK_UPDATE);
       launch_pcg_update<T>(nullptr, r, p, q, c.sc_dev, pa, c.g, c.partB, nb, c.st);
       prof_mark(c, PK_BETA);
-      launch_pcg_beta(c.sc_dev, c.partB, nb, pc, 0, c.st);
+      launch_pcg_beta_step(c.sc_dev, c.partB, nb, c.dc_dev, pc, c.st);
       prof_mark(c, PK_PUPDATE);
       launch_pcg_xp<T>(x, p, r, c.sc_dev, pa, c.g, nb, c.st);
     }

@@ -230,4 +230,64 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// alpha = <r, M r> / <p, K p> from the z pass's energy partials
+// (fixed-order sum), done by the first block of a following pass (every
+// thread of that block calls it); marks the step pending for the direction
+// kernel, or flags a breakdown.  A converged iteration clears the pending
+// step.  The macroscopic part of the step is taken by the beta kernel.
+template <int NT>
+__device__ __forceinline__ void alpha_task(PcgScalars* sc, const double* __restrict__ eparts, int neparts) {
+  __shared__ double red[NT / 64];
+  if (sc->converged) {
+    if (threadIdx.x == 0) sc->pending = 0;
+    return;
+  }
+  double e = 0.0;
+  for (int i = threadIdx.x; i < neparts; i += NT) e += eparts[i];
+  const double pq = block_sum<NT>(e, red);
+  if (threadIdx.x == 0) {
+    sc->pq = pq;
+    if (!(pq > 0.0)) {
+      sc->converged = 2;
+      sc->pending = 0;
+    } else {
+      sc->alpha = sc->rz / pq;
+      sc->pending = 1;
+    }
+  }
+}
+
+// alpha_task by the first wave of a block alone (fixed-order sum over its
+// lanes, then across them), for blocks whose size is not a multiple of 64;
+// the other threads return at once and nothing waits on a barrier.
+__device__ __forceinline__ void alpha_task_wave(PcgScalars* sc, const double* __restrict__ eparts, int neparts) {
+  if (threadIdx.x >= 64) return;
+  if (sc->converged) {
+    if (threadIdx.x == 0) sc->pending = 0;
+    return;
+  }
+  // eight loads in flight per lane (the partials of a large grid number a
+  // few thousand), summed in a fixed order
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 7 * 64 < neparts; i += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += eparts[i + u * 64];
+  }
+  for (; i < neparts; i += 64) a[0] += eparts[i];
+  double e = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if (threadIdx.x == 0) {
+    sc->pq = e;
+    if (!(e > 0.0)) {
+      sc->converged = 2;
+      sc->pending = 0;
+    } else {
+      sc->alpha = sc->rz / e;
+      sc->pending = 1;
+    }
+  }
+}
+
 }  // namespace dbfft

@@ -123,32 +123,6 @@ __device__ __forceinline__ constexpr int fast_out_pos(int g) {
 }
 
 // ------------------------------------------------------------------ x / y passes
-// Fused CG: alpha = <r, M r> / <p, K p> from the z pass's energy partials
-// (fixed-order sum), done by one block of the following y pass; marks the
-// step pending for the direction kernel, or flags a breakdown.  A converged
-// iteration clears the pending step.
-template <int NT>
-__device__ __forceinline__ void alpha_task(PcgScalars* sc, const double* __restrict__ eparts, int neparts) {
-  __shared__ double red[NT / 64];
-  if (sc->converged) {
-    if (threadIdx.x == 0) sc->pending = 0;
-    return;
-  }
-  double e = 0.0;
-  for (int i = threadIdx.x; i < neparts; i += NT) e += eparts[i];
-  const double pq = block_sum<NT>(e, red);
-  if (threadIdx.x == 0) {
-    sc->pq = pq;
-    if (!(pq > 0.0)) {
-      sc->converged = 2;
-      sc->pending = 0;
-    } else {
-      sc->alpha = sc->rz / pq;
-      sc->pending = 1;
-    }
-  }
-}
-
 // Elements per thread: 4 for the passes that keep several vectors live
 // (gradient, divergence), 8 for the plain ones.
 template <typename T, int N, int MODE>
@@ -608,53 +582,45 @@ static void launch_fast_nm(const void* in, void* out, int ncomp_plain, const Str
                      eparts, neparts);
 }
 
-// plain y pass whose first block also computes alpha (fused CG)
-template <typename T>
-void launch_strided_fast_alpha(const void* in, void* out, int ncomp, const StridedGeom& sg, const Geom& g,
-                               const void* tw, int dir, hipStream_t st, const int* stop, PcgScalars* sc,
-                               const double* eparts, int neparts) {
-  switch (sg.nline) {
-    case 8: launch_fast_nm<T, 8, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
-    case 16: launch_fast_nm<T, 16, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
-    case 32: launch_fast_nm<T, 32, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
-    case 64: launch_fast_nm<T, 64, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
-    case 128: launch_fast_nm<T, 128, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
-    default: launch_fast_nm<T, 256, SP_PLAIN>(in, out, ncomp, sg, g, tw, dir, nullptr, st, stop, sc, eparts, neparts); break;
-  }
-}
-template void launch_strided_fast_alpha<double>(const void*, void*, int, const StridedGeom&, const Geom&, const void*,
-                                                int, hipStream_t, const int*, PcgScalars*, const double*, int);
-template void launch_strided_fast_alpha<float>(const void*, void*, int, const StridedGeom&, const Geom&, const void*,
-                                               int, hipStream_t, const int*, PcgScalars*, const double*, int);
-
 template <typename T, int N>
 static void launch_fast_n(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,
-                          const Geom& g, const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+                          const Geom& g, const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                          const AlphaTask& at) {
+  PcgScalars* a = at.sc;
+  const double* e = at.eparts;
+  const int ne = at.neparts;
   switch (mode) {
-    case SP_PLAIN: launch_fast_nm<T, N, SP_PLAIN>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case SP_GRAD_SMALL: launch_fast_nm<T, N, SP_GRAD_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case SP_GRAD_FINITE: launch_fast_nm<T, N, SP_GRAD_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case SP_DIV_SMALL: launch_fast_nm<T, N, SP_DIV_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    default: launch_fast_nm<T, N, SP_DIV_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    case SP_PLAIN: launch_fast_nm<T, N, SP_PLAIN>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, a, e, ne); break;
+    case SP_GRAD_SMALL:
+      launch_fast_nm<T, N, SP_GRAD_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, a, e, ne);
+      break;
+    case SP_GRAD_FINITE:
+      launch_fast_nm<T, N, SP_GRAD_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, a, e, ne);
+      break;
+    case SP_DIV_SMALL:
+      launch_fast_nm<T, N, SP_DIV_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, a, e, ne);
+      break;
+    default: launch_fast_nm<T, N, SP_DIV_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, a, e, ne); break;
   }
 }
 
 template <typename T>
 void launch_strided_fast(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
-                         const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+                         const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                         const AlphaTask& at) {
   switch (sg.nline) {
-    case 8: launch_fast_n<T, 8>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case 16: launch_fast_n<T, 16>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case 32: launch_fast_n<T, 32>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case 64: launch_fast_n<T, 64>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case 128: launch_fast_n<T, 128>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    default: launch_fast_n<T, 256>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    case 8: launch_fast_n<T, 8>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    case 16: launch_fast_n<T, 16>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    case 32: launch_fast_n<T, 32>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    case 64: launch_fast_n<T, 64>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    case 128: launch_fast_n<T, 128>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    default: launch_fast_n<T, 256>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
   }
 }
 template void launch_strided_fast<double>(int, const void*, void*, int, const StridedGeom&, const Geom&, const void*,
-                                          int, double*, hipStream_t, const int*);
+                                          int, double*, hipStream_t, const int*, const AlphaTask&);
 template void launch_strided_fast<float>(int, const void*, void*, int, const StridedGeom&, const Geom&, const void*,
-                                         int, double*, hipStream_t, const int*);
+                                         int, double*, hipStream_t, const int*, const AlphaTask&);
 
 // ------------------------------------------------------------------ z pass (fused tangent)
 // One wave per block; TL = M/8 threads per z line, 64/TL lines per wave.

@@ -10,9 +10,10 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__(MixedShape<N>::NT) void k_strided_mixed(const cpx<T>* in, cpx<T>* out, StridedGeom sg,
                                                                      Geom g, const cpx<T>* __restrict__ twg, T d,
                                                                      double* __restrict__ dc_out,
-                                                                     const int* __restrict__ stop) {
-  if (stop != nullptr && *stop) return;
+                                                                     const int* __restrict__ stop, AlphaTask at) {
   using S = MixedShape<N>;
+  if (at.sc != nullptr && blockIdx.x == 0 && blockIdx.z == 0) alpha_task_wave(at.sc, at.eparts, at.neparts);
+  if (stop != nullptr && *stop) return;
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> lds[N * S::PITCH];
   for (int i = threadIdx.x; i < N; i += S::NT) tw[i] = twg[i];
@@ -33,34 +34,41 @@ bool mixed_strided_supported(int n) { return two_step_n1(n) != 0; }
 
 template <typename T, int N, int MODE>
 static void launch_mixed_nm(const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
-                            const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+                            const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                            const AlphaTask& at) {
   using S = MixedShape<N>;
   const long long npair = (long long)sg.nother * sg.ncols;
   const int ntiles = (int)((npair + S::TZ - 1) / S::TZ);
   const int nz = MODE == SP_PLAIN ? ncomp_plain : ((MODE == SP_GRAD_SMALL || MODE == SP_DIV_SMALL) ? 3 : 1);
   dim3 grid(ntiles, 1, nz);
   DB_LAUNCH((k_strided_mixed<T, N, MODE>), grid, dim3(S::NT), 0, st, static_cast<const cpx<T>*>(in),
-                     static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop);
+                     static_cast<cpx<T>*>(out), sg, g, static_cast<const cpx<T>*>(tw), (T)dir, dc_out, stop, at);
 }
 
 template <typename T, int N>
 static void launch_mixed_n(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg,
-                           const Geom& g, const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+                           const Geom& g, const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                           const AlphaTask& at) {
   switch (mode) {
-    case SP_PLAIN: launch_mixed_nm<T, N, SP_PLAIN>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case SP_GRAD_SMALL: launch_mixed_nm<T, N, SP_GRAD_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case SP_GRAD_FINITE: launch_mixed_nm<T, N, SP_GRAD_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    case SP_DIV_SMALL: launch_mixed_nm<T, N, SP_DIV_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
-    default: launch_mixed_nm<T, N, SP_DIV_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+    case SP_PLAIN: launch_mixed_nm<T, N, SP_PLAIN>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    case SP_GRAD_SMALL:
+      launch_mixed_nm<T, N, SP_GRAD_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at);
+      break;
+    case SP_GRAD_FINITE:
+      launch_mixed_nm<T, N, SP_GRAD_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at);
+      break;
+    case SP_DIV_SMALL: launch_mixed_nm<T, N, SP_DIV_SMALL>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
+    default: launch_mixed_nm<T, N, SP_DIV_FINITE>(in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
   }
 }
 
 template <typename T>
 void launch_strided_mixed(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
-                          const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop) {
+                          const void* tw, int dir, double* dc_out, hipStream_t st, const int* stop,
+                          const AlphaTask& at) {
   switch (sg.nline) {
 #define DBFFT_MIX(NN) \
-  case NN: launch_mixed_n<T, NN>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop); break;
+  case NN: launch_mixed_n<T, NN>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at); break;
     DBFFT_MIX(12) DBFFT_MIX(15) DBFFT_MIX(18) DBFFT_MIX(20) DBFFT_MIX(24) DBFFT_MIX(25) DBFFT_MIX(27)
     DBFFT_MIX(30) DBFFT_MIX(36) DBFFT_MIX(40) DBFFT_MIX(45) DBFFT_MIX(48) DBFFT_MIX(50) DBFFT_MIX(54)
     DBFFT_MIX(60) DBFFT_MIX(63) DBFFT_MIX(72) DBFFT_MIX(80) DBFFT_MIX(90) DBFFT_MIX(96)
@@ -69,9 +77,9 @@ void launch_strided_mixed(int mode, const void* in, void* out, int ncomp_plain, 
   }
 }
 template void launch_strided_mixed<double>(int, const void*, void*, int, const StridedGeom&, const Geom&,
-                                           const void*, int, double*, hipStream_t, const int*);
+                                           const void*, int, double*, hipStream_t, const int*, const AlphaTask&);
 template void launch_strided_mixed<float>(int, const void*, void*, int, const StridedGeom&, const Geom&, const void*,
-                                          int, double*, hipStream_t, const int*);
+                                          int, double*, hipStream_t, const int*, const AlphaTask&);
 
 // ---------------------------------------------------------------- z pass
 template <typename T, int M, int KIN, int ISO>

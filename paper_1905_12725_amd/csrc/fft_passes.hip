@@ -21,7 +21,9 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kStridedThreads) void k_strided(const cpx<T>* in, cpx<T>* out, StridedGeom sg, Geom g,
                                                              FftPlan plan, const cpx<T>* __restrict__ twg,
                                                              T d, int TZ, double* __restrict__ dc_out,
-                                                             const int* __restrict__ stop) {
+                                                             const int* __restrict__ stop, AlphaTask at) {
+  if (at.sc != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
+    alpha_task_wave(at.sc, at.eparts, at.neparts);
   if (stop != nullptr && *stop) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   strided_core<T, MODE>(in, out, sg, g, plan, twg, d, TZ, dc_out, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
@@ -41,13 +43,13 @@ static int strided_tile(int nline, int elem_bytes, int fused) {
 template <typename T>
 void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const StridedGeom& sg, const Geom& g,
                     const FftPlan& plan, const void* tw, int dir, double* dc_out, hipStream_t st,
-                    const int* stop) {
+                    const int* stop, const AlphaTask& at) {
   if (fast_strided_supported(sg.nline)) {
-    launch_strided_fast<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop);
+    launch_strided_fast<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at);
     return;
   }
   if (mixed_strided_supported(sg.nline)) {
-    launch_strided_mixed<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop);
+    launch_strided_mixed<T>(mode, in, out, ncomp_plain, sg, g, tw, dir, dc_out, st, stop, at);
     return;
   }
   const int eb = (int)sizeof(cpx<T>);
@@ -61,27 +63,27 @@ void launch_strided(int mode, const void* in, void* out, int ncomp_plain, const 
   auto t = static_cast<const cpx<T>*>(tw);
   switch (mode) {
     case SP_PLAIN:
-      DB_LAUNCH((k_strided<T, SP_PLAIN>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_PLAIN>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop, at);
       break;
     case SP_GRAD_SMALL:
-      DB_LAUNCH((k_strided<T, SP_GRAD_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_GRAD_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop, at);
       break;
     case SP_GRAD_FINITE:
-      DB_LAUNCH((k_strided<T, SP_GRAD_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_GRAD_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop, at);
       break;
     case SP_DIV_SMALL:
-      DB_LAUNCH((k_strided<T, SP_DIV_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_DIV_SMALL>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop, at);
       break;
     default:
-      DB_LAUNCH((k_strided<T, SP_DIV_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop);
+      DB_LAUNCH((k_strided<T, SP_DIV_FINITE>), grid, dim3(kStridedThreads), shm, st, i, o, sg, g, plan, t, d, TZ, dc_out, stop, at);
       break;
   }
 }
 
 template void launch_strided<double>(int, const void*, void*, int, const StridedGeom&, const Geom&, const FftPlan&,
-                                     const void*, int, double*, hipStream_t, const int*);
+                                     const void*, int, double*, hipStream_t, const int*, const AlphaTask&);
 template void launch_strided<float>(int, const void*, void*, int, const StridedGeom&, const Geom&, const FftPlan&,
-                                    const void*, int, double*, hipStream_t, const int*);
+                                    const void*, int, double*, hipStream_t, const int*, const AlphaTask&);
 
 // ------------------------------------------------------------------ z pass
 // Block = L consecutive (x, y) lines.  A real transform of even length n3 is

@@ -39,19 +39,9 @@ __global__ __launch_bounds__(kVecThreads) void k_pinit(cpx<T>* __restrict__ p, c
   pinit_core<T, WRITE_P>(p, r, pa, g, partials, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_alpha(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
-                                                       int nparts, const double* __restrict__ dc, PcgConst pc) {
-  alpha_core(sc, partials, nparts, dc, pc);
-}
-
 __global__ __launch_bounds__(kVecThreads) void k_beta(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
                                                       int nparts, PcgConst pc, int first) {
   beta_core(sc, partials, nparts, pc, first);
-}
-
-__global__ __launch_bounds__(kVecThreads) void k_alpha_only(PcgScalars* __restrict__ sc,
-                                                            const double* __restrict__ partials, int nparts) {
-  alpha_only_core(sc, partials, nparts);
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_beta_step(PcgScalars* __restrict__ sc,
@@ -67,9 +57,6 @@ __global__ __launch_bounds__(kVecThreads) void k_xp(cpx<T>* __restrict__ x, cpx<
   xp_core<T>(x, p, r, sc, pa, g, blockIdx.x, gridDim.x);
 }
 
-void launch_pcg_alpha_only(PcgScalars* sc, const double* partials, int nparts, hipStream_t st) {
-  DB_LAUNCH(k_alpha_only, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts);
-}
 void launch_pcg_beta_step(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
                           hipStream_t st) {
   DB_LAUNCH(k_beta_step, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
@@ -118,10 +105,6 @@ void launch_precond_dots(void* r, const PrecondArgs& pa, const Geom& g, double* 
 }
 template void launch_precond_dots<double>(void*, const PrecondArgs&, const Geom&, double*, int, hipStream_t);
 template void launch_precond_dots<float>(void*, const PrecondArgs&, const Geom&, double*, int, hipStream_t);
-void launch_pcg_alpha(PcgScalars* sc, const double* partials, int nparts, const double* dc, const PcgConst& pc,
-                      hipStream_t st) {
-  DB_LAUNCH(k_alpha, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, dc, pc);
-}
 void launch_pcg_beta(PcgScalars* sc, const double* partials, int nparts, const PcgConst& pc, int first,
                      hipStream_t st) {
   DB_LAUNCH(k_beta, dim3(1), dim3(kVecThreads), 0, st, sc, partials, nparts, pc, first);

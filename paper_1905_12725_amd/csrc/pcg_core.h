@@ -257,27 +257,6 @@ __device__ __forceinline__ void macro_step(PcgScalars* __restrict__ sc, double a
   for (int c = 0; c < pc.ncomp; ++c) sc->sig[c] += alpha * dc[c];
 }
 
-// fused CG: alpha = <r,z>/<p,Kp> only; `pending` tells the direction kernel
-// whether x still takes this iteration's step
-__device__ __forceinline__ void alpha_only_core(PcgScalars* __restrict__ sc, const double* __restrict__ partials,
-                                                int nparts) {
-  __shared__ double red[kVecThreads / 64];
-  if (sc->converged) {
-    if (threadIdx.x == 0) sc->pending = 0;
-    return;
-  }
-  const double pq = reduce_fixed(partials, nparts, 1, 0, red);
-  if (threadIdx.x != 0) return;
-  sc->pq = pq;
-  if (!(pq > 0.0)) {
-    sc->converged = 2;
-    sc->pending = 0;
-    return;
-  }
-  sc->alpha = sc->rz / pq;
-  sc->pending = 1;
-}
-
 // alpha = <r,z>/<p,Kp>; macro block of x and r; tracked average stress.
 // partials: energy sums of the z pass (one per block) = <p, K p>.  The
 // field part of x takes alpha p in the direction kernel (`pending`, as in
