@@ -48,14 +48,14 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 is recorded here and are reported as null once those change.
 TRAFFIC_SOURCES = ("paper_1905_12725_amd/csrc/fft_fast.hip", "paper_1905_12725_amd/csrc/fft_common.h",
                    "paper_1905_12725_amd/csrc/pcg_core.h", "paper_1905_12725_amd/csrc/pcg.hip")
-TRAFFIC_SHA256 = "cb0f1a129e6657f84d102e6ee990e8a74440b2803f4eeec1c2991e552b6ebf8f"
+TRAFFIC_SHA256 = "8f2028f5d67fb94f288b6723d40ac1b30fd4ef582ec77f93066a0f5e428116f1"
 TRAFFIC_128 = {
-    "fp64": {"x_inverse_grad": 153575310, "y_inverse": 207253072, "y_forward": 207253072,
-             "z_fused_tangent": 213072495, "x_forward_div": 227601009, "cg_beta": 34815,
-             "cg_direction": 255661750},
-    "fp32_mixed": {"x_inverse_grad": 76856582, "y_inverse": 102462160, "y_forward": 102462160,
-                   "z_fused_tangent": 108701094, "x_forward_div": 123959788, "cg_beta": 34815,
-                   "cg_direction": 127875418},
+    "fp64": {"x_inverse_grad": 153575322, "y_inverse": 207308617, "y_forward": 207308617,
+             "z_fused_tangent": 213127961, "x_forward_div": 227591867, "cg_beta": 34815,
+             "cg_direction": 255661787},
+    "fp32_mixed": {"x_inverse_grad": 76856972, "y_inverse": 102418812, "y_forward": 102418812,
+                   "z_fused_tangent": 108695284, "x_forward_div": 123940035, "cg_beta": 34815,
+                   "cg_direction": 127875436},
 }
 
 
