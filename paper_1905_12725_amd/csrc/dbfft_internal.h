@@ -188,6 +188,12 @@ void launch_line_real(int mode, const void* in, void* out, const Geom& g, const 
 // small strains), two parts
 bool odd_line_supported(int n3);
 int odd_line_energy_blocks(const Geom& g);
+// FP64 staged z pass of anisotropic / finite-strain tangents, n3 = 32 or 64
+bool staged_line_supported(int n3, int elem_bytes, bool iso);
+int staged_line_blocks(const Geom& g);
+void launch_line_staged(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
+                        const TangentArgs<double>& tan, const double* macro_dev, double* partials, hipStream_t st,
+                        const int* stop);
 template <typename T>
 void launch_line_odd(const void* in, void* out, const Geom& g, const void* tw, const TangentArgs<T>& tan,
                      const double* macro_dev, double* partials, hipStream_t st, const int* stop);

@@ -26,10 +26,12 @@ def oracle_j2_law(grain, R, dt):
 
 
 @pytest.mark.parametrize("ninc", [4])
-def test_j2_mixed_control_parity(gpu, ninc):
+@pytest.mark.parametrize("n", [(8, 8, 6), (4, 4, 32), (3, 4, 64)])
+def test_j2_mixed_control_parity(gpu, ninc, n):
+    """n3 = 32 and 64 take the staged FP64 z pass (four waves per line
+    group), n3 = 6 the LDS engine."""
     import torch
     from paper_1905_12725_amd.api import Cell
-    n = (8, 8, 6)
     print(f"case j2 mixed n={n} ninc={ninc}", flush=True)
     grain, _ = ms.voronoi_grains(n, 6, 31)
     R = ms.random_rotations(6, 32)
