@@ -88,3 +88,28 @@ def test_many_reports_failures_per_load(gpu):
         with pytest.raises(nat.DbfftError) as ex:
             cell.solve_many([np.eye(3)], nstreams=2)
         assert ex.value.status == EUNSUPPORTED
+
+
+def test_many_follows_a_change_of_lengths(gpu):
+    """Helper contexts made for one set of cell lengths take the new ones
+    when the cell's lengths change between two calls (Sec. 2.1: the
+    frequencies scale with 1/L), and more streams than loads are fine."""
+    import torch
+    from paper_1905_12725_amd.api import Cell
+    print("case solve_many lengths change", flush=True)
+    n = (12, 10, 16)
+    rng = np.random.default_rng(501)
+    phase = (rng.random(n) < 0.35).astype(np.uint8)
+    loads = mandel_loads()[:3]
+    with Cell(n, "iso_phase", torch.from_numpy(phase), [1.0, 0.3, 8.0, 0.3]) as cell:
+        first = cell.solve_many(loads, nstreams=3, tol=1e-11, tol_load=1e-11)
+        cell.set_lengths((2.0, 1.0, 0.5))
+        got = cell.solve_many(loads, nstreams=4, tol=1e-11, tol_load=1e-11)
+        ref = [cell.solve(L, tol=1e-11, tol_load=1e-11) for L in loads]
+    for f, g, r in zip(first, got, ref):
+        assert g["status"] == 0
+        assert np.array_equal(g["sigma_bar"], r["sigma_bar"])
+        assert g["pcg_iters"] == r["pcg_iters"]
+        # strain control: stretching the axes by different factors changes
+        # the microstructure's shape, so the response differs from the unit cell's
+        assert not np.array_equal(g["sigma_bar"], f["sigma_bar"])
