@@ -188,11 +188,13 @@ void launch_line_real(int mode, const void* in, void* out, const Geom& g, const 
 // small strains), two parts
 bool odd_line_supported(int n3);
 int odd_line_energy_blocks(const Geom& g);
-// FP64 staged z pass of anisotropic / finite-strain tangents, n3 = 32 or 64
-bool staged_line_supported(int n3, int elem_bytes, bool iso);
+// staged z pass of anisotropic / finite-strain tangents on power-of-two
+// lines (n3 = 32, 64; FP32 also 128)
+bool staged_line_supported(int n3, int elem_bytes, bool iso, bool finite);
 int staged_line_blocks(const Geom& g);
+template <typename T>
 void launch_line_staged(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
-                        const TangentArgs<double>& tan, const double* macro_dev, double* partials, hipStream_t st,
+                        const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
                         const int* stop);
 template <typename T>
 void launch_line_odd(const void* in, void* out, const Geom& g, const void* tw, const TangentArgs<T>& tan,

@@ -1796,7 +1796,7 @@ static void init_grid(Ctx* c, const int64_t n[3], int kin, int prec, int mat, vo
 static int partial_count(const Geom& g) {
   const int zparts = std::max(std::max(mixed_line_supported(g.n3, 16, true) ? mixed_line_energy_blocks(g, true) : 0,
                                        odd_line_supported(g.n3) ? odd_line_energy_blocks(g) : 0),
-                              staged_line_supported(g.n3, 16, false) ? staged_line_blocks(g) : 0);
+                              staged_line_supported(g.n3, 8, false, false) ? staged_line_blocks(g) : 0);
   return std::max(std::max(std::max(std::max(line_block_count(g), 2 * pcg_block_count(g)),
                                     tangent_mean_block_count(g) * 81),
                            fused_cg_partials(g)),

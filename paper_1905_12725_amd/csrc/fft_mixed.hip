@@ -188,43 +188,54 @@ void launch_line_mixed(int kin, bool iso, const void* in, void* out, const Geom&
     default: break;
   }
 }
-// FP64 anisotropic and finite-strain tangents on power-of-two lines of
-// n3/2 = 16 or 32 points: the staged z pass (a block of four waves per line
-// group; the register kernel's one-wave blocks, one line group each, leave
-// most SIMDs idle on grids of 64^3 and below).  Longer lines would not fit
-// the 64 KB of a block's LDS in FP64.
-bool staged_line_supported(int n3, int elem_bytes, bool iso) {
-  return !iso && elem_bytes == 16 && (n3 == 32 || n3 == 64);
+// Anisotropic and finite-strain tangents on power-of-two lines: the staged
+// z pass (a block of four waves per line group) instead of the register
+// kernel, whose one-wave blocks hold every component of their lines (up to
+// 256 VGPRs, one wave per SIMD; on grids of 64^3 and below they also leave
+// SIMDs idle).  The staging buffer and the exchange buffers fit the 64 KB
+// of a block's LDS up to n3 = 64 in FP64 and n3 = 128 in FP32.  FP32
+// finite-strain lines of 128 keep the register kernel (measured faster
+// there: 60 against 67 us at 128^3).
+bool staged_line_supported(int n3, int elem_bytes, bool iso, bool finite) {
+  if (iso) return false;
+  if (n3 == 32 || n3 == 64) return true;
+  return elem_bytes == 8 && n3 == 128 && !finite;
 }
 
 int staged_line_blocks(const Geom& g) { return mixed_line_blocks(g); }
 
-template <int M>
+template <typename T, int M>
 static void launch_staged_m(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
-                            const TangentArgs<double>& tan, const double* macro_dev, double* partials, hipStream_t st,
+                            const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
                             const int* stop) {
   const int nb = staged_line_blocks(g);
-  auto i = static_cast<const cpx<double>*>(in);
-  auto o = static_cast<cpx<double>*>(out);
-  auto t = static_cast<const cpx<double>*>(tw);
-  auto r = static_cast<const cpx<double>*>(rtw);
+  auto i = static_cast<const cpx<T>*>(in);
+  auto o = static_cast<cpx<T>*>(out);
+  auto t = static_cast<const cpx<T>*>(tw);
+  auto r = static_cast<const cpx<T>*>(rtw);
   if (kin == KIN_SMALL)
-    DB_LAUNCH((k_line_staged<double, M, KIN_SMALL, 0>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_staged<T, M, KIN_SMALL, 0>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
               partials, stop);
   else if (finite_law(tan.kind) == 2)
-    DB_LAUNCH((k_line_staged<double, M, KIN_FINITE, 2>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_staged<T, M, KIN_FINITE, 2>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
               partials, stop);
   else
-    DB_LAUNCH((k_line_staged<double, M, KIN_FINITE, 0>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
+    DB_LAUNCH((k_line_staged<T, M, KIN_FINITE, 0>), dim3(nb), dim3(256), 0, st, i, o, g, t, r, tan, macro_dev,
               partials, stop);
 }
 
+template <typename T>
 void launch_line_staged(int kin, const void* in, void* out, const Geom& g, const void* tw, const void* rtw,
-                        const TangentArgs<double>& tan, const double* macro_dev, double* partials, hipStream_t st,
+                        const TangentArgs<T>& tan, const double* macro_dev, double* partials, hipStream_t st,
                         const int* stop) {
-  if (g.n3 == 32) launch_staged_m<16>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
-  else launch_staged_m<32>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
+  if (g.n3 == 32) launch_staged_m<T, 16>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
+  else if (g.n3 == 64) launch_staged_m<T, 32>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
+  else if constexpr (sizeof(T) == 4) launch_staged_m<T, 64>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
 }
+template void launch_line_staged<double>(int, const void*, void*, const Geom&, const void*, const void*,
+                                         const TangentArgs<double>&, const double*, double*, hipStream_t, const int*);
+template void launch_line_staged<float>(int, const void*, void*, const Geom&, const void*, const void*,
+                                        const TangentArgs<float>&, const double*, double*, hipStream_t, const int*);
 
 template void launch_line_mixed<double>(int, bool, const void*, void*, const Geom&, const void*, const void*,
                                         const TangentArgs<double>&, const double*, double*, hipStream_t, const int*);

@@ -118,12 +118,11 @@ void launch_line(int mode, int kin, const void* in, void* out, const Geom& g, co
                  const void* rtw, const TangentArgs<T>& tan, const double* macro_dev, const double* macro_add,
                  double* partials, int ncomp, hipStream_t st, int* nblocks_out, const int* stop) {
   const bool iso = kin == KIN_SMALL && (tan.kind == TAN_ISO_PHASE || tan.kind == TAN_ISO_FIELD);
-  if constexpr (sizeof(T) == 8) {
-    if (mode == LP_FUSED && macro_add == nullptr && staged_line_supported(g.n3, (int)sizeof(cpx<T>), iso)) {
-      if (nblocks_out) *nblocks_out = staged_line_blocks(g);
-      launch_line_staged(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
-      return;
-    }
+  if (mode == LP_FUSED && macro_add == nullptr &&
+      staged_line_supported(g.n3, (int)sizeof(cpx<T>), iso, kin == KIN_FINITE)) {
+    if (nblocks_out) *nblocks_out = staged_line_blocks(g);
+    launch_line_staged<T>(kin, in, out, g, tw, rtw, tan, macro_dev, partials, st, stop);
+    return;
   }
   if (mode == LP_FUSED && macro_add == nullptr && fast_line_supported(g.n3)) {
     if (nblocks_out) *nblocks_out = fast_line_blocks(g, (int)sizeof(cpx<T>));
@@ -193,7 +192,7 @@ template void launch_line<float>(int, int, const void*, void*, const Geom&, cons
 
 int fused_line_blocks(const Geom& g, int ncomp, int elem_bytes, int tan_kind) {
   const bool iso = (ncomp == 6) && (tan_kind == TAN_ISO_PHASE || tan_kind == TAN_ISO_FIELD);
-  if (staged_line_supported(g.n3, elem_bytes, iso)) return staged_line_blocks(g);
+  if (staged_line_supported(g.n3, elem_bytes, iso, ncomp == 9)) return staged_line_blocks(g);
   if (fast_line_supported(g.n3)) return fast_line_blocks(g, elem_bytes);
   if (iso && odd_line_supported(g.n3)) return odd_line_energy_blocks(g);
   if (mixed_line_supported(g.n3, elem_bytes, iso)) return mixed_line_energy_blocks(g, iso);

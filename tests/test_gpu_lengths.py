@@ -19,10 +19,10 @@ from oracle import spectral as sp, solver as so, materials as mt
 
 pytestmark = pytest.mark.gpu
 
-# z lengths n3 whose half n3/2 is a two-step length (32 and 64: the staged FP64
+# z lengths n3 whose half n3/2 is a two-step length (32, 64 and 128: the staged
 # z pass of anisotropic and finite-strain tangents), and the x / y lengths of
 # the batch and adjoint workloads
-Z_LENGTHS = [24, 32, 36, 40, 48, 50, 54, 64, 72, 80, 90, 96, 108, 120, 144, 160, 180, 192]
+Z_LENGTHS = [24, 32, 36, 40, 48, 50, 54, 64, 72, 80, 90, 96, 108, 120, 128, 144, 160, 180, 192]
 XY_LENGTHS = [54, 72, 80, 90, 96]
 SHAPES = ([(4, 6, n3) for n3 in Z_LENGTHS] + [(n, 6, 8) for n in XY_LENGTHS] + [(6, n, 8) for n in XY_LENGTHS]
           + [(72, 4, 54), (8, 6, 80), (96, 6, 8), (6, 90, 8)])
@@ -82,8 +82,8 @@ def test_real_apply_lengths(gpu, n, kin, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
-@pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 54), (4, 6, 90), (4, 6, 32), (4, 6, 64), (96, 6, 8), (6, 90, 8),
-                               (72, 4, 54)])
+@pytest.mark.parametrize("n", [(4, 6, 96), (4, 6, 54), (4, 6, 90), (4, 6, 32), (4, 6, 64), (4, 6, 128), (96, 6, 8),
+                               (6, 90, 8), (72, 4, 54)])
 def test_real_apply_aniso_lengths(gpu, n, prec):
     """Anisotropic grain stiffness (21 coefficients: the z pass that couples
     every component; in FP32 the components of a line group are staged in
