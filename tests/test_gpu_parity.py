@@ -298,11 +298,13 @@ def test_solve_parity_power_of_two(gpu, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mixed"])
-@pytest.mark.parametrize("n", [(32, 16, 24), (16, 32, 32), (64, 64, 8)])
+@pytest.mark.parametrize("n", [(32, 16, 24), (16, 32, 32), (64, 64, 8), (32, 24, 16), (16, 14, 12)])
 def test_fused_cg_matches_separate_kernels(gpu, n, prec):
     """The fused CG iteration (residual update in the divergence pass,
-    alpha in the y pass, Hermitian planes in-block) against the separate
-    vector kernels and against the oracle, mixed control (uniaxial stress)."""
+    alpha in the first block of the y pass, Hermitian planes in-block)
+    against the separate vector kernels (alpha in the first block of the x
+    pass) and against the oracle, mixed control (uniaxial stress).  n2 = 24
+    and 14 take the two-step and the LDS-engine y passes."""
     import torch
     from paper_1905_12725_amd.api import Cell
     print(f"case fused vs separate n={n} {prec}", flush=True)
