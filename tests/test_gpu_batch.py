@@ -287,19 +287,19 @@ def test_batch_neohooke_smooth_sizes_fp32_vs_fp64_single(gpu):
         c.close()
 
 
-@pytest.mark.parametrize("n", [(128, 128, 128), (96, 96, 96)])
-def test_batch_of_large_cells_solves_cell_by_cell(gpu, n):
+@pytest.mark.parametrize("n,prec", [((128, 128, 128), "fp64"), ((96, 96, 96), "fp64"), ((96, 96, 96), "fp32_mixed")])
+def test_batch_of_large_cells_solves_cell_by_cell(gpu, n, prec):
     """Two small-strain cells of at least 96^3 voxels (128^3: the fused
     single-cell iteration; 96^3: the two-step single-cell passes): the batch
     solves them with the single-cell passes (on two streams at once), so
     each result equals the cell's own solve bit for bit."""
     import torch
     from paper_1905_12725_amd.api import Batch, Cell
-    print(f"case batch of two {n} cells", flush=True)
+    print(f"case batch of two {n} cells {prec}", flush=True)
     phase, _, _ = ms.random_spheres(n, 2, 6.0 * n[0] / 128, 10.0 * n[0] / 128, 0.3)
     params = [1.0, 0.3, 100.0, 0.3]
     loads = [np.diag([1e-3, 0.0, 0.0]), np.array([[0.0, 1e-3, 0.0], [1e-3, 0.0, 0.0], [0.0, 0.0, 0.0]])]
-    cells = [Cell(n, "iso_phase", torch.from_numpy(phase), params) for _ in loads]
+    cells = [Cell(n, "iso_phase", torch.from_numpy(phase), params, precision=prec) for _ in loads]
     with Batch(cells) as b:
         infos = b.solve(loads, None, tol=1e-8)
         sols = [c.solution()[0].cpu().numpy() for c in cells]
